@@ -1,0 +1,174 @@
+/*
+ * rpi.h -- C ABI of librpi: the residual path estimator of
+ * "Residual path integrals for re-rendering" (Xu, Li, Georgiev, Hedstrom,
+ * Ramamoorthi, EGSR 2024) on one AMD Instinct MI355X (gfx950).
+ *
+ * All entry points return an rpi_status (0 = success, negative = error) and
+ * never throw across the ABI.  A human-readable message for the last failing
+ * call on the calling thread is available from rpi_last_error().
+ *
+ * Device pointers are plain HIP device addresses (for example the data_ptr
+ * of a torch CUDA tensor on ROCm); streams are hipStream_t passed as void*.
+ * Rendering calls are asynchronous on the given stream unless they are asked
+ * to return statistics, in which case they synchronise that stream.
+ *
+ * Shared input conventions (see rpi_scene_desc):
+ *   - geometry is a triangle soup; triangles of the dynamic / edited object
+ *     carry tri_object = 1 and are given at the OLD pose;
+ *   - materials are rows of 8 floats: type (0 Lambertian, 1 GGX conductor,
+ *     2 one-sided emitter), albedo rgb (GGX: F0), roughness (GGX alpha),
+ *     emission rgb;
+ *   - images are H x W x 3 float32, row-major, row 0 at the top.
+ */
+#ifndef RPI_H
+#define RPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rpi_status;
+#define RPI_OK 0
+#define RPI_ERR_INVALID_ARG (-1)   /* malformed input; nothing was launched */
+#define RPI_ERR_UNSUPPORTED (-2)   /* well-formed but outside what the library handles */
+#define RPI_ERR_OUT_OF_MEMORY (-3) /* a device allocation failed */
+#define RPI_ERR_DEVICE (-4)        /* a HIP runtime call failed (sticky device errors included) */
+
+#define RPI_EDIT_RIGID 0
+#define RPI_EDIT_MATERIAL 1
+
+/* rpi_render_params.flags */
+#define RPI_FLAG_TWO_WAY 1u    /* sample both frames, two-way mapping (motion edits) */
+#define RPI_FLAG_ACCUMULATE 2u /* add into the output instead of overwriting it */
+#define RPI_FLAG_COUNT_WORK 4u /* count BVH node visits and triangle tests (slower kernels) */
+#define RPI_FLAG_RECORDS 8u    /* keep per-path splat records for inspection (rpi_get_records) */
+#define RPI_FLAG_TIME_KERNELS 16u /* time every launch with HIP events (per-kernel durations in rpi_stats) */
+
+typedef struct rpi_scene rpi_scene;
+typedef struct rpi_edit rpi_edit;
+
+/* Scene description.  Every array is host memory, copied by rpi_build_scene;
+ * the caller may free it on return. */
+typedef struct {
+  const float* positions;      /* [3 * num_vertices] */
+  int32_t num_vertices;
+  const int32_t* indices;      /* [3 * num_triangles], counter-clockwise around the normal */
+  int32_t num_triangles;
+  const int32_t* tri_material; /* [num_triangles], < num_materials */
+  const int32_t* tri_object;   /* [num_triangles], 0 static, 1 dynamic/edited object */
+  const float* materials;      /* [8 * num_materials] */
+  int32_t num_materials;
+  const float* env;            /* [3] constant environment radiance (0 = none) */
+  const float* camera;         /* [12] eye xyz, target xyz, up xyz, vfov_deg, width, height */
+} rpi_scene_desc;
+
+/* An edit between the old frame (the scene as given) and the new frame.
+ * RIGID: the object moves by old_to_new, a 3x4 row-major rigid transform
+ *   (R orthonormal, det +1: the vertex map of Sec. 5 has unit Jacobian).
+ * MATERIAL: the object's material becomes new_material in the new frame. */
+typedef struct {
+  int32_t kind;
+  float old_to_new[12];
+  float new_material[8];
+} rpi_edit_desc;
+
+typedef struct {
+  int32_t spp;            /* samples per pixel per technique per direction */
+  int32_t max_depth;      /* maximum number of path segments (>= 2) */
+  uint64_t seed;          /* Philox key */
+  uint32_t strategy_mask; /* bit t-1 enables technique t: 1..6 of Sec. 4, 7 = path tracing */
+  uint32_t flags;         /* RPI_FLAG_* */
+  float alpha_min;        /* reconnection roughness threshold (Sec. 5), default 0.2 */
+  float d_min;            /* reconnection distance threshold; < 0: 1% of the scene diagonal */
+  float jac_max;          /* Jacobian rejection threshold, default 10 */
+  float c_weight;         /* two-way weight of accepted pairs, default 0.5 */
+  int64_t sample_begin;   /* sample-index range of every (technique, direction) stream */
+  int64_t sample_end;     /* < 0: spp * width * height */
+  int32_t queue_cap;      /* samples per chunk (0: automatic) */
+  uint32_t job;           /* third Philox counter word (distinct jobs get independent streams) */
+} rpi_render_params;
+
+typedef struct {
+  int64_t samples;        /* technique samples drawn */
+  int64_t paths;          /* connected paths evaluated and splatted (residual paths) */
+  int64_t accepted;       /* paths whose mapped path was accepted */
+  int64_t rejected[7];    /* by rule R1..R6 (index 0 unused) */
+  int64_t by_tech[9];     /* paths by technique (index 1..8) */
+  int64_t rays[6];        /* with RPI_FLAG_COUNT_WORK: closest, shadow, camera, ghost all-hit,
+                             mapping re-trace, mapping visibility */
+  int64_t nodes_visited;  /* with RPI_FLAG_COUNT_WORK */
+  int64_t tris_tested;    /* with RPI_FLAG_COUNT_WORK */
+  double milliseconds;    /* device time of the call (when stats are requested) */
+  /* Per kernel: index t = 1..7 walk kernel of technique t, 8 connect, 9 splat
+   * (all splat kernels of a chunk), 10 frame.  ms/launches with
+   * RPI_FLAG_TIME_KERNELS; node/triangle fetches and record bytes written
+   * with RPI_FLAG_COUNT_WORK. */
+  double kernel_ms[16];
+  int64_t kernel_launches[16];
+  int64_t kernel_nodes[16];
+  int64_t kernel_tris[16];
+  int64_t kernel_bytes_written[16];
+} rpi_stats;
+
+/* Copy, validate and upload a scene; builds binned-SAH BVHs for the static
+ * geometry and for the object in object space, and the area CDFs.
+ * Errors: INVALID_ARG (NaN/inf vertex, index out of range, bad material id,
+ * zero-area object or emitter, bad camera), UNSUPPORTED (emissive object,
+ * no dynamic triangles), OUT_OF_MEMORY, DEVICE. */
+rpi_status rpi_build_scene(const rpi_scene_desc* desc, rpi_scene** out);
+rpi_status rpi_destroy_scene(rpi_scene* scene);
+
+/* Record an edit of the scene's object.  Errors: INVALID_ARG (unknown kind,
+ * non-orthonormal or mirrored transform, bad material), UNSUPPORTED
+ * (emissive new material). */
+rpi_status rpi_apply_edit(rpi_scene* scene, const rpi_edit_desc* desc, rpi_edit** out);
+rpi_status rpi_destroy_edit(rpi_edit* edit);
+
+/* The residual I2 - I1 (Sec. 3.2, eq. shiftmapped) into d_out
+ * (H*W*3 float32, caller-owned device memory), by the dynamic-path
+ * techniques of Sec. 4, MIS (Sec. 4.3), path mapping and rejection (Sec. 5).
+ * Material edits use techniques 1-3 (and 7 if enabled), one-way.
+ * stats may be NULL; when given, the call synchronises hip_stream. */
+rpi_status rpi_render_residual(const rpi_scene* scene, const rpi_edit* edit, const rpi_render_params* params,
+                               float* d_out, rpi_stats* stats, void* hip_stream);
+
+/* Plain path tracing (next-event estimation, emission seen directly) of one
+ * frame (Sec. 3.1): which = 1 old frame, 2 new frame (edit may be NULL: the
+ * scene as given). */
+rpi_status rpi_render_frame(const rpi_scene* scene, const rpi_edit* edit, int32_t which,
+                            const rpi_render_params* params, float* d_out, void* hip_stream);
+
+/* One job of a batch: a rigid edit given by the object's poses in the two
+ * frames (3x4 row-major, relative to the scene as given), its own image. */
+typedef struct {
+  float pose_old[12];
+  float pose_new[12];
+  int32_t width, height;
+  float* d_out;            /* height * width * 3 float32 device memory */
+} rpi_job;
+
+/* Many residual jobs (e.g. consecutive frames of an animation) with uneven
+ * image sizes in one persistent launch replayed from a captured hipGraph.
+ * Job j uses Philox counter word params->job + j.  Errors as above. */
+rpi_status rpi_render_residual_batch(const rpi_scene* scene, const rpi_job* jobs, int32_t num_jobs,
+                                     const rpi_render_params* params, rpi_stats* stats, void* hip_stream);
+
+/* Per-path records of the last rpi_render_residual call on this scene made
+ * with RPI_FLAG_RECORDS (host copy): each record is 8 int32/float words
+ * {dir, tech, sample, pair(i<<8|j), pixel, r, g, b}.  Returns the count in
+ * *count; copies at most cap records. */
+rpi_status rpi_get_records(const rpi_scene* scene, void* host_out, int64_t cap, int64_t* count);
+
+/* Thread-local message of the last error. */
+const char* rpi_last_error(void);
+
+/* Library version string. */
+const char* rpi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPI_H */

@@ -944,6 +944,11 @@ static int map_path(const Scene& S, const Frame& F, const Frame& Fp, const Path&
   }
   // y_1
   bool retrace = X.v[1].dyn || (F.ghosts && crossings(S, F, X, 0).n > 0);
+  {
+    int mv = retrace ? 1 : 0;
+    for (int i = 2; i <= k - 2; ++i) mv += X.v[i].dyn ? 1 : 0;
+    if (mv > 1) return R2;
+  }
   if (retrace) {
     V3 w = normalize(X.v[1].p - S.cam.eye);
     Hit h = closest(S, Fp.pose, S.cam.eye, w);
@@ -1071,6 +1076,8 @@ static bool assemble(const Gen& g, const PV* eye, int i, const PV* mid, const PV
   P.tech = g.tech;
   P.p_gen = p_gen;
   P.start = start;
+  P.i = i;
+  P.j = j;
   return true;
 }
 
@@ -1377,6 +1384,7 @@ static void camera_path(const Gen& g, uint32_t sample) {
   Q.v[0] = PV{C.eye, C.fwd, -1, false};
   Q.tech = g.tech;
   Q.start = 0;
+  Q.i = Q.j = -1;
   if (!h.ok) {
     if (g.S.has_env) {
       Q.k = 2;
@@ -1522,6 +1530,7 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
         r.pixel = pix;
         r.reason = reason;
         r.n_starts = n_starts_for(S, F, X, tech);
+        r.pad = ((X.i + 1) << 4) | (X.j + 1);
         r.val[0] = val.x;
         r.val[1] = val.y;
         r.val[2] = val.z;

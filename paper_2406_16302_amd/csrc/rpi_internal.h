@@ -1,0 +1,189 @@
+// Internal types shared by the host runtime (rpi_host.cpp) and the kernels
+// (rpi_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RPI_HD __host__ __device__ __forceinline__
+
+namespace rpi {
+
+// ------------------------------------------------------------------ vectors
+struct vec3 {
+  float x, y, z;
+};
+RPI_HD vec3 v3(float x, float y, float z) { return vec3{x, y, z}; }
+RPI_HD vec3 operator+(vec3 a, vec3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+RPI_HD vec3 operator-(vec3 a, vec3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+RPI_HD vec3 operator-(vec3 a) { return v3(-a.x, -a.y, -a.z); }
+RPI_HD vec3 operator*(vec3 a, float s) { return v3(a.x * s, a.y * s, a.z * s); }
+RPI_HD vec3 vmul(vec3 a, vec3 b) { return v3(a.x * b.x, a.y * b.y, a.z * b.z); }
+RPI_HD float dot(vec3 a, vec3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+RPI_HD vec3 cross(vec3 a, vec3 b) {
+  return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+RPI_HD float len2(vec3 a) { return dot(a, a); }
+RPI_HD vec3 unit(vec3 a) {
+  float l = sqrtf(dot(a, a));
+  return v3(a.x / l, a.y / l, a.z / l);
+}
+
+// Rigid pose: world = R p + t (R row-major).
+struct Pose {
+  float r[9];
+  float t[3];
+};
+RPI_HD vec3 pose_apply(const Pose& P, vec3 p) {
+  return v3(P.r[0] * p.x + P.r[1] * p.y + P.r[2] * p.z + P.t[0],
+            P.r[3] * p.x + P.r[4] * p.y + P.r[5] * p.z + P.t[1],
+            P.r[6] * p.x + P.r[7] * p.y + P.r[8] * p.z + P.t[2]);
+}
+RPI_HD vec3 pose_rot(const Pose& P, vec3 v) {
+  return v3(P.r[0] * v.x + P.r[1] * v.y + P.r[2] * v.z, P.r[3] * v.x + P.r[4] * v.y + P.r[5] * v.z,
+            P.r[6] * v.x + P.r[7] * v.y + P.r[8] * v.z);
+}
+RPI_HD vec3 pose_inv_rot(const Pose& P, vec3 v) {
+  return v3(P.r[0] * v.x + P.r[3] * v.y + P.r[6] * v.z, P.r[1] * v.x + P.r[4] * v.y + P.r[7] * v.z,
+            P.r[2] * v.x + P.r[5] * v.y + P.r[8] * v.z);
+}
+RPI_HD vec3 pose_inv_apply(const Pose& P, vec3 p) {
+  return pose_inv_rot(P, p - v3(P.t[0], P.t[1], P.t[2]));
+}
+
+// ------------------------------------------------------------------ scene on the device
+enum { MAT_DIFFUSE = 0, MAT_GGX = 1, MAT_EMITTER = 2 };
+
+// BVH2 node (64 B): both children's boxes and links.
+//   f4[0] = c0.lo.xyz, c0.hi.x   f4[1] = c0.hi.yz, c1.lo.xy
+//   f4[2] = c1.lo.z, c1.hi.xyz   f4[3] = child0, child1 (int bits), 0, 0
+// A child link >= 0 is an inner node; a negative link is a leaf
+// 0x80000000 | first << 4 | count (count <= 15) into the triangle array.
+// Triangle (48 B): f4[0] = v0.xyz, id; f4[1] = e1.xyz, material; f4[2] = e2.xyz, 0.
+struct DevBvh {
+  const float4* nodes;
+  const float4* tris;
+  int32_t ntris;
+};
+
+constexpr int kStackDepth = 48;  // the builder keeps every leaf at depth < kStackDepth
+
+struct DevCamera {
+  vec3 eye, fwd, right, up;
+  float tan_half, aspect;
+  int32_t W, H;
+  float a_film;  // 4 aspect tan^2: film area at distance 1
+};
+
+struct DevScene {
+  DevBvh stat, obj;
+  const float4* obj_tris;  // object triangles in input order (area sampling), 3 float4 each
+  const float* obj_cdf;
+  int32_t nobj;
+  const float4* light_tris;  // emitter triangles in input order
+  const float* light_cdf;
+  int32_t nlights;
+  const float* mats;  // 8 floats per material
+  int32_t nmats;
+  float inv_obj_area;   // p_D = p_G
+  float inv_light_area;
+  float p_env;          // probability of selecting the environment
+  vec3 env;
+  DevCamera cam;
+  float eps;            // ray offset: 1e-4 of the scene diagonal
+};
+
+struct Material {
+  int32_t type;
+  vec3 albedo;
+  float rough;
+  vec3 emit;
+};
+
+struct DevFrame {
+  Pose pose;       // object pose in this frame
+  Pose ghost;      // object pose in the other frame (the ghost)
+  Material objmat; // object material in this frame
+  vec3 olo, ohi;   // padded world bounds of the object at pose
+  vec3 glo, ghi;   // padded world bounds of the ghost
+  int32_t ghosts;  // 1 for motion edits
+  int32_t same_pose;  // the two frames place the object identically
+};
+
+// ------------------------------------------------------------------ workspace
+// Sub-path vertex records, SoA: record r of slot v of sample s is at
+// base[(v * FIELDS + r) * Q + s] (float4), so a wave's lanes touch
+// consecutive 16-byte words.
+constexpr int kEyeFields = 4;    // pos+md, nrm+pred.n, pred sums+flags, camera-edge crossings
+constexpr int kLightFields = 6;  // pos+md, nrm+pred.n, pred sums+flags, light pos+md, light nrm+nee.n, nee sums+ok
+constexpr int kStartFields = 5;  // mid pos+md, mid nrm+cam.n, cam sums, x_L pos+md, x_L nrm
+
+struct Workspace {
+  float4* eye;
+  float4* light;
+  float4* start;
+  uint32_t* counts;    // per sample: nE | nL << 8
+  uint32_t* pairs;     // queue of connected paths: sample << 8 | (i+1) << 4 | (j+1)
+  uint32_t* npairs;    // [1] queue length
+  float4* records;     // per queued path: pixel (int bits), rgb
+  uint32_t* rec_keys;  // optional: dir | tech << 1 | pair << 8  (debug records)
+  uint32_t* rec_sample;
+  int32_t Q;           // samples per chunk
+  int64_t pair_cap;
+  int32_t nslot;       // vertex slots per side
+};
+
+struct DevStats {
+  unsigned long long paths, accepted, rejected[7], by_tech[9], rays[6], nodes, tris, samples;
+  unsigned long long knodes[16], ktris[16], kbytes[16];
+};
+
+struct WalkArgs {
+  DevScene S;
+  DevFrame F;   // frame f the paths live in
+  DevFrame Fp;  // the other frame f'
+  Workspace W;
+  DevStats* stats;
+  uint32_t k0, k1, job;
+  int64_t sample0;  // first sample index of the chunk
+  int32_t nsamples; // samples in the chunk
+  int32_t tech, dir, depth;
+  int32_t material_mode;
+  uint32_t mask;
+  float sigma, cweight, inv_n;
+  float alpha_min, d_min, jac_max;
+  int32_t count_work;
+  int32_t keep_records;
+};
+
+struct SplatArgs {
+  const float4* records;
+  const uint32_t* nrec;
+  int64_t cap;
+  uint32_t* tcount;   // [ntiles]
+  uint32_t* toff;     // [ntiles + 1]
+  uint32_t* tcursor;  // [ntiles]
+  float4* binned;     // [cap]
+  float* image;
+  int W, H, tilesx, ntiles;
+};
+
+struct FrameArgs {
+  DevScene S;
+  DevFrame F;
+  float* image;
+  uint32_t k0, k1, job;
+  int dir, depth, spp, accumulate;
+  int64_t s0, s1;
+  DevStats* stats;
+};
+
+// launchers (rpi_kernels.hip)
+void launch_walk(const WalkArgs& A, hipStream_t st);
+void launch_connect(const WalkArgs& A, int blocks, hipStream_t st);
+void launch_splat(const SplatArgs& a, int blocks, hipStream_t st);
+void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
+void launch_zero_f32(float* p, int64_t n, hipStream_t st);
+void launch_frame(const FrameArgs& A, hipStream_t st);
+
+}  // namespace rpi

@@ -1,0 +1,1178 @@
+// HIP kernels of the residual path estimator (gfx950, wave64).
+//
+// Pipeline per (direction, technique, chunk of samples), all on one stream:
+//   walk_kernel<TECH>  one lane per sample: start sampling (Sec. 4.1/4.2),
+//                      random walks with BVH traversal, next-event and camera
+//                      connections, ghost-crossing records (Sec. 4.3, Sec. 6.1);
+//                      sub-path vertices go to SoA records in HBM and every
+//                      connected path is appended to a queue with one atomic
+//                      per wave (ballot/prefix compaction).
+//   connect_kernel     one lane per connected path: MIS over N_D + N_G + 1
+//                      strategies from forward/backward pdf prefix tables
+//                      (Sec. 4.3), path mapping and rejection (Sec. 5),
+//                      evaluation in both frames (eq. shiftmapped), one signed
+//                      splat record per path.
+//   splat kernels      counting sort of the records by 16x16 tile, then one
+//                      workgroup per tile accumulates in LDS and writes the
+//                      tile once (no float atomics on the image in HBM).
+// frame_kernel renders a frame by plain path tracing (Sec. 3.1).
+#include "rpi_device.h"
+
+namespace rpi {
+
+constexpr int kMaxK = 8;  // vertices per path: max_depth <= 7
+constexpr int kTile = 16;
+
+// ------------------------------------------------------------------ SoA records
+DEV float4 f4(vec3 a, float w) { return make_float4(a.x, a.y, a.z, w); }
+DEV float4 f4u(vec3 a, uint32_t w) { return make_float4(a.x, a.y, a.z, __uint_as_float(w)); }
+DEV vec3 xyz(float4 a) { return v3(a.x, a.y, a.z); }
+
+DEV float4& EYE(const Workspace& W, int slot, int field, int s) {
+  return W.eye[((size_t)slot * kEyeFields + field) * W.Q + s];
+}
+DEV float4& LIT(const Workspace& W, int slot, int field, int s) {
+  return W.light[((size_t)slot * kLightFields + field) * W.Q + s];
+}
+DEV float4& STA(const Workspace& W, int field, int s) { return W.start[(size_t)field * W.Q + s]; }
+
+// reflection-only support at vertex p: both neighbours on one side
+DEV bool same_side(vec3 n, vec3 p, vec3 a, vec3 b) { return dot(n, a - p) * dot(n, b - p) > 0.0f; }
+DEV bool same_side_dir(vec3 n, vec3 p, vec3 a, vec3 dir) { return dot(n, a - p) * dot(n, dir) > 0.0f; }
+
+DEV bool is_emitter(const DevScene& S, uint32_t md) {
+  return !(md & kDynBit) && S.mats[8 * (md & ~kDynBit)] == (float)MAT_EMITTER;
+}
+
+struct Lane {
+  const WalkArgs& A;
+  Rng g;
+  int s;
+  int* stk;
+  WorkCount wc;
+  int nE, nL;
+  uint32_t camok, neeok, dynpre;
+  int k2;  // path tracing saw an emitter / the environment at x_1
+};
+
+// Extend a walk from (p, n, md) whose other neighbour lies in direction wi.
+template <bool CW>
+DEV bool extend(Lane& L, vec3 p, vec3 n, uint32_t md, vec3 wi, const float u[4], vec3& q, vec3& qn,
+                uint32_t& qmd) {
+  const Material m = vmat(L.A.S, L.A.F, md);
+  vec3 wo;
+  if (!bsdf_sample(m, n, wi, u[0], u[1], wo)) return false;
+  const vec3 o = spawn_dir(L.A.S, p, n, wo);
+  const Hit h = closest<CW>(L.A.S, L.A.F.pose, L.A.F.olo, L.A.F.ohi, o, wo, L.stk, L.wc);
+  if (!h.ok) return false;
+  hit_vertex(L.A.S, L.A.F.pose, h, o, wo, q, qn, qmd);
+  return !is_emitter(L.A.S, qmd);
+}
+
+DEV uint32_t light_word(const LightEnd& E) { return E.mat | (E.env ? 0x40000000u : 0u); }
+
+// Light-side walk.  Slot 0 vertex (p0, n0, md0) with its predecessor edge
+// crossing pred0; prev0 = the neighbour towards the camera.  Next-event
+// estimation at each vertex.  dyn0: path-tracing dynamic state before slot 0.
+template <bool CW>
+DEV void light_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End prev0, int jmax, bool dyn0) {
+  const WalkArgs& A = L.A;
+  const DevScene& S = A.S;
+  vec3 p = p0, n = n0;
+  uint32_t md = md0;
+  Cross pred = pred0;
+  End prev = prev0;
+  bool dyn = dyn0;
+  for (int j = 0; j <= jmax; ++j) {
+    dyn = dyn || (md & kDynBit) || pred.n > 0.0f;
+    // next-event estimation
+    float u[4];
+    draw(L.g, 0, j + 1, 1, u);
+    LightEnd E;
+    bool ok = sample_light(S, u, E);
+    Cross nee = no_cross();
+    if (ok) {
+      const End eL = end_light(E);
+      ok = E.env ? same_side_dir(n, p, prev.p, E.n)
+                 : (dot(E.n, p - E.p) > 0.0f && same_side(n, p, prev.p, E.p));
+      if (ok) {
+        const End cur = end_surf(p, n);
+        ok = edge_visible<CW>(S, A.F, cur, eL, L.stk, L.wc, RAY_SHADOW);
+        if (ok) nee = edge_cross<CW>(S, A.F, cur, eL, L.stk, L.wc);
+      }
+    }
+    LIT(A.W, j, 0, L.s) = f4u(p, md);
+    LIT(A.W, j, 1, L.s) = f4(n, pred.n);
+    LIT(A.W, j, 2, L.s) = make_float4(pred.s0, pred.sa, pred.sb, 0.0f);
+    LIT(A.W, j, 3, L.s) = f4u(E.p, light_word(E));
+    LIT(A.W, j, 4, L.s) = f4(E.n, nee.n);
+    LIT(A.W, j, 5, L.s) = make_float4(nee.s0, nee.sa, nee.sb, 0.0f);
+    if (CW) L.wc.bytes += kLightFields * 16;
+    L.nL = j + 1;
+    if (ok) L.neeok |= 1u << j;
+    if (dyn || nee.n > 0.0f) L.dynpre |= 1u << j;
+    if (j == jmax) break;
+    draw(L.g, 0, j + 1, 0, u);
+    vec3 q, qn;
+    uint32_t qmd;
+    if (!extend<CW>(L, p, n, md, unit(prev.p - p), u, q, qn, qmd)) break;
+    pred = edge_cross<CW>(S, A.F, end_surf(p, n), end_surf(q, qn), L.stk, L.wc);
+    prev = end_surf(p, n);
+    p = q;
+    n = qn;
+    md = qmd;
+  }
+}
+
+// Eye-side walk.  Slot 0 vertex with predecessor crossing pred0 (the edge to
+// next0, its neighbour towards the light); camera connection at each vertex.
+template <bool CW>
+DEV void eye_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End next0, int imax) {
+  const WalkArgs& A = L.A;
+  const DevScene& S = A.S;
+  vec3 p = p0, n = n0;
+  uint32_t md = md0;
+  Cross pred = pred0;
+  End next = next0;
+  for (int i = 0; i <= imax; ++i) {
+    const vec3 nxt = next.kind == END_ENV ? p + next.n : next.p;
+    bool ok = raster(S.cam, p) >= 0 && same_side(n, p, S.cam.eye, nxt);
+    Cross cam = no_cross();
+    if (ok) {
+      const End e0 = end_eye(S), cur = end_surf(p, n);
+      ok = edge_visible<CW>(S, A.F, e0, cur, L.stk, L.wc, RAY_CAMERA);
+      if (ok) cam = edge_cross<CW>(S, A.F, e0, cur, L.stk, L.wc);
+    }
+    EYE(A.W, i, 0, L.s) = f4u(p, md);
+    EYE(A.W, i, 1, L.s) = f4(n, pred.n);
+    EYE(A.W, i, 2, L.s) = make_float4(pred.s0, pred.sa, pred.sb, 0.0f);
+    EYE(A.W, i, 3, L.s) = make_float4(cam.n, cam.s0, cam.sa, cam.sb);
+    if (CW) L.wc.bytes += kEyeFields * 16;
+    L.nE = i + 1;
+    if (ok) L.camok |= 1u << i;
+    if (i == imax) break;
+    float u[4];
+    draw(L.g, 1, i + 1, 0, u);
+    vec3 q, qn;
+    uint32_t qmd;
+    if (!extend<CW>(L, p, n, md, unit(nxt - p), u, q, qn, qmd)) break;
+    pred = edge_cross<CW>(S, A.F, end_surf(q, qn), end_surf(p, n), L.stk, L.wc);
+    next = end_surf(p, n);
+    p = q;
+    n = qn;
+    md = qmd;
+  }
+}
+
+DEV void store_xl(const Lane& L, const LightEnd& E) {
+  STA(L.A.W, 3, L.s) = f4u(E.p, light_word(E));
+  STA(L.A.W, 4, L.s) = f4(E.n, 0.0f);
+}
+DEV void store_mid(const Lane& L, vec3 p, vec3 n, uint32_t md, Cross cam, uint32_t flags) {
+  STA(L.A.W, 0, L.s) = f4u(p, md);
+  STA(L.A.W, 1, L.s) = f4(n, cam.n);
+  STA(L.A.W, 2, L.s) = make_float4(cam.s0, cam.sa, cam.sb, __uint_as_float(flags));
+}
+
+// A ghost-started sample generates its path only if its ghost triangle is
+// crossed strictly inside the generated edge's canonical segment.
+DEV bool ghost_on_edge(const Lane& L, const End& A, const End& B, int tri) {
+  const DevScene& S = L.A.S;
+  const Seg s = canon(S, A, B);
+  vec3 v0, e1, e2;
+  int id, mat;
+  load_tri(S.obj_tris, tri, v0, e1, e2, id, mat);
+  const float t = tri_t(pose_inv_apply(L.A.F.ghost, s.o), pose_inv_rot(L.A.F.ghost, s.d), v0, e1, e2);
+  return t > 0.0f && t < s.tmax;
+}
+
+// (1) dynamic from emitter
+template <bool CW>
+DEV void tech1(Lane& L) {
+  const WalkArgs& A = L.A;
+  const DevScene& S = A.S;
+  float u[4];
+  draw(L.g, 0, 0, 0, u);
+  vec3 p, n;
+  uint32_t md;
+  int tri;
+  object_point(S, A.F.pose, u, p, n, md, tri);
+  draw(L.g, 0, 0, 1, u);
+  LightEnd E;
+  if (!sample_light(S, u, E)) return;
+  const End eL = end_light(E);
+  if (!E.env && !(dot(E.n, p - E.p) > 0.0f)) return;
+  if (!edge_visible<CW>(S, A.F, end_surf(p, n), eL, L.stk, L.wc, RAY_SHADOW)) return;
+  const Cross c = edge_cross<CW>(S, A.F, end_surf(p, n), eL, L.stk, L.wc);
+  store_xl(L, E);
+  eye_walk<CW>(L, p, n, md, c, eL, A.depth - 2);
+}
+
+// (2) dynamic from sensor
+template <bool CW>
+DEV void tech2(Lane& L) {
+  const WalkArgs& A = L.A;
+  const DevScene& S = A.S;
+  if (A.depth < 3) return;
+  float u[4];
+  draw(L.g, 0, 0, 0, u);
+  vec3 p, n;
+  uint32_t md;
+  int tri;
+  object_point(S, A.F.pose, u, p, n, md, tri);
+  if (raster(S.cam, p) < 0) return;
+  const End e0 = end_eye(S), xd = end_surf(p, n);
+  if (!edge_visible<CW>(S, A.F, e0, xd, L.stk, L.wc, RAY_CAMERA)) return;
+  const Cross cam = edge_cross<CW>(S, A.F, e0, xd, L.stk, L.wc);
+  draw(L.g, 0, 0, 2, u);
+  vec3 q, qn;
+  uint32_t qmd;
+  if (!extend<CW>(L, p, n, md, unit(S.cam.eye - p), u, q, qn, qmd)) return;
+  store_mid(L, p, n, md, cam, 1u);
+  const Cross pred = edge_cross<CW>(S, A.F, xd, end_surf(q, qn), L.stk, L.wc);
+  light_walk<CW>(L, q, qn, qmd, pred, xd, A.depth - 3, false);
+}
+
+// (3) dynamic two ends: cosine lobe about the outward normal towards the
+// light side, then a BSDF direction towards the sensor.
+template <bool CW>
+DEV void tech3(Lane& L) {
+  const WalkArgs& A = L.A;
+  const DevScene& S = A.S;
+  if (A.depth < 4) return;
+  float u[4];
+  draw(L.g, 0, 0, 0, u);
+  vec3 p, n;
+  uint32_t md;
+  int tri;
+  object_point(S, A.F.pose, u, p, n, md, tri);
+  draw(L.g, 0, 0, 2, u);
+  const vec3 wl = cosine_dir(n, u[0], u[1]);
+  if (!(dot(wl, n) > 0.0f)) return;
+  const vec3 ol = spawn_dir(S, p, n, wl);
+  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, ol, wl, L.stk, L.wc);
+  if (!hl.ok) return;
+  vec3 l0, l0n;
+  uint32_t l0md;
+  hit_vertex(S, A.F.pose, hl, ol, wl, l0, l0n, l0md);
+  if (is_emitter(S, l0md)) return;
+  draw(L.g, 0, 0, 3, u);
+  const Material m = vmat(S, A.F, md);
+  vec3 we;
+  if (!bsdf_sample(m, n, wl, u[0], u[1], we)) return;
+  const vec3 oe = spawn_dir(S, p, n, we);
+  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, oe, we, L.stk, L.wc);
+  if (!he.ok) return;
+  vec3 e0, e0n;
+  uint32_t e0md;
+  hit_vertex(S, A.F.pose, he, oe, we, e0, e0n, e0md);
+  if (is_emitter(S, e0md)) return;
+  const End xd = end_surf(p, n);
+  store_mid(L, p, n, md, no_cross(), 1u);
+  const Cross ce = edge_cross<CW>(S, A.F, end_surf(e0, e0n), xd, L.stk, L.wc);
+  const Cross cl = edge_cross<CW>(S, A.F, xd, end_surf(l0, l0n), L.stk, L.wc);
+  light_walk<CW>(L, l0, l0n, l0md, cl, xd, A.depth - 4, false);
+  eye_walk<CW>(L, e0, e0n, e0md, ce, xd, A.depth - 4);
+}
+
+// (4) ghost from emitter: the ray x_L -> x_G gives the first vertex.
+template <bool CW>
+DEV void tech4(Lane& L) {
+  const WalkArgs& A = L.A;
+  const DevScene& S = A.S;
+  float u[4];
+  draw(L.g, 0, 0, 0, u);
+  vec3 xg, ng;
+  uint32_t gmd;
+  int tri;
+  object_point(S, A.F.ghost, u, xg, ng, gmd, tri);
+  draw(L.g, 0, 0, 1, u);
+  LightEnd E;
+  if (!sample_light(S, u, E) || E.env) return;
+  if (!(dot(E.n, xg - E.p) > 0.0f)) return;
+  const vec3 o = spawn(S, E.p, E.n, xg);
+  const vec3 w = unit(xg - o);
+  const float tg = sqrtf(len2(xg - o));
+  const Hit h = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, o, w, L.stk, L.wc);
+  if (!h.ok || !(h.t > tg)) return;
+  vec3 q, qn;
+  uint32_t qmd;
+  hit_vertex(S, A.F.pose, h, o, w, q, qn, qmd);
+  if (is_emitter(S, qmd)) return;
+  const End eL = end_light(E), x1 = end_surf(q, qn);
+  if (!ghost_on_edge(L, x1, eL, tri)) return;
+  const Cross c = edge_cross<CW>(S, A.F, x1, eL, L.stk, L.wc);
+  store_xl(L, E);
+  eye_walk<CW>(L, q, qn, qmd, c, eL, A.depth - 2);
+}
+
+// (5) ghost from sensor: the camera ray through x_G gives x_1.
+template <bool CW>
+DEV void tech5(Lane& L) {
+  const WalkArgs& A = L.A;
+  const DevScene& S = A.S;
+  if (A.depth < 2) return;
+  float u[4];
+  draw(L.g, 0, 0, 0, u);
+  vec3 xg, ng;
+  uint32_t gmd;
+  int tri;
+  object_point(S, A.F.ghost, u, xg, ng, gmd, tri);
+  const vec3 w = unit(xg - S.cam.eye);
+  const float tg = sqrtf(len2(xg - S.cam.eye));
+  const Hit h = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, S.cam.eye, w, L.stk, L.wc);
+  if (!h.ok || !(h.t > tg)) return;
+  vec3 q, qn;
+  uint32_t qmd;
+  hit_vertex(S, A.F.pose, h, S.cam.eye, w, q, qn, qmd);
+  if (is_emitter(S, qmd)) return;
+  if (raster(S.cam, q) < 0) return;
+  const End e0 = end_eye(S), x1 = end_surf(q, qn);
+  if (!ghost_on_edge(L, e0, x1, tri)) return;
+  const Cross c = edge_cross<CW>(S, A.F, e0, x1, L.stk, L.wc);
+  light_walk<CW>(L, q, qn, qmd, c, e0, A.depth - 2, false);
+}
+
+// (6) ghost two ends: a uniform direction through x_G, rays both ways.
+template <bool CW>
+DEV void tech6(Lane& L) {
+  const WalkArgs& A = L.A;
+  const DevScene& S = A.S;
+  if (A.depth < 3) return;
+  float u[4];
+  draw(L.g, 0, 0, 0, u);
+  vec3 xg, ng;
+  uint32_t gmd;
+  int tri;
+  object_point(S, A.F.ghost, u, xg, ng, gmd, tri);
+  draw(L.g, 0, 0, 2, u);
+  const vec3 w = sphere_dir(u[0], u[1]);
+  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, xg, w, L.stk, L.wc);
+  if (!hl.ok) return;
+  vec3 l0, l0n;
+  uint32_t l0md;
+  hit_vertex(S, A.F.pose, hl, xg, w, l0, l0n, l0md);
+  if (is_emitter(S, l0md)) return;
+  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, xg, -w, L.stk, L.wc);
+  if (!he.ok) return;
+  vec3 e0, e0n;
+  uint32_t e0md;
+  hit_vertex(S, A.F.pose, he, xg, -w, e0, e0n, e0md);
+  if (is_emitter(S, e0md)) return;
+  const End ee = end_surf(e0, e0n), el = end_surf(l0, l0n);
+  if (!ghost_on_edge(L, ee, el, tri)) return;
+  const Cross c = edge_cross<CW>(S, A.F, ee, el, L.stk, L.wc);
+  light_walk<CW>(L, l0, l0n, l0md, c, ee, A.depth - 3, false);
+  eye_walk<CW>(L, e0, e0n, e0md, c, el, A.depth - 3);
+}
+
+// (7) path tracing with static paths rejected (and tech 0: plain frames).
+template <bool CW>
+DEV void tech7(Lane& L) {
+  const WalkArgs& A = L.A;
+  const DevScene& S = A.S;
+  const int P = S.cam.W * S.cam.H;
+  const int pixel = (int)((uint32_t)(A.sample0 + L.s) % (uint32_t)P);
+  float u[4];
+  draw(L.g, 0, 0, 0, u);
+  const vec3 w = camera_dir(S.cam, pixel, u[0], u[1]);
+  const Hit h = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, S.cam.eye, w, L.stk, L.wc);
+  const End e0 = end_eye(S);
+  if (!h.ok) {
+    if (S.p_env > 0.0f) {
+      LightEnd E;
+      E.env = 1;
+      E.n = w;
+      E.p = v3(0, 0, 0);
+      E.mat = 0;
+      if (raster(S.cam, S.cam.eye + w) < 0) return;
+      const Cross c = edge_cross<CW>(S, A.F, e0, end_light(E), L.stk, L.wc);
+      store_xl(L, E);
+      store_mid(L, v3(0, 0, 0), v3(0, 0, 0), 0u, c, 0u);
+      L.k2 = c.n > 0.0f ? 1 : 0;
+    }
+    return;
+  }
+  vec3 q, qn;
+  uint32_t qmd;
+  hit_vertex(S, A.F.pose, h, S.cam.eye, w, q, qn, qmd);
+  if (is_emitter(S, qmd)) {
+    LightEnd E;
+    E.env = 0;
+    E.p = q;
+    E.n = qn;
+    E.mat = qmd & ~kDynBit;
+    if (!(dot(qn, S.cam.eye - q) > 0.0f) || raster(S.cam, q) < 0) return;
+    const Cross c = edge_cross<CW>(S, A.F, e0, end_light(E), L.stk, L.wc);
+    store_xl(L, E);
+    store_mid(L, v3(0, 0, 0), v3(0, 0, 0), 0u, c, 0u);
+    L.k2 = c.n > 0.0f ? 1 : 0;
+    return;
+  }
+  if (raster(S.cam, q) < 0) return;
+  const Cross c = edge_cross<CW>(S, A.F, e0, end_surf(q, qn), L.stk, L.wc);
+  light_walk<CW>(L, q, qn, qmd, c, e0, A.depth - 2, false);
+}
+
+// Number of connected paths of a sample and the i-th of them.
+template <int TECH>
+DEV int pair_count(const Lane& L, int depth) {
+  int c = 0;
+  if (TECH == 1 || TECH == 4) {
+    c = __popc(L.camok);
+  } else if (TECH == 2 || TECH == 5) {
+    c = __popc(L.neeok);
+  } else if (TECH == 7) {
+    c = __popc(L.neeok & L.dynpre) + L.k2;
+  } else {
+    const int extra = TECH == 3 ? 4 : 3;
+    for (int i = 0; i < L.nE; ++i)
+      if (L.camok >> i & 1u)
+        for (int j = 0; j < L.nL; ++j)
+          if ((L.neeok >> j & 1u) && i + j + extra <= depth) ++c;
+  }
+  return c;
+}
+DEV uint32_t pair_code(int s, int i, int j) { return ((uint32_t)s << 8) | ((uint32_t)(i + 1) << 4) | (uint32_t)(j + 1); }
+
+template <int TECH>
+DEV void write_pairs(const Lane& L, uint32_t* out, int depth) {
+  int w = 0;
+  if (TECH == 1 || TECH == 4) {
+    for (int i = 0; i < L.nE; ++i)
+      if (L.camok >> i & 1u) out[w++] = pair_code(L.s, i, -1);
+  } else if (TECH == 2 || TECH == 5 || TECH == 7) {
+    if (TECH == 7 && L.k2) out[w++] = pair_code(L.s, -1, -1);
+    const uint32_t m = TECH == 7 ? (L.neeok & L.dynpre) : L.neeok;
+    for (int j = 0; j < L.nL; ++j)
+      if (m >> j & 1u) out[w++] = pair_code(L.s, -1, j);
+  } else {
+    const int extra = TECH == 3 ? 4 : 3;
+    for (int i = 0; i < L.nE; ++i)
+      if (L.camok >> i & 1u)
+        for (int j = 0; j < L.nL; ++j)
+          if ((L.neeok >> j & 1u) && i + j + extra <= depth) out[w++] = pair_code(L.s, i, j);
+  }
+}
+
+// Wave-level exclusive prefix sum with one queue reservation per wave.
+DEV uint32_t wave_reserve(uint32_t* counter, int c, int& total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int x = c;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  total = __shfl(x, kWave - 1, kWave);
+  uint32_t base = 0;
+  if (lane == kWave - 1 && total > 0) base = atomicAdd(counter, (uint32_t)total);
+  base = __shfl(base, kWave - 1, kWave);
+  return base + (uint32_t)(x - c);
+}
+
+// Instrumented variants: wave-reduced work counters, one atomic per wave and field.
+DEV unsigned long long wave_sum(uint32_t x) {
+  unsigned long long v = x;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+DEV void flush_work(DevStats* st, int kid, const WorkCount& wc) {
+  const bool lead = (threadIdx.x & (kWave - 1)) == 0;
+  const unsigned long long n = wave_sum(wc.nodes), t = wave_sum(wc.tris), b = wave_sum(wc.bytes);
+  unsigned long long r[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) r[q] = wave_sum(wc.rays[q]);
+  if (lead) {
+    atomicAdd(&st->nodes, n);
+    atomicAdd(&st->tris, t);
+    atomicAdd(&st->knodes[kid], n);
+    atomicAdd(&st->ktris[kid], t);
+    atomicAdd(&st->kbytes[kid], b);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) atomicAdd(&st->rays[q], r[q]);
+  }
+}
+
+template <int TECH, bool CW>
+__global__ __launch_bounds__(kTraceBlock) void walk_kernel(WalkArgs A) {
+  __shared__ int stk[kStackDepth * kTraceBlock];
+  const int s = blockIdx.x * kTraceBlock + threadIdx.x;
+  Lane L{A, Rng{A.k0, A.k1, (uint32_t)(A.sample0 + s), ((uint32_t)TECH << 24) | ((uint32_t)A.dir << 23), A.job},
+         s, stk, WorkCount{}, 0, 0, 0u, 0u, 0u, 0};
+  if (s < A.nsamples) {
+    if (TECH == 1) tech1<CW>(L);
+    if (TECH == 2) tech2<CW>(L);
+    if (TECH == 3) tech3<CW>(L);
+    if (TECH == 4) tech4<CW>(L);
+    if (TECH == 5) tech5<CW>(L);
+    if (TECH == 6) tech6<CW>(L);
+    if (TECH == 7) tech7<CW>(L);
+    A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
+  }
+  const int c = s < A.nsamples ? pair_count<TECH>(L, A.depth) : 0;
+  int total;
+  const uint32_t at = wave_reserve(A.W.npairs, c, total);
+  if (c > 0 && at + (uint32_t)c <= (uint32_t)A.W.pair_cap) write_pairs<TECH>(L, A.W.pairs + at, A.depth);
+  if (CW) {
+    L.wc.bytes += 4u * (uint32_t)c + (s < A.nsamples ? 4u : 0u);
+    flush_work(A.stats, TECH, L.wc);
+  }
+}
+
+// ------------------------------------------------------------------ connect
+struct PV {
+  vec3 p, n;
+  uint32_t md;
+};
+
+DEV vec3 lpos(const LightEnd& E, vec3 from) { return E.env ? from + E.n : E.p; }
+
+
+template <bool CW>
+DEV void connect_one(const WalkArgs& A, uint32_t code, int* stk, WorkCount& wc, float4& rec, int& reason) {
+  const DevScene& S = A.S;
+  const Workspace& W = A.W;
+  const int s = (int)(code >> 8);
+  const int i = (int)((code >> 4) & 15u) - 1;
+  const int j = (int)(code & 15u) - 1;
+  const int T = A.tech;
+  const bool mid = (T == 2 || T == 3);
+  const int nsc = (i + 1) + (mid ? 1 : 0) + (j + 1);  // scattering vertices
+  const int k = nsc + 2;
+  reason = 0;
+  rec = make_float4(__int_as_float(-1), 0.f, 0.f, 0.f);
+
+  // ---- assemble x_0 .. x_{k-1}
+  PV v[kMaxK];
+  Cross ex[kMaxK];
+  v[0] = PV{S.cam.eye, S.cam.fwd, 0u};
+#pragma unroll
+  for (int q = 1; q < kMaxK - 1; ++q) {
+    if (q > nsc) break;
+    float4 a, b;
+    if (q <= i + 1) {
+      a = EYE(W, i + 1 - q, 0, s);
+      b = EYE(W, i + 1 - q, 1, s);
+    } else if (mid && q == i + 2) {
+      a = STA(W, 0, s);
+      b = STA(W, 1, s);
+    } else {
+      const int bb = q - (i + 1) - (mid ? 1 : 0) - 1;
+      a = LIT(W, bb, 0, s);
+      b = LIT(W, bb, 1, s);
+    }
+    v[q] = PV{xyz(a), xyz(b), __float_as_uint(a.w)};
+  }
+  LightEnd E;
+  {
+    float4 a, b;
+    if (j >= 0) {
+      a = LIT(W, j, 3, s);
+      b = LIT(W, j, 4, s);
+    } else {
+      a = STA(W, 3, s);
+      b = STA(W, 4, s);
+    }
+    const uint32_t w = __float_as_uint(a.w);
+    E.p = xyz(a);
+    E.n = xyz(b);
+    E.env = (w & 0x40000000u) ? 1 : 0;
+    E.mat = w & 0x3fffffffu;
+  }
+  // edge crossing records in path order
+  const bool motion = !A.material_mode;
+#pragma unroll
+  for (int a = 0; a < kMaxK - 1; ++a) {
+    ex[a] = no_cross();
+    if (a > k - 2 || !motion) continue;
+    float4 r1, r2;  // crossing record: count in r1.w, sums in r2.xyz
+    if (a == 0 && k == 2) {
+      r1 = STA(W, 1, s);
+      r2 = STA(W, 2, s);
+    } else if (a == 0) {
+      if (i >= 0) {
+        const float4 c = EYE(W, i, 3, s);
+        ex[a] = Cross{c.x, c.y, c.z, c.w};
+        continue;
+      } else if (mid) {
+        r1 = STA(W, 1, s);
+        r2 = STA(W, 2, s);
+      } else {
+        r1 = LIT(W, 0, 1, s);
+        r2 = LIT(W, 0, 2, s);
+      }
+    } else if (a == k - 2) {
+      if (j >= 0) {
+        r1 = LIT(W, j, 4, s);
+        r2 = LIT(W, j, 5, s);
+      } else {
+        r1 = EYE(W, 0, 1, s);
+        r2 = EYE(W, 0, 2, s);
+      }
+    } else if (a <= i + 1) {
+      r1 = EYE(W, i + 1 - a, 1, s);
+      r2 = EYE(W, i + 1 - a, 2, s);
+    } else if (mid && a == i + 2) {
+      r1 = LIT(W, 0, 1, s);
+      r2 = LIT(W, 0, 2, s);
+    } else {
+      const int bb = a - (i + 1) - (mid ? 1 : 0);  // edge (light[bb-1], light[bb])
+      r1 = LIT(W, bb, 1, s);
+      r2 = LIT(W, bb, 2, s);
+    }
+    ex[a] = Cross{r1.w, r2.x, r2.y, r2.z};
+  }
+
+  const DevCamera& C = S.cam;
+  const float P = (float)(C.W * C.H);
+  // ---- pixel and camera factor W_j G(x0, x1) (shared by the mapped path)
+  int pixel;
+  float camf, pcam;
+  if (k == 2) {
+    if (E.env) {
+      pixel = raster(C, C.eye + E.n);
+      pcam = camera_geo_dir(C, E.n);
+    } else {
+      pixel = raster(C, E.p);
+      pcam = camera_geo(C, E.p, E.n);
+    }
+  } else {
+    pixel = raster(C, v[1].p);
+    pcam = camera_geo(C, v[1].p, v[1].n);
+  }
+  camf = P * pcam;
+  if (pixel < 0) {
+    reason = 7;
+    return;
+  }
+  const vec3 Le = light_Le(S, E);
+
+
+  // ---- f in frame F with vertex `sub` replaced by y (sub = 0: none)
+  auto rest = [&](const DevFrame& F, int sub, const PV& y) -> vec3 {
+    vec3 f = v3(1.f, 1.f, 1.f);
+#pragma unroll
+    for (int q = 1; q < kMaxK - 1; ++q) {
+      if (q > k - 2) break;
+      const PV cur = q == sub ? y : v[q];
+      const vec3 pp = q - 1 == sub ? y.p : v[q - 1].p;
+      vec3 pn;
+      vec3 nn;
+      bool envn = false;
+      if (q + 1 == k - 1) {
+        envn = E.env;
+        pn = E.env ? cur.p + E.n : E.p;
+        nn = E.n;
+      } else {
+        const PV nx = q + 1 == sub ? y : v[q + 1];
+        pn = nx.p;
+        nn = nx.n;
+      }
+      const Material m = vmat(S, F, cur.md);
+      const vec3 wi = unit(pp - cur.p), wo = envn ? E.n : unit(pn - cur.p);
+      const vec3 rho = bsdf_eval(m, cur.n, wi, wo);
+      float g;
+      if (envn) {
+        g = fabsf(dot(cur.n, wo));
+      } else {
+        const vec3 d = pn - cur.p;
+        const vec3 w = unit(d);
+        g = fabsf(dot(cur.n, w)) * fabsf(dot(nn, w)) / len2(d);
+      }
+      f = vmul(f, rho) * g;
+    }
+    return vmul(f, Le);
+  };
+
+  const vec3 fx = (k == 2 ? Le : rest(A.F, 0, v[0])) * camf;
+
+  // ---- MIS (Sec. 4.3): forward/backward pdf tables
+  const float pL = light_pdf(S, E.env);
+  const float pD = S.inv_obj_area;
+  auto origin = [&](int r, int q) -> vec3 {  // ray origin generating q from r
+    const vec3 to = q == k - 1 ? lpos(E, v[k - 2].p) : v[q].p;
+    if (r == 0) return C.eye;
+    if (r == k - 1) return spawn(S, E.p, E.n, to);
+    return spawn(S, v[r].p, v[r].n, to);
+  };
+  auto to_area = [&](int r, int q, vec3 o) -> float {
+    if (q == k - 1 && E.env) return 1.0f;
+    const vec3 d = (q == k - 1 ? E.p : v[q].p) - o;
+    const vec3 nq = q == k - 1 ? E.n : v[q].n;
+    return fabsf(dot(nq, unit(d))) / len2(d);
+  };
+  auto dir_from = [&](int r, int q) -> vec3 {  // unit direction r -> q between path vertices
+    if (q == k - 1 && E.env) return E.n;
+    if (r == k - 1 && E.env) return -E.n;
+    const vec3 a = r == 0 ? C.eye : (r == k - 1 ? E.p : v[r].p);
+    const vec3 b = q == 0 ? C.eye : (q == k - 1 ? E.p : v[q].p);
+    return unit(b - a);
+  };
+  // vertex-generation pdf: vertex q from r by BSDF sampling at r, incoming from o
+  auto gen = [&](int r, int q, int inc) -> float {
+    const Material m = vmat(S, A.F, v[r].md);
+    vec3 og = origin(r, q);
+    const vec3 wo = (q == k - 1 && E.env) ? E.n : unit((q == k - 1 ? E.p : v[q].p) - og);
+    return bsdf_pdf(m, v[r].n, dir_from(r, inc), wo) * to_area(r, q, og);
+  };
+  float Apre[kMaxK], Bsuf[kMaxK + 1];
+  Apre[0] = 1.0f;
+#pragma unroll
+  for (int q = 1; q < kMaxK; ++q) Apre[q] = Apre[q - 1];
+#pragma unroll
+  for (int q = 1; q <= kMaxK - 3; ++q)
+    if (q <= k - 3) Apre[q] = Apre[q - 1] * gen(q + 1, q, q + 2);
+#pragma unroll
+  for (int q = kMaxK; q >= 0; --q) Bsuf[q] = 1.0f;
+#pragma unroll
+  for (int q = kMaxK - 2; q >= 2; --q) Bsuf[q] = (q <= k - 2) ? Bsuf[q + 1] * gen(q - 1, q, q - 2) : 1.0f;
+  auto on = [&](int t) { return (A.mask >> (t - 1)) & 1u; };
+  float sum = 0.0f;
+  if (on(7)) sum += k == 2 ? pcam : pcam * Bsuf[2] * pL;
+#pragma unroll
+  for (int m = 1; m < kMaxK - 1; ++m) {
+    if (m > k - 2 || !(v[m].md & kDynBit)) continue;
+    if (m == k - 2) {
+      if (on(1)) sum += pL * pD * Apre[m - 1];
+    } else if (m == 1) {
+      if (on(2) && k >= 4) sum += pD * Bsuf[2] * pL;
+    } else if (on(3)) {
+      const vec3 o = origin(m, m + 1);
+      const vec3 w = unit(v[m + 1].p - o);
+      const float c = dot(v[m].n, w);
+      if (c > 0.0f) sum += pD * (c / kPi) * to_area(m, m + 1, o) * Apre[m - 1] * Bsuf[m + 2] * pL;
+    }
+  }
+  if (motion && k >= 3) {
+    const float pG = pD;
+    const float pdir = 1.0f / (4.0f * kPi);
+#pragma unroll
+    for (int a = 0; a < kMaxK - 1; ++a) {
+      if (a > k - 2 || !(ex[a].n > 0.0f)) continue;
+      if (a == k - 2) {
+        if (on(4) && !E.env) {
+          const vec3 o = origin(k - 1, k - 2);
+          const vec3 d = v[k - 2].p - o;
+          sum += pL * pG * ex[a].sb * fabsf(dot(v[k - 2].n, unit(d))) / len2(d) * Apre[k - 3];
+        }
+      } else if (a == 0) {
+        if (on(5)) {
+          const vec3 d = v[1].p - C.eye;
+          sum += pG * ex[a].sa * fabsf(dot(v[1].n, unit(d))) / len2(d) * Bsuf[2] * pL;
+        }
+      } else if (on(6)) {
+        const vec3 d = v[a + 1].p - v[a].p;
+        const vec3 w = unit(d);
+        const float G = fabsf(dot(v[a].n, w)) * fabsf(dot(v[a + 1].n, w)) / len2(d);
+        sum += pG * pdir * G * ex[a].s0 * Apre[a > 0 ? a - 1 : 0] * Bsuf[a + 2] * pL;
+      }
+    }
+  }
+  if (!(sum > 0.0f)) {
+    reason = 8;
+    return;
+  }
+
+  // ---- path mapping and rejection (Sec. 5)
+  vec3 val;
+  if (A.material_mode) {
+    val = (fx - (k == 2 ? Le : rest(A.Fp, 0, v[0])) * camf) * A.cweight;
+  } else {
+    int rej = 0;
+    PV y = v[0];
+    int istar = 0;
+    const DevFrame& Fp = A.Fp;
+    if (k <= 2) {
+      rej = 1;
+    } else if (A.F.same_pose) {
+#pragma unroll
+      for (int a = 0; a < kMaxK - 1; ++a)
+        if (a <= k - 2 && ex[a].n > 0.0f) rej = 5;
+    } else {
+      const bool retrace = (v[1].md & kDynBit) || ex[0].n > 0.0f;
+      int moved = retrace ? 1 : 0;
+      istar = retrace ? 1 : 0;
+#pragma unroll
+      for (int q = 2; q < kMaxK - 1; ++q)
+        if (q <= k - 2 && (v[q].md & kDynBit)) {
+          ++moved;
+          istar = q;
+        }
+      if (moved > 1) rej = 2;
+      if (!rej && moved == 1) {
+        if (istar == 1) {
+          const vec3 w = unit(v[1].p - C.eye);
+          const Hit h = closest<CW>(S, Fp.pose, Fp.olo, Fp.ohi, C.eye, w, stk, wc, RAY_RETRACE);
+          if (!h.ok) {
+            rej = 1;
+          } else {
+            hit_vertex(S, Fp.pose, h, C.eye, w, y.p, y.n, y.md);
+            if (is_emitter(S, y.md)) rej = 1;
+          }
+        } else {
+          PV x = v[1];
+#pragma unroll
+          for (int q = 2; q < kMaxK - 1; ++q)
+            if (q == istar) x = v[q];
+          y.p = pose_apply(Fp.pose, pose_inv_apply(A.F.pose, x.p));
+          y.n = pose_rot(Fp.pose, pose_inv_rot(A.F.pose, x.n));
+          y.md = x.md;
+        }
+      }
+      // R3 / R4 at the reconnection neighbours of the moved vertex
+      if (!rej && moved == 1) {
+        PV xs = v[1];
+#pragma unroll
+        for (int q = 2; q < kMaxK - 1; ++q)
+          if (q == istar) xs = v[q];
+        const float ax = roughness(vmat(S, A.F, xs.md)), ay = roughness(vmat(S, Fp, y.md));
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int jn = side == 0 ? istar - 1 : istar + 1;
+          if (jn < 1 || rej) continue;
+          const bool light = jn == k - 1;
+          PV xj = v[1];
+#pragma unroll
+          for (int q = 1; q < kMaxK - 1; ++q)
+            if (q == jn) xj = v[q];
+          if (!light && (xj.md & kDynBit)) rej = 3;
+          const float aj = light ? 1.0f : roughness(vmat(S, A.F, xj.md));
+          if (fminf(fminf(ax, ay), aj) < A.alpha_min) rej = rej ? rej : 3;
+          if (rej || (light && E.env)) continue;
+          const vec3 pj = light ? E.p : xj.p, nj = light ? E.n : xj.n;
+          const vec3 dy = y.p - pj, dxv = xs.p - pj;
+          const float ly2 = dot(dy, dy), lx2 = dot(dxv, dxv);
+          if (fminf(sqrtf(ly2), sqrtf(lx2)) < A.d_min) {
+            rej = 3;
+            continue;
+          }
+          const float jac = (fabsf(dot(nj, dy)) / sqrtf(ly2)) / (fabsf(dot(nj, dxv)) / sqrtf(lx2)) * (lx2 / ly2);
+          if (!(jac <= A.jac_max && jac >= 1.0f / A.jac_max)) rej = 4;
+        }
+      }
+      // R6: support of the mapped path in f'
+      if (!rej) {
+#pragma unroll
+        for (int q = 1; q < kMaxK - 1; ++q) {
+          if (q > k - 2 || rej) continue;
+          const PV cur = q == istar ? y : v[q];
+          if (is_emitter(S, cur.md)) rej = 6;
+          const vec3 a = q - 1 == 0 ? C.eye : (q - 1 == istar ? y.p : v[q - 1].p);
+          vec3 b;
+          if (q + 1 == k - 1) b = E.env ? cur.p + E.n : E.p;
+          else b = q + 1 == istar ? y.p : v[q + 1].p;
+          if (!same_side(cur.n, cur.p, a, b)) rej = 6;
+        }
+        if (!rej && !E.env) {
+          const vec3 prv = k - 2 == istar ? y.p : v[k - 2].p;
+          if (!(dot(E.n, prv - E.p) > 0.0f)) rej = 6;
+        }
+      }
+      // R5: visibility in f' (edges at the moved vertex), ghost records elsewhere
+      if (!rej) {
+#pragma unroll
+        for (int a = 0; a < kMaxK - 1; ++a) {
+          if (a > k - 2 || rej) continue;
+          const bool touches = moved == 1 && (a == istar - 1 || a == istar);
+          if (touches) {
+            if (a == 0) continue;
+            const PV pa = a == istar ? y : v[a];
+            const End EA = end_surf(pa.p, pa.n);
+            End EB;
+            if (a + 1 == k - 1) EB = end_light(E);
+            else {
+              const PV pb = a + 1 == istar ? y : v[a + 1];
+              EB = end_surf(pb.p, pb.n);
+            }
+            if (!edge_visible<CW>(S, Fp, EA, EB, stk, wc, RAY_MAPVIS)) rej = 5;
+          } else if (ex[a].n > 0.0f) {
+            rej = 5;
+          }
+        }
+      }
+    }
+    if (!rej) {
+      const vec3 fy = rest(Fp, istar, y) * camf;
+      val = (fx - fy) * A.cweight;
+    } else {
+      val = fx;
+    }
+    reason = rej;
+  }
+  const float sc = A.sigma / sum * A.inv_n;
+  rec = make_float4(__int_as_float(pixel), val.x * sc, val.y * sc, val.z * sc);
+}
+
+template <bool CW>
+__global__ __launch_bounds__(kTraceBlock) void connect_kernel(WalkArgs A) {
+  __shared__ int stk[kStackDepth * kTraceBlock];
+  __shared__ unsigned long long cnt[16];
+  if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t n = min((uint32_t)A.W.pair_cap, *A.W.npairs);
+  WorkCount wc{};
+  for (uint32_t idx = blockIdx.x * kTraceBlock + threadIdx.x; idx < n; idx += gridDim.x * kTraceBlock) {
+    const uint32_t code = A.W.pairs[idx];
+    float4 rec;
+    int reason;
+    connect_one<CW>(A, code, stk, wc, rec, reason);
+    A.W.records[idx] = rec;
+    if (CW) wc.bytes += 16u;
+    if (A.keep_records) {
+      A.W.rec_keys[idx] = (uint32_t)A.dir | ((uint32_t)A.tech << 1) | ((code & 0xffu) << 8);
+      A.W.rec_sample[idx] = (uint32_t)(A.sample0 + (code >> 8));
+    }
+    if (A.stats && reason <= 6) {
+      atomicAdd(&cnt[reason], 1ull);
+    }
+  }
+  __syncthreads();
+  if (A.stats && threadIdx.x < 7) {
+    const unsigned long long c = cnt[threadIdx.x];
+    if (c) {
+      if (threadIdx.x == 0) atomicAdd(&A.stats->accepted, c);
+      else atomicAdd(&A.stats->rejected[threadIdx.x], c);
+      atomicAdd(&A.stats->paths, c);
+      atomicAdd(&A.stats->by_tech[A.tech], c);
+    }
+  }
+  if (CW) flush_work(A.stats, 8, wc);
+}
+
+// ------------------------------------------------------------------ splat
+DEV int tile_of(const SplatArgs& a, int pixel) {
+  const int px = pixel % a.W, py = pixel / a.W;
+  return (py / kTile) * a.tilesx + px / kTile;
+}
+
+__global__ void zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+__global__ void zero_f32(float* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void splat_hist(SplatArgs a) {
+  const uint32_t n = (uint32_t)min((int64_t)*a.nrec, a.cap);
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int pixel = __float_as_int(a.records[i].x);
+    if (pixel >= 0) atomicAdd(&a.tcount[tile_of(a, pixel)], 1u);
+  }
+}
+
+// Exclusive scan of the tile counts by one workgroup.
+__global__ __launch_bounds__(1024) void splat_scan(SplatArgs a) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (a.ntiles + 1023) / 1024;
+  uint32_t sum = 0;
+  for (int i = t * per; i < min(a.ntiles, (t + 1) * per); ++i) sum += a.tcount[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t x = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += x;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+  for (int i = t * per; i < min(a.ntiles, (t + 1) * per); ++i) {
+    a.toff[i] = run;
+    run += a.tcount[i];
+  }
+  if (t == 1023) a.toff[a.ntiles] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void splat_scatter(SplatArgs a) {
+  const uint32_t n = (uint32_t)min((int64_t)*a.nrec, a.cap);
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const float4 r = a.records[i];
+    const int pixel = __float_as_int(r.x);
+    if (pixel < 0) continue;
+    const int t = tile_of(a, pixel);
+    const uint32_t at = a.toff[t] + atomicAdd(&a.tcursor[t], 1u);
+    const int px = pixel % a.W, py = pixel / a.W;
+    const int local = (py % kTile) * kTile + (px % kTile);
+    a.binned[at] = make_float4(__int_as_float(local), r.y, r.z, r.w);
+  }
+}
+
+// One workgroup per tile: LDS accumulation, one read-modify-write of the tile.
+__global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
+  __shared__ float acc[kTile * kTile * 3];
+  const int t = blockIdx.x;
+  for (int i = threadIdx.x; i < kTile * kTile * 3; i += 256) acc[i] = 0.0f;
+  __syncthreads();
+  const uint32_t b = a.toff[t], e = a.toff[t + 1];
+  for (uint32_t i = b + threadIdx.x; i < e; i += 256) {
+    const float4 r = a.binned[i];
+    const int l = __float_as_int(r.x);
+    atomicAdd(&acc[3 * l + 0], r.y);
+    atomicAdd(&acc[3 * l + 1], r.z);
+    atomicAdd(&acc[3 * l + 2], r.w);
+  }
+  __syncthreads();
+  if (e == b) return;
+  const int tx = t % a.tilesx, ty = t / a.tilesx;
+  const int l = threadIdx.x;
+  const int px = tx * kTile + (l % kTile), py = ty * kTile + (l / kTile);
+  if (px < a.W && py < a.H) {
+    float* o = a.image + 3 * ((size_t)py * a.W + px);
+    o[0] += acc[3 * l];
+    o[1] += acc[3 * l + 1];
+    o[2] += acc[3 * l + 2];
+  }
+}
+
+// ------------------------------------------------------------------ frames
+// One lane per pixel; samples s = pixel + m * P (the residual technique (7)
+// uses the same pixel-of-sample rule).
+__global__ __launch_bounds__(kTraceBlock) void frame_kernel(FrameArgs A) {
+  __shared__ int stk[kStackDepth * kTraceBlock];
+  const DevScene& S = A.S;
+  const DevCamera& C = S.cam;
+  const int P = C.W * C.H;
+  const int pixel = blockIdx.x * kTraceBlock + threadIdx.x;
+  if (pixel >= P) return;
+  WorkCount wc{};
+  vec3 sum = v3(0, 0, 0);
+  const float Pf = (float)P;
+  const float invN = 1.0f / ((float)A.spp * Pf);
+  for (int m = 0; m < A.spp; ++m) {
+    const int64_t smp = (int64_t)pixel + (int64_t)m * P;
+    if (smp < A.s0 || smp >= A.s1) continue;
+    Rng g{A.k0, A.k1, (uint32_t)smp, (uint32_t)A.dir << 23, A.job};
+    float u[4];
+    draw(g, 0, 0, 0, u);
+    const vec3 w = camera_dir(C, pixel, u[0], u[1]);
+    const Hit h = closest<false>(S, A.F.pose, A.F.olo, A.F.ohi, C.eye, w, stk, wc);
+    if (!h.ok) {
+      if (S.p_env > 0.0f && raster(C, C.eye + w) >= 0) sum = sum + S.env * (Pf * invN);
+      continue;
+    }
+    vec3 p, n;
+    uint32_t md;
+    hit_vertex(S, A.F.pose, h, C.eye, w, p, n, md);
+    const int pix1 = raster(C, p);
+    if (pix1 < 0) continue;
+    if (is_emitter(S, md)) {
+      if (dot(n, C.eye - p) > 0.0f) {
+        const float* em = S.mats + 8 * (md & ~kDynBit) + 5;
+        sum = sum + v3(em[0], em[1], em[2]) * (Pf * invN);
+      }
+      continue;
+    }
+    // throughput f / p up to the current vertex (camera factor / camera pdf = P)
+    vec3 beta = v3(Pf, Pf, Pf);
+    vec3 prev = C.eye;
+    for (int b = 0; b + 2 <= A.depth; ++b) {
+      const Material mt = vmat(S, A.F, md);
+      draw(g, 0, b + 1, 1, u);
+      LightEnd E;
+      if (sample_light(S, u, E)) {
+        const bool face = E.env ? true : dot(E.n, p - E.p) > 0.0f;
+        const vec3 lp = E.env ? p + E.n : E.p;
+        if (face && same_side(n, p, prev, lp) &&
+            edge_visible<false>(S, A.F, end_surf(p, n), end_light(E), stk, wc, RAY_SHADOW)) {
+          const vec3 wl = E.env ? E.n : unit(E.p - p);
+          const vec3 rho = bsdf_eval(mt, n, unit(prev - p), wl);
+          float gg;
+          if (E.env) {
+            gg = fabsf(dot(n, wl));
+          } else {
+            const vec3 d = E.p - p;
+            gg = fabsf(dot(n, wl)) * fabsf(dot(E.n, wl)) / len2(d);
+          }
+          const vec3 c = vmul(vmul(beta, rho), light_Le(S, E)) * (gg / light_pdf(S, E.env));
+          sum = sum + c * invN;
+        }
+      }
+      if (b + 3 > A.depth) break;
+      draw(g, 0, b + 1, 0, u);
+      vec3 wo;
+      if (!bsdf_sample(mt, n, unit(prev - p), u[0], u[1], wo)) break;
+      const vec3 o = spawn_dir(S, p, n, wo);
+      const Hit h2 = closest<false>(S, A.F.pose, A.F.olo, A.F.ohi, o, wo, stk, wc);
+      if (!h2.ok) break;
+      vec3 q, qn;
+      uint32_t qmd;
+      hit_vertex(S, A.F.pose, h2, o, wo, q, qn, qmd);
+      if (is_emitter(S, qmd)) break;
+      // f/p update: rho G / (pdf_w * cos_q / r^2 from the offset origin)
+      const vec3 wi = unit(prev - p);
+      const vec3 rho = bsdf_eval(mt, n, wi, unit(q - p));
+      const vec3 d = q - p;
+      const vec3 du = unit(d);
+      const float G = fabsf(dot(n, du)) * fabsf(dot(qn, du)) / len2(d);
+      const vec3 dq = q - o;
+      const float pa = bsdf_pdf(mt, n, wi, wo) * fabsf(dot(qn, unit(dq))) / len2(dq);
+      beta = vmul(beta, rho) * (G / pa);
+      prev = p;
+      p = q;
+      n = qn;
+      md = qmd;
+    }
+  }
+  float* o = A.image + 3 * (size_t)pixel;
+  if (A.accumulate) {
+    o[0] += sum.x;
+    o[1] += sum.y;
+    o[2] += sum.z;
+  } else {
+    o[0] = sum.x;
+    o[1] = sum.y;
+    o[2] = sum.z;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <int T, bool CW>
+static void launch_walk_t(const WalkArgs& A, hipStream_t st) {
+  const int blocks = (A.nsamples + kTraceBlock - 1) / kTraceBlock;
+  hipLaunchKernelGGL((walk_kernel<T, CW>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
+}
+template <bool CW>
+static void launch_walk_cw(const WalkArgs& A, hipStream_t st) {
+  switch (A.tech) {
+    case 1: launch_walk_t<1, CW>(A, st); break;
+    case 2: launch_walk_t<2, CW>(A, st); break;
+    case 3: launch_walk_t<3, CW>(A, st); break;
+    case 4: launch_walk_t<4, CW>(A, st); break;
+    case 5: launch_walk_t<5, CW>(A, st); break;
+    case 6: launch_walk_t<6, CW>(A, st); break;
+    default: launch_walk_t<7, CW>(A, st); break;
+  }
+}
+
+void launch_walk(const WalkArgs& A, hipStream_t st) {
+  if (A.count_work) launch_walk_cw<true>(A, st);
+  else launch_walk_cw<false>(A, st);
+}
+void launch_connect(const WalkArgs& A, int blocks, hipStream_t st) {
+  if (A.count_work)
+    hipLaunchKernelGGL((connect_kernel<true>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
+  else
+    hipLaunchKernelGGL((connect_kernel<false>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
+}
+void launch_splat(const SplatArgs& a, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, st, a.tcount, (int64_t)a.ntiles);
+  hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, st, a.tcursor, (int64_t)a.ntiles);
+  hipLaunchKernelGGL(splat_hist, dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(splat_scan, dim3(1), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(splat_scatter, dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(splat_tiles, dim3(a.ntiles), dim3(256), 0, st, a);
+}
+void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_u32, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256 + 1)), dim3(256), 0, st, p, n);
+}
+void launch_zero_f32(float* p, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_f32, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256 + 1)), dim3(256), 0, st, p, n);
+}
+void launch_frame(const FrameArgs& A, hipStream_t st) {
+  const int P = A.S.cam.W * A.S.cam.H;
+  hipLaunchKernelGGL(frame_kernel, dim3((P + kTraceBlock - 1) / kTraceBlock), dim3(kTraceBlock), 0, st, A);
+}
+
+}  // namespace rpi

@@ -1,0 +1,220 @@
+"""ctypes binding of librpi.so with the names of include/rpi.h.
+
+Argument marshalling only: host arrays go to rpi_build_scene, device tensors
+(torch, ROCm) and the current HIP stream go to the rendering calls.  Loading
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpi.so")
+
+RPI_OK = 0
+EDIT_RIGID, EDIT_MATERIAL = 0, 1
+FLAG_TWO_WAY, FLAG_ACCUMULATE, FLAG_COUNT_WORK, FLAG_RECORDS, FLAG_TIME_KERNELS = 1, 2, 4, 8, 16
+
+
+class RpiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("rpi error %d: %s" % (code, msg))
+        self.code = code
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("positions", C.POINTER(C.c_float)), ("num_vertices", C.c_int32),
+                ("indices", C.POINTER(C.c_int32)), ("num_triangles", C.c_int32),
+                ("tri_material", C.POINTER(C.c_int32)), ("tri_object", C.POINTER(C.c_int32)),
+                ("materials", C.POINTER(C.c_float)), ("num_materials", C.c_int32),
+                ("env", C.POINTER(C.c_float)), ("camera", C.POINTER(C.c_float))]
+
+
+class EditDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("old_to_new", C.c_float * 12), ("new_material", C.c_float * 8)]
+
+
+class Params(C.Structure):
+    _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("seed", C.c_uint64),
+                ("strategy_mask", C.c_uint32), ("flags", C.c_uint32), ("alpha_min", C.c_float),
+                ("d_min", C.c_float), ("jac_max", C.c_float), ("c_weight", C.c_float),
+                ("sample_begin", C.c_int64), ("sample_end", C.c_int64), ("queue_cap", C.c_int32),
+                ("job", C.c_uint32)]
+
+    @staticmethod
+    def make(spp, depth, seed, mask=0x7F, flags=FLAG_TWO_WAY, alpha_min=0.2, d_min=-1.0, jac_max=10.0,
+             c_weight=0.5, sample_begin=0, sample_end=-1, queue_cap=0, job=0):
+        return Params(spp, depth, seed, mask, flags, alpha_min, d_min, jac_max, c_weight, sample_begin,
+                      sample_end, queue_cap, job)
+
+
+class Stats(C.Structure):
+    _fields_ = [("samples", C.c_int64), ("paths", C.c_int64), ("accepted", C.c_int64),
+                ("rejected", C.c_int64 * 7), ("by_tech", C.c_int64 * 9), ("rays", C.c_int64 * 6),
+                ("nodes_visited", C.c_int64), ("tris_tested", C.c_int64), ("milliseconds", C.c_double),
+                ("kernel_ms", C.c_double * 16), ("kernel_launches", C.c_int64 * 16),
+                ("kernel_nodes", C.c_int64 * 16), ("kernel_tris", C.c_int64 * 16),
+                ("kernel_bytes_written", C.c_int64 * 16)]
+
+    def as_dict(self):
+        return {"samples": self.samples, "paths": self.paths, "accepted": self.accepted,
+                "rejected": list(self.rejected), "by_tech": list(self.by_tech), "rays": list(self.rays),
+                "nodes_visited": self.nodes_visited, "tris_tested": self.tris_tested,
+                "milliseconds": self.milliseconds, "kernel_ms": list(self.kernel_ms),
+                "kernel_launches": list(self.kernel_launches), "kernel_nodes": list(self.kernel_nodes),
+                "kernel_tris": list(self.kernel_tris), "kernel_bytes_written": list(self.kernel_bytes_written)}
+
+
+class Job(C.Structure):
+    _fields_ = [("pose_old", C.c_float * 12), ("pose_new", C.c_float * 12), ("width", C.c_int32),
+                ("height", C.c_int32), ("d_out", C.c_void_p)]
+
+
+_lib = None
+
+
+def load_library():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RpiError(-4, "librpi.so is not built (run __graft_entry__.build() or "
+                               "python paper_2406_16302_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.rpi_build_scene.argtypes = [C.POINTER(SceneDesc), C.POINTER(vp)]
+        L.rpi_destroy_scene.argtypes = [vp]
+        L.rpi_apply_edit.argtypes = [vp, C.POINTER(EditDesc), C.POINTER(vp)]
+        L.rpi_destroy_edit.argtypes = [vp]
+        L.rpi_render_residual.argtypes = [vp, vp, C.POINTER(Params), vp, C.POINTER(Stats), vp]
+        L.rpi_render_frame.argtypes = [vp, vp, C.c_int32, C.POINTER(Params), vp, vp]
+        L.rpi_render_residual_batch.argtypes = [vp, C.POINTER(Job), C.c_int32, C.POINTER(Params),
+                                                C.POINTER(Stats), vp]
+        L.rpi_get_records.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.rpi_last_error.restype = C.c_char_p
+        L.rpi_version.restype = C.c_char_p
+        for f in ("rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
+                  "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records"):
+            getattr(L, f).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != RPI_OK:
+        raise RpiError(rc, load_library().rpi_last_error().decode())
+
+
+def _fp(a, t=C.c_float):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _devptr(t, n):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise RpiError(-1, "output must be a contiguous float32 device tensor")
+    if t.numel() != n:
+        raise RpiError(-1, "output has %d elements, expected %d" % (t.numel(), n))
+    return C.c_void_p(t.data_ptr())
+
+
+class Scene:
+    """rpi_build_scene over a scenes.Scene (host arrays copied by the library)."""
+
+    def __init__(self, sc):
+        L = load_library()
+        self.src = sc
+        arrs = [np.ascontiguousarray(sc.positions, np.float32), np.ascontiguousarray(sc.indices, np.int32),
+                np.ascontiguousarray(sc.tri_material, np.int32), np.ascontiguousarray(sc.tri_object, np.int32),
+                np.ascontiguousarray(sc.materials, np.float32), np.ascontiguousarray(sc.env, np.float32),
+                np.ascontiguousarray(sc.camera, np.float32)]
+        pos, idx, tm, to, mats, env, cam = arrs
+        d = SceneDesc(_fp(pos), len(pos), _fp(idx, C.c_int32), len(idx), _fp(tm, C.c_int32), _fp(to, C.c_int32),
+                      _fp(mats), len(mats), _fp(env), _fp(cam))
+        h = C.c_void_p()
+        _check(L.rpi_build_scene(C.byref(d), C.byref(h)))
+        self.h = h
+        self.width, self.height = sc.width, sc.height
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.rpi_destroy_scene(self.h)
+            self.h = None
+
+    def records(self):
+        L = load_library()
+        n = C.c_int64()
+        _check(L.rpi_get_records(self.h, None, 0, C.byref(n)))
+        out = np.zeros((n.value, 8), np.uint32)
+        _check(L.rpi_get_records(self.h, out.ctypes.data_as(C.c_void_p), n.value, C.byref(n)))
+        return out
+
+
+class Edit:
+    """rpi_apply_edit: rigid motion (old_to_new 3x4) or a material edit."""
+
+    def __init__(self, scene: Scene, edit):
+        L = load_library()
+        d = EditDesc()
+        d.kind = int(edit.kind)
+        m = np.asarray(edit.old_to_new, np.float32).reshape(12)
+        for i in range(12):
+            d.old_to_new[i] = float(m[i])
+        if edit.new_material is not None:
+            nm = np.asarray(edit.new_material, np.float32).reshape(8)
+            for i in range(8):
+                d.new_material[i] = float(nm[i])
+        h = C.c_void_p()
+        _check(L.rpi_apply_edit(scene.h, C.byref(d), C.byref(h)))
+        self.h = h
+        self.scene = scene
+        self.kind = int(edit.kind)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.rpi_destroy_edit(self.h)
+            self.h = None
+
+
+def render_residual(scene: Scene, edit: Edit, params: Params, out, stats=False, stream=None):
+    L = load_library()
+    st = Stats() if stats else None
+    _check(L.rpi_render_residual(scene.h, edit.h, C.byref(params), _devptr(out, scene.width * scene.height * 3),
+                                 C.byref(st) if st is not None else None, _stream(stream)))
+    return st.as_dict() if st is not None else None
+
+
+def render_frame(scene: Scene, edit: Edit | None, which: int, params: Params, out, stream=None):
+    L = load_library()
+    _check(L.rpi_render_frame(scene.h, edit.h if edit is not None else None, int(which), C.byref(params),
+                              _devptr(out, scene.width * scene.height * 3), _stream(stream)))
+
+
+def render_residual_batch(scene: Scene, jobs, params: Params, stats=False, stream=None):
+    """jobs: list of dicts with pose_old, pose_new (3x4), out (float32 device tensor [H, W, 3])."""
+    L = load_library()
+    arr = (Job * len(jobs))()
+    for i, j in enumerate(jobs):
+        po = np.asarray(j["pose_old"], np.float32).reshape(12)
+        pn = np.asarray(j["pose_new"], np.float32).reshape(12)
+        for q in range(12):
+            arr[i].pose_old[q] = float(po[q])
+            arr[i].pose_new[q] = float(pn[q])
+        h, w = j["out"].shape[0], j["out"].shape[1]
+        arr[i].width, arr[i].height = w, h
+        arr[i].d_out = _devptr(j["out"], w * h * 3).value
+    st = Stats() if stats else None
+    _check(L.rpi_render_residual_batch(scene.h, arr, len(jobs), C.byref(params),
+                                       C.byref(st) if st is not None else None, _stream(stream)))
+    return st.as_dict() if st is not None else None
