@@ -622,7 +622,7 @@ struct Ws {
   void* mem = nullptr;
   Workspace W{};
   DevStats* stats = nullptr;
-  uint32_t *tcount, *toff, *tcursor;
+  uint32_t *tcount, *toff, *hist;
   float4* binned;
   size_t bytes = 0;
 };
@@ -651,6 +651,8 @@ int max_pairs_per_sample(int tech, int d) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int kSplatBlocks = 256;
+
 rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, bool keep, hipStream_t st) {
   const int nslot = depth;
   size_t off = 0;
@@ -671,7 +673,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, bool 
   const size_t o_stats = take(sizeof(DevStats));
   const size_t o_tc = take((size_t)ntiles * 4);
   const size_t o_to = take((size_t)(ntiles + 1) * 4);
-  const size_t o_tu = take((size_t)ntiles * 4);
+  const size_t o_tu = take((size_t)ntiles * kSplatBlocks * 4);
   const size_t o_bin = take((size_t)pair_cap * sizeof(float4));
   w.bytes = off;
   HIP_OK(hipMallocAsync(&w.mem, off, st));
@@ -691,7 +693,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, bool 
   w.stats = (DevStats*)(b + o_stats);
   w.tcount = (uint32_t*)(b + o_tc);
   w.toff = (uint32_t*)(b + o_to);
-  w.tcursor = (uint32_t*)(b + o_tu);
+  w.hist = (uint32_t*)(b + o_tu);
   w.binned = (float4*)(b + o_bin);
   return RPI_OK;
 }
@@ -743,6 +745,7 @@ static rpi_status residual_job(const rpi_scene* s, const float* pose_old, const 
   Q = std::min(Q, 1 << 24);
   const int d = p->max_depth;
   const int tilesx = (W + 15) / 16, ntiles = tilesx * ((H + 15) / 16);
+  if (ntiles > 16384) return fail(RPI_ERR_UNSUPPORTED, "image larger than 2048x2048");
   int maxp = 0;
   for (int t = 1; t <= 7; ++t) maxp = std::max(maxp, max_pairs_per_sample(t, d) + (t == 7 ? 1 : 0));
   const int64_t pair_cap = (int64_t)Q * maxp;
@@ -785,7 +788,8 @@ static rpi_status residual_job(const rpi_scene* s, const float* pose_old, const 
   sa.cap = pair_cap;
   sa.tcount = w.tcount;
   sa.toff = w.toff;
-  sa.tcursor = w.tcursor;
+  sa.hist = w.hist;
+  sa.nblk = kSplatBlocks;
   sa.binned = w.binned;
   sa.image = out;
   sa.W = W;
@@ -811,7 +815,7 @@ static rpi_status residual_job(const rpi_scene* s, const float* pose_old, const 
         if (r1) return r1;
         r1 = timed(8, [&] { launch_connect(A, cblocks, st); });
         if (r1) return r1;
-        r1 = timed(9, [&] { launch_splat(sa, cblocks, st); });
+        r1 = timed(9, [&] { launch_splat(sa, st); });
         if (r1) return r1;
         if (keep && rec_out) {
           // host copies of this chunk's records (debug path; synchronous)

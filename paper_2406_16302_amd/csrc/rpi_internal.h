@@ -156,16 +156,18 @@ struct WalkArgs {
   int32_t keep_records;
 };
 
+// Tile-binned splat of one record queue.  ntiles * 4 bytes of LDS per
+// workgroup hold a tile histogram (ntiles <= 16384).
 struct SplatArgs {
   const float4* records;
   const uint32_t* nrec;
   int64_t cap;
+  uint32_t* hist;     // [ntiles * nblk], then its per-tile exclusive scan
   uint32_t* tcount;   // [ntiles]
   uint32_t* toff;     // [ntiles + 1]
-  uint32_t* tcursor;  // [ntiles]
   float4* binned;     // [cap]
   float* image;
-  int W, H, tilesx, ntiles;
+  int W, H, tilesx, ntiles, nblk;
 };
 
 struct FrameArgs {
@@ -181,7 +183,7 @@ struct FrameArgs {
 // launchers (rpi_kernels.hip)
 void launch_walk(const WalkArgs& A, hipStream_t st);
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st);
-void launch_splat(const SplatArgs& a, int blocks, hipStream_t st);
+void launch_splat(const SplatArgs& a, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
 void launch_zero_f32(float* p, int64_t n, hipStream_t st);
 void launch_frame(const FrameArgs& A, hipStream_t st);

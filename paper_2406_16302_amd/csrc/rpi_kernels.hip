@@ -954,16 +954,59 @@ __global__ void zero_f32(float* p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.0f;
 }
 
-__global__ __launch_bounds__(256) void splat_hist(SplatArgs a) {
-  const uint32_t n = (uint32_t)min((int64_t)*a.nrec, a.cap);
-  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const int pixel = __float_as_int(a.records[i].x);
-    if (pixel >= 0) atomicAdd(&a.tcount[tile_of(a, pixel)], 1u);
-  }
+// Counting sort of the records by tile without global atomics: block b owns
+// the contiguous record slice [b*len, (b+1)*len) and histograms it in LDS;
+// hist[tile * nblk + b] is then scanned tile-major, and the same block
+// scatters its slice with LDS cursors.
+DEV void slice(const SplatArgs& a, uint32_t n, uint32_t& b0, uint32_t& b1) {
+  const uint32_t len = (n + a.nblk - 1) / a.nblk;
+  b0 = min(n, blockIdx.x * len);
+  b1 = min(n, b0 + len);
 }
 
-// Exclusive scan of the tile counts by one workgroup.
-__global__ __launch_bounds__(1024) void splat_scan(SplatArgs a) {
+__global__ __launch_bounds__(256) void splat_count(SplatArgs a) {
+  extern __shared__ uint32_t lh[];  // [ntiles]
+  const uint32_t n = (uint32_t)min((int64_t)*a.nrec, a.cap);
+  for (int t = threadIdx.x; t < a.ntiles; t += 256) lh[t] = 0u;
+  __syncthreads();
+  uint32_t b0, b1;
+  slice(a, n, b0, b1);
+  for (uint32_t i = b0 + threadIdx.x; i < b1; i += 256) {
+    const int pixel = __float_as_int(a.records[i].x);
+    if (pixel >= 0) atomicAdd(&lh[tile_of(a, pixel)], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < a.ntiles; t += 256) a.hist[(size_t)t * a.nblk + blockIdx.x] = lh[t];
+}
+
+// One workgroup per tile: exclusive scan of its nblk block counts (in place)
+// and the tile total.
+__global__ __launch_bounds__(256) void splat_scan_blocks(SplatArgs a) {
+  __shared__ uint32_t part[256];
+  const int t = blockIdx.x;
+  uint32_t* h = a.hist + (size_t)t * a.nblk;
+  const int per = (a.nblk + 255) / 256;
+  uint32_t sum = 0;
+  for (int i = threadIdx.x * per; i < min(a.nblk, (int)(threadIdx.x + 1) * per); ++i) sum += h[i];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - sum;
+  for (int i = threadIdx.x * per; i < min(a.nblk, (int)(threadIdx.x + 1) * per); ++i) {
+    const uint32_t c = h[i];
+    h[i] = run;
+    run += c;
+  }
+  if (threadIdx.x == 255) a.tcount[t] = part[255];
+}
+
+// Exclusive scan of the tile totals by one workgroup.
+__global__ __launch_bounds__(1024) void splat_scan_tiles(SplatArgs a) {
   __shared__ uint32_t part[1024];
   const int t = threadIdx.x;
   const int per = (a.ntiles + 1023) / 1024;
@@ -986,13 +1029,18 @@ __global__ __launch_bounds__(1024) void splat_scan(SplatArgs a) {
 }
 
 __global__ __launch_bounds__(256) void splat_scatter(SplatArgs a) {
+  extern __shared__ uint32_t cur[];  // [ntiles] write cursors of this block
   const uint32_t n = (uint32_t)min((int64_t)*a.nrec, a.cap);
-  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+  for (int t = threadIdx.x; t < a.ntiles; t += 256) cur[t] = a.toff[t] + a.hist[(size_t)t * a.nblk + blockIdx.x];
+  __syncthreads();
+  uint32_t b0, b1;
+  slice(a, n, b0, b1);
+  for (uint32_t i = b0 + threadIdx.x; i < b1; i += 256) {
     const float4 r = a.records[i];
     const int pixel = __float_as_int(r.x);
     if (pixel < 0) continue;
     const int t = tile_of(a, pixel);
-    const uint32_t at = a.toff[t] + atomicAdd(&a.tcursor[t], 1u);
+    const uint32_t at = atomicAdd(&cur[t], 1u);
     const int px = pixel % a.W, py = pixel / a.W;
     const int local = (py % kTile) * kTile + (px % kTile);
     a.binned[at] = make_float4(__int_as_float(local), r.y, r.z, r.w);
@@ -1003,9 +1051,10 @@ __global__ __launch_bounds__(256) void splat_scatter(SplatArgs a) {
 __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
   __shared__ float acc[kTile * kTile * 3];
   const int t = blockIdx.x;
+  const uint32_t b = a.toff[t], e = a.toff[t + 1];
+  if (e == b) return;
   for (int i = threadIdx.x; i < kTile * kTile * 3; i += 256) acc[i] = 0.0f;
   __syncthreads();
-  const uint32_t b = a.toff[t], e = a.toff[t + 1];
   for (uint32_t i = b + threadIdx.x; i < e; i += 256) {
     const float4 r = a.binned[i];
     const int l = __float_as_int(r.x);
@@ -1014,7 +1063,6 @@ __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
     atomicAdd(&acc[3 * l + 2], r.w);
   }
   __syncthreads();
-  if (e == b) return;
   const int tx = t % a.tilesx, ty = t / a.tilesx;
   const int l = threadIdx.x;
   const int px = tx * kTile + (l % kTile), py = ty * kTile + (l / kTile);
@@ -1156,12 +1204,12 @@ void launch_connect(const WalkArgs& A, int blocks, hipStream_t st) {
   else
     hipLaunchKernelGGL((connect_kernel<false>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
 }
-void launch_splat(const SplatArgs& a, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, st, a.tcount, (int64_t)a.ntiles);
-  hipLaunchKernelGGL(zero_u32, dim3(64), dim3(256), 0, st, a.tcursor, (int64_t)a.ntiles);
-  hipLaunchKernelGGL(splat_hist, dim3(blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(splat_scan, dim3(1), dim3(1024), 0, st, a);
-  hipLaunchKernelGGL(splat_scatter, dim3(blocks), dim3(256), 0, st, a);
+void launch_splat(const SplatArgs& a, hipStream_t st) {
+  const size_t lds = (size_t)a.ntiles * sizeof(uint32_t);
+  hipLaunchKernelGGL(splat_count, dim3(a.nblk), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(splat_scan_blocks, dim3(a.ntiles), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(splat_scan_tiles, dim3(1), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(splat_scatter, dim3(a.nblk), dim3(256), lds, st, a);
   hipLaunchKernelGGL(splat_tiles, dim3(a.ntiles), dim3(256), 0, st, a);
 }
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
