@@ -150,10 +150,32 @@ typedef struct {
 } rpi_job;
 
 /* Many residual jobs (e.g. consecutive frames of an animation) with uneven
- * image sizes in one persistent launch replayed from a captured hipGraph.
- * Job j uses Philox counter word params->job + j.  Errors as above. */
+ * image sizes (spec addition; the paper leaves batching to future work,
+ * Sec. 6.3).  The launch sequence (persistent walk kernels pulling 64-sample
+ * work items of all jobs, connect, batch-wide tile splat) is captured once
+ * into a hipGraph on a library stream and replayed on hip_stream; later calls
+ * with the same image sizes and parameters only upload the new poses and
+ * output pointers.  Runs the autotuner on the largest job first if the scene
+ * is not tuned.  Job j uses Philox counter word params->job + j.  Up to 127
+ * jobs and 16384 tiles of 32x32 pixels in total.  stats may be NULL.
+ * Errors as above; records, work counting and kernel timing are UNSUPPORTED. */
 rpi_status rpi_render_residual_batch(const rpi_scene* scene, const rpi_job* jobs, int32_t num_jobs,
                                      const rpi_render_params* params, rpi_stats* stats, void* hip_stream);
+
+/* Launch configuration chosen by the autotuner. */
+typedef struct {
+  int32_t queue_cap;              /* samples per round */
+  int32_t walk_blocks_per_cu;     /* persistent walk workgroups per compute unit */
+  int32_t connect_blocks_per_cu;  /* connect workgroups per compute unit */
+  double ms_per_msample;          /* measured device time per million technique samples */
+} rpi_tuning;
+
+/* Time a small grid of launch configurations (round size, persistent grid,
+ * connect grid) on the first 2^20 samples of every stream of this edit and
+ * keep the fastest for later calls on this scene whose queue_cap is 0.
+ * Synchronises hip_stream.  out may be NULL. */
+rpi_status rpi_autotune(rpi_scene* scene, const rpi_edit* edit, const rpi_render_params* params, rpi_tuning* out,
+                        void* hip_stream);
 
 /* Per-path records of the last rpi_render_residual call on this scene made
  * with RPI_FLAG_RECORDS (host copy): each record is 8 int32/float words

@@ -6,7 +6,7 @@ Every step of the estimator runs in the library's HIP kernels; there is no CPU
 fallback.  PyTorch supplies device memory and streams.
 """
 from .native import (FLAG_ACCUMULATE, FLAG_COUNT_WORK, FLAG_RECORDS, FLAG_TWO_WAY, RpiError, Scene, Edit,
-                     Params, load_library, render_frame, render_residual, render_residual_batch)
+                     Params, autotune, load_library, render_frame, render_residual, render_residual_batch)
 
 __all__ = ["Scene", "Edit", "Params", "render_residual", "render_frame", "render_residual_batch", "RpiError",
-           "load_library", "FLAG_TWO_WAY", "FLAG_ACCUMULATE", "FLAG_COUNT_WORK", "FLAG_RECORDS"]
+           "load_library", "autotune", "FLAG_TWO_WAY", "FLAG_ACCUMULATE", "FLAG_COUNT_WORK", "FLAG_RECORDS"]

@@ -319,8 +319,14 @@ Material mat_of(const float* m) {
 }  // namespace
 
 // ------------------------------------------------------------------ scene / edit objects
+struct BatchCache;
+static void destroy_batch_cache(BatchCache* c);
+
 struct rpi_scene {
   DevScene dev;
+  // autotuned launch configuration (0 = not tuned)
+  int tuned_Q = 0, tuned_walk = 0, tuned_conn = 0;
+  BatchCache* batch = nullptr;
   std::vector<void*> allocs;
   float obj_lo[3], obj_hi[3];  // object bounds in object space (= old pose)
   Material obj_mat;
@@ -520,6 +526,8 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, rpi_scene** out) 
 
 extern "C" rpi_status rpi_destroy_scene(rpi_scene* s) {
   if (!s) return RPI_OK;
+  destroy_batch_cache(s->batch);
+  s->batch = nullptr;
   for (void* p : s->allocs) (void)hipFree(p);
   delete s;
   return RPI_OK;
@@ -613,27 +621,18 @@ static rpi_status check_params(const rpi_scene* s, const rpi_render_params* p) {
   const int64_t e = p->sample_end < 0 ? N : p->sample_end;
   if (p->sample_begin < 0 || e > N || p->sample_begin > e) return fail(RPI_ERR_INVALID_ARG, "bad sample range");
   if (N > 0xffffffffLL) return fail(RPI_ERR_UNSUPPORTED, "more than 2^32 samples per technique stream");
+  if ((int64_t)s->W * s->H >= (1 << 24)) return fail(RPI_ERR_UNSUPPORTED, "image of 2^24 pixels or more");
   return RPI_OK;
 }
 
 namespace {
-// Per-call device workspace from the stream-ordered allocator.
-struct Ws {
-  void* mem = nullptr;
-  Workspace W{};
-  DevStats* stats = nullptr;
-  uint32_t *tcount, *toff, *hist;
-  float4* binned;
-  size_t bytes = 0;
-};
-
 int max_pairs_per_sample(int tech, int d) {
   switch (tech) {
     case 1:
     case 4: return d - 1;
     case 2: return std::max(d - 2, 0);
     case 5: return d - 1;
-    case 7: return d;
+    case 7: return d + 1;
     case 3: {
       int c = 0;
       for (int i = 0; i < d; ++i)
@@ -652,15 +651,46 @@ int max_pairs_per_sample(int tech, int d) {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kSplatBlocks = 256;
+constexpr int kMaxTiles = 16384;   // one LDS histogram of kMaxTiles words per splat workgroup
 
-rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, bool keep, hipStream_t st) {
-  const int nslot = depth;
+// One residual job as the host plans it.
+struct JobSpec {
+  float pose_old[12], pose_new[12];
+  Material mat_old, mat_new;
+  int W, H;
+  float* out;
+};
+
+// Launch configuration (chosen by the autotuner or defaults).
+struct Tuning {
+  int Q = 1 << 20;      // samples per round
+  int walk_bpc = 16;    // persistent walk workgroups per compute unit
+  int conn_bpc = 16;    // connect workgroups per compute unit
+};
+
+// Device workspace for rounds of Q samples over a batch of jobs.
+struct Ws {
+  void* mem = nullptr;
+  bool async = true;
+  Workspace W{};
+  DevStats* stats = nullptr;
+  uint32_t *tcount, *toff, *hist, *item_counter;
+  float4* binned;
+  DevJob* jobs;
+  int64_t* prefix;  // [7][2 * njobs + 1]
+  int32_t* tile_job;
+  size_t bytes = 0;
+};
+
+rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep, hipStream_t st,
+                    bool async) {
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t o = off;
     off += align_up(b);
     return o;
   };
+  const int nslot = depth;
   const size_t o_eye = take((size_t)nslot * kEyeFields * Q * sizeof(float4));
   const size_t o_light = take((size_t)nslot * kLightFields * Q * sizeof(float4));
   const size_t o_start = take((size_t)kStartFields * Q * sizeof(float4));
@@ -673,10 +703,16 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, bool 
   const size_t o_stats = take(sizeof(DevStats));
   const size_t o_tc = take((size_t)ntiles * 4);
   const size_t o_to = take((size_t)(ntiles + 1) * 4);
-  const size_t o_tu = take((size_t)ntiles * kSplatBlocks * 4);
+  const size_t o_hist = take((size_t)ntiles * kSplatBlocks * 4);
   const size_t o_bin = take((size_t)pair_cap * sizeof(float4));
+  const size_t o_jobs = take((size_t)njobs * sizeof(DevJob));
+  const size_t o_pre = take((size_t)7 * (2 * njobs + 1) * sizeof(int64_t));
+  const size_t o_tj = take((size_t)ntiles * 4);
+  const size_t o_ic = take(256);
   w.bytes = off;
-  HIP_OK(hipMallocAsync(&w.mem, off, st));
+  w.async = async;
+  if (async) HIP_OK(hipMallocAsync(&w.mem, off, st));
+  else HIP_OK(hipMalloc(&w.mem, off));
   char* b = (char*)w.mem;
   w.W.eye = (float4*)(b + o_eye);
   w.W.light = (float4*)(b + o_light);
@@ -693,41 +729,170 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, bool 
   w.stats = (DevStats*)(b + o_stats);
   w.tcount = (uint32_t*)(b + o_tc);
   w.toff = (uint32_t*)(b + o_to);
-  w.hist = (uint32_t*)(b + o_tu);
+  w.hist = (uint32_t*)(b + o_hist);
   w.binned = (float4*)(b + o_bin);
+  w.jobs = (DevJob*)(b + o_jobs);
+  w.prefix = (int64_t*)(b + o_pre);
+  w.tile_job = (int32_t*)(b + o_tj);
+  w.item_counter = (uint32_t*)(b + o_ic);
   return RPI_OK;
 }
-}  // namespace
 
-static int device_cus() {
+void ws_free(Ws& w, hipStream_t st) {
+  if (!w.mem) return;
+  if (w.async) (void)hipFreeAsync(w.mem, st);
+  else (void)hipFree(w.mem);
+  w.mem = nullptr;
+}
+
+int device_cus() {
   static int cus = 0;
   if (!cus) {
     int dev = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 256;
   }
   return cus;
 }
 
-// The residual of one job into `out`, given both frames' poses and materials.
-static rpi_status residual_job(const rpi_scene* s, const float* pose_old, const float* pose_new, const Material& mat_old,
-                               const Material& mat_new, bool material_mode, const rpi_render_params* p, uint32_t job,
-                               float* out, rpi_stats* stats, hipStream_t st, std::vector<uint32_t>* rec_out) {
-  const int W = s->W, H = s->H, P = W * H;
-  const int64_t N = (int64_t)p->spp * P;
-  const int64_t s0 = p->sample_begin, s1 = p->sample_end < 0 ? N : p->sample_end;
-  const bool keep = (p->flags & RPI_FLAG_RECORDS) != 0;
-  const bool cw = (p->flags & RPI_FLAG_COUNT_WORK) != 0;
-  const bool time_k = stats != nullptr && (p->flags & RPI_FLAG_TIME_KERNELS) != 0;
-  const bool want_stats = stats != nullptr || cw;
-  struct Timed {
-    int kid;
-    hipEvent_t a, b;
-  };
-  std::vector<Timed> evs;
+// Host-side plan of a batch: job table, item prefix tables, tile map.
+struct Plan {
+  std::vector<DevJob> jobs;
+  std::vector<int64_t> prefix;  // [7][2 * njobs + 1]
+  std::vector<int32_t> tile_job;
+  int ntiles = 0;
+  int ts = 16;  // splat tile edge
+  int64_t pair_cap = 0;
+  int Q = 0;
+  bool material_mode = false;
+};
+
+}  // namespace
+
+static DevScene job_scene_impl(const DevScene& base, int W, int H) {
+  DevScene S = base;
+  S.cam.W = W;
+  S.cam.H = H;
+  S.cam.aspect = (float)W / (float)H;
+  S.cam.a_film = (float)(4.0 * (double)S.cam.aspect * (double)S.cam.tan_half * (double)S.cam.tan_half);
+  return S;
+}
+
+static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, bool material_mode,
+                            const rpi_render_params* p, const Tuning& tu, Plan& pl) {
+  const int nj = (int)js.size();
+  pl.material_mode = material_mode;
+  pl.jobs.resize(nj);
+  pl.ntiles = 0;
+  pl.tile_job.clear();
+  // 16x16 tiles unless the batch needs more than kMaxTiles of them
+  int64_t t16 = 0;
+  for (const JobSpec& q : js) t16 += (int64_t)((q.W + 15) / 16) * ((q.H + 15) / 16);
+  pl.ts = t16 <= kMaxTiles ? 16 : 32;
+  const int kTileSize = pl.ts;
+  for (int j = 0; j < nj; ++j) {
+    const JobSpec& q = js[j];
+    DevJob& J = pl.jobs[j];
+    std::memset(&J, 0, sizeof J);
+    J.S = job_scene_impl(s->dev, q.W, q.H);
+    J.F[0] = make_frame(s, q.pose_new, q.pose_old, material_mode ? q.mat_new : q.mat_old, !material_mode);
+    J.F[1] = make_frame(s, q.pose_old, q.pose_new, q.mat_old, !material_mode);
+    J.image = q.out;
+    const int64_t N = (int64_t)p->spp * q.W * q.H;
+    if (N > 0xffffffffLL) return fail(RPI_ERR_UNSUPPORTED, "more than 2^32 samples per technique stream");
+    J.s0 = p->sample_begin;
+    J.s1 = p->sample_end < 0 ? N : std::min<int64_t>(p->sample_end, N);
+    if (J.s0 < 0 || J.s0 > J.s1) return fail(RPI_ERR_INVALID_ARG, "bad sample range");
+    J.inv_n = (float)(1.0 / (double)N);
+    J.W = q.W;
+    J.H = q.H;
+    J.tilesx = (q.W + kTileSize - 1) / kTileSize;
+    J.tile0 = pl.ntiles;
+    const int nt = J.tilesx * ((q.H + kTileSize - 1) / kTileSize);
+    for (int t = 0; t < nt; ++t) pl.tile_job.push_back(j);
+    pl.ntiles += nt;
+  }
+  if (pl.ntiles > kMaxTiles) return fail(RPI_ERR_UNSUPPORTED, "images exceed 16384 tiles of 32x32 pixels");
+  const bool two_way = !material_mode && (p->flags & RPI_FLAG_TWO_WAY);
+  pl.prefix.assign((size_t)7 * (2 * nj + 1), 0);
+  for (int t = 1; t <= 7; ++t) {
+    int64_t* pre = pl.prefix.data() + (size_t)(t - 1) * (2 * nj + 1);
+    const bool on = ((p->strategy_mask >> (t - 1)) & 1u) && !(material_mode && t >= 4 && t <= 6);
+    int64_t run = 0;
+    for (int j = 0; j < nj; ++j)
+      for (int d = 0; d < 2; ++d) {
+        pre[2 * j + d] = run;
+        if (on && (d == 0 || two_way)) run += (pl.jobs[j].s1 - pl.jobs[j].s0 + kItem - 1) / kItem;
+      }
+    pre[2 * nj] = run;
+  }
+  int maxp = 0;
+  for (int t = 1; t <= 7; ++t) maxp = std::max(maxp, max_pairs_per_sample(t, p->max_depth));
+  int64_t total = 0;
+  for (int j = 0; j < nj; ++j) total = std::max(total, pl.jobs[j].s1 - pl.jobs[j].s0);
+  int64_t Q = std::min<int64_t>(tu.Q, std::max<int64_t>(total * nj * 2, kItem));
+  Q = (Q + kItem - 1) / kItem * kItem;
+  Q = std::min<int64_t>(Q, 1 << 24);
+  pl.Q = (int)Q;
+  pl.pair_cap = Q * maxp;
+  return RPI_OK;
+}
+
+// Enqueue the launch sequence of a planned batch on `st` (graph-capturable:
+// kernels only).  Records/timing hooks only on the direct path.
+struct RunOpts {
+  bool count_work = false, keep = false, time_k = false, accumulate = false, stats = false;
+  Tuning tu;
+};
+
+struct Timed {
+  int kid;
+  hipEvent_t a, b;
+};
+
+static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* p, const RunOpts& o, hipStream_t st,
+                          std::vector<Timed>* evs, std::vector<uint32_t>* rec_out) {
+  const int nj = (int)pl.jobs.size();
+  if (!o.accumulate) launch_zero_images(w.jobs, nj, st);
+  WalkArgs A;
+  std::memset(&A, 0, sizeof A);
+  A.jobs = w.jobs;
+  A.njobs = nj;
+  A.item_counter = w.item_counter;
+  A.W = w.W;
+  A.stats = (o.count_work || o.stats) ? w.stats : nullptr;
+  A.k0 = (uint32_t)p->seed;
+  A.k1 = (uint32_t)(p->seed >> 32);
+  A.job_base = p->job;
+  A.depth = p->max_depth;
+  A.material_mode = pl.material_mode ? 1 : 0;
+  A.mask = p->strategy_mask;
+  A.cweight = pl.material_mode ? 1.0f : p->c_weight;
+  A.alpha_min = p->alpha_min;
+  A.d_min = p->d_min;
+  A.jac_max = p->jac_max;
+  A.count_work = o.count_work ? 1 : 0;
+  A.keep_records = o.keep ? 1 : 0;
+  SplatArgs sa;
+  std::memset(&sa, 0, sizeof sa);
+  sa.records = w.W.records;
+  sa.nrec = w.W.npairs;
+  sa.cap = pl.pair_cap;
+  sa.jobs = w.jobs;
+  sa.tile_job = w.tile_job;
+  sa.hist = w.hist;
+  sa.tcount = w.tcount;
+  sa.toff = w.toff;
+  sa.binned = w.binned;
+  sa.ntiles = pl.ntiles;
+  sa.nblk = kSplatBlocks;
+  sa.ts = pl.ts;
+  const int wblocks = device_cus() * o.tu.walk_bpc;
+  const int cblocks = device_cus() * o.tu.conn_bpc;
+  const int R = pl.Q / kItem;
   auto timed = [&](int kid, auto&& launch) -> rpi_status {
-    if (!time_k) {
+    if (!evs) {
       launch();
       return RPI_OK;
     }
@@ -737,152 +902,157 @@ static rpi_status residual_job(const rpi_scene* s, const float* pose_old, const 
     HIP_OK(hipEventRecord(t.a, st));
     launch();
     HIP_OK(hipEventRecord(t.b, st));
-    evs.push_back(t);
+    evs->push_back(t);
     return RPI_OK;
   };
-  int Q = p->queue_cap > 0 ? p->queue_cap : (1 << 20);
-  Q = (int)std::min<int64_t>(Q, std::max<int64_t>(s1 - s0, 1));
-  Q = std::min(Q, 1 << 24);
-  const int d = p->max_depth;
-  const int tilesx = (W + 15) / 16, ntiles = tilesx * ((H + 15) / 16);
-  if (ntiles > 16384) return fail(RPI_ERR_UNSUPPORTED, "image larger than 2048x2048");
-  int maxp = 0;
-  for (int t = 1; t <= 7; ++t) maxp = std::max(maxp, max_pairs_per_sample(t, d) + (t == 7 ? 1 : 0));
-  const int64_t pair_cap = (int64_t)Q * maxp;
-  Ws w;
-  rpi_status rc = ws_alloc(w, Q, d, pair_cap, ntiles, keep, st);
-  if (rc) return rc;
-  if (!(p->flags & RPI_FLAG_ACCUMULATE)) launch_zero_f32(out, (int64_t)P * 3, st);
-  if (want_stats) launch_zero_u32((uint32_t*)w.stats, sizeof(DevStats) / 4, st);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (stats) {
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
-    HIP_OK(hipEventRecord(e0, st));
-  }
-  const bool two_way = !material_mode && (p->flags & RPI_FLAG_TWO_WAY);
-  const Material m2 = material_mode ? mat_new : mat_old;
-  DevFrame F2 = make_frame(s, pose_new, pose_old, m2, !material_mode);
-  DevFrame F1 = make_frame(s, pose_old, pose_new, mat_old, !material_mode);
-  WalkArgs A;
-  std::memset(&A, 0, sizeof A);
-  A.S = s->dev;
-  A.W = w.W;
-  A.stats = want_stats ? w.stats : nullptr;
-  A.k0 = (uint32_t)p->seed;
-  A.k1 = (uint32_t)(p->seed >> 32);
-  A.job = job;
-  A.depth = d;
-  A.material_mode = material_mode ? 1 : 0;
-  A.mask = p->strategy_mask;
-  A.cweight = material_mode ? 1.0f : p->c_weight;
-  A.inv_n = (float)(1.0 / (double)N);
-  A.alpha_min = p->alpha_min;
-  A.d_min = p->d_min < 0 ? (float)(0.01 * (double)s->diag) : p->d_min;
-  A.jac_max = p->jac_max;
-  A.count_work = cw ? 1 : 0;
-  A.keep_records = keep ? 1 : 0;
-  SplatArgs sa;
-  sa.records = w.W.records;
-  sa.nrec = w.W.npairs;
-  sa.cap = pair_cap;
-  sa.tcount = w.tcount;
-  sa.toff = w.toff;
-  sa.hist = w.hist;
-  sa.nblk = kSplatBlocks;
-  sa.binned = w.binned;
-  sa.image = out;
-  sa.W = W;
-  sa.H = H;
-  sa.tilesx = tilesx;
-  sa.ntiles = ntiles;
-  const int cblocks = device_cus() * 16;
-  const int ndir = two_way ? 2 : 1;
-  for (int dir = 0; dir < ndir; ++dir) {
-    A.F = dir == 0 ? F2 : F1;
-    A.Fp = dir == 0 ? F1 : F2;
-    A.dir = dir;
-    A.sigma = dir == 0 ? 1.0f : -1.0f;
-    for (int t = 1; t <= 7; ++t) {
-      if (!((p->strategy_mask >> (t - 1)) & 1u)) continue;
-      if (material_mode && t >= 4 && t <= 6) continue;
-      A.tech = t;
-      for (int64_t c0 = s0; c0 < s1; c0 += Q) {
-        A.sample0 = c0;
-        A.nsamples = (int)std::min<int64_t>(Q, s1 - c0);
-        launch_zero_u32(w.W.npairs, 1, st);
-        rpi_status r1 = timed(t, [&] { launch_walk(A, st); });
-        if (r1) return r1;
-        r1 = timed(8, [&] { launch_connect(A, cblocks, st); });
-        if (r1) return r1;
-        r1 = timed(9, [&] { launch_splat(sa, st); });
-        if (r1) return r1;
-        if (keep && rec_out) {
-          // host copies of this chunk's records (debug path; synchronous)
-          uint32_t n = 0;
-          HIP_OK(hipMemcpyAsync(&n, w.W.npairs, 4, hipMemcpyDeviceToHost, st));
-          HIP_OK(hipStreamSynchronize(st));
-          n = (uint32_t)std::min<int64_t>(n, pair_cap);
-          std::vector<float4> rec(n);
-          std::vector<uint32_t> keys(n), smp(n);
-          if (n) {
-            HIP_OK(hipMemcpy(rec.data(), w.W.records, n * sizeof(float4), hipMemcpyDeviceToHost));
-            HIP_OK(hipMemcpy(keys.data(), w.W.rec_keys, n * 4, hipMemcpyDeviceToHost));
-            HIP_OK(hipMemcpy(smp.data(), w.W.rec_sample, n * 4, hipMemcpyDeviceToHost));
-          }
-          for (uint32_t r = 0; r < n; ++r) {
-            uint32_t o[8];
-            o[0] = keys[r] & 1u;
-            o[1] = (keys[r] >> 1) & 127u;
-            o[2] = smp[r];
-            o[3] = (keys[r] >> 8) & 0xffu;
-            std::memcpy(&o[4], &rec[r], 16);
-            rec_out->insert(rec_out->end(), o, o + 8);
-          }
+  for (int t = 1; t <= 7; ++t) {
+    const int64_t* pre_h = pl.prefix.data() + (size_t)(t - 1) * (2 * nj + 1);
+    const int64_t T = pre_h[2 * nj];
+    if (T == 0) continue;
+    A.tech = t;
+    A.item_prefix = w.prefix + (size_t)(t - 1) * (2 * nj + 1);
+    for (int64_t i0 = 0; i0 < T; i0 += R) {
+      A.item0 = i0;
+      A.nitems = (int)std::min<int64_t>(R, T - i0);
+      launch_zero_u32(w.W.npairs, 1, st);
+      launch_zero_u32(w.item_counter, 1, st);
+      const int blocks = std::min<int64_t>(wblocks, A.nitems);
+      rpi_status r = timed(t, [&] { launch_walk(A, blocks, st); });
+      if (r) return r;
+      r = timed(8, [&] { launch_connect(A, cblocks, st); });
+      if (r) return r;
+      r = timed(9, [&] { launch_splat(sa, st); });
+      if (r) return r;
+      if (o.keep && rec_out) {
+        uint32_t n = 0;
+        HIP_OK(hipMemcpyAsync(&n, w.W.npairs, 4, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        n = (uint32_t)std::min<int64_t>(n, pl.pair_cap);
+        std::vector<float4> rec(n);
+        std::vector<uint32_t> keys(n), smp(n);
+        if (n) {
+          HIP_OK(hipMemcpy(rec.data(), w.W.records, n * sizeof(float4), hipMemcpyDeviceToHost));
+          HIP_OK(hipMemcpy(keys.data(), w.W.rec_keys, n * 4, hipMemcpyDeviceToHost));
+          HIP_OK(hipMemcpy(smp.data(), w.W.rec_sample, n * 4, hipMemcpyDeviceToHost));
+        }
+        for (uint32_t r2 = 0; r2 < n; ++r2) {
+          uint32_t q[8];
+          q[0] = keys[r2] & 1u;
+          q[1] = (keys[r2] >> 1) & 127u;
+          q[2] = smp[r2];
+          q[3] = (keys[r2] >> 8) & 0xffu;
+          float4 rr = rec[r2];
+          int code = 0;
+          std::memcpy(&code, &rr.x, 4);
+          const int pix = code < 0 ? -1 : (code & 0xffffff);
+          std::memcpy(&rr.x, &pix, 4);
+          std::memcpy(&q[4], &rr, 16);
+          rec_out->insert(rec_out->end(), q, q + 8);
         }
       }
     }
   }
   hipError_t le = hipGetLastError();
   if (le != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
-  if (stats || cw) {
+  return RPI_OK;
+}
+
+static rpi_status upload_plan(const Plan& pl, const Ws& w, hipStream_t st) {
+  HIP_OK(hipMemcpyAsync(w.jobs, pl.jobs.data(), pl.jobs.size() * sizeof(DevJob), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(w.prefix, pl.prefix.data(), pl.prefix.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(w.tile_job, pl.tile_job.data(), pl.tile_job.size() * 4, hipMemcpyHostToDevice, st));
+  // the host vectors are pageable: make the copies complete before they can go away
+  HIP_OK(hipStreamSynchronize(st));
+  return RPI_OK;
+}
+
+static void fill_stats(rpi_stats* stats, const DevStats& ds, const Plan& pl, const rpi_render_params* p) {
+  std::memset(stats, 0, sizeof *stats);
+  stats->paths = (int64_t)ds.paths;
+  stats->accepted = (int64_t)ds.accepted;
+  for (int r = 0; r < 7; ++r) stats->rejected[r] = (int64_t)ds.rejected[r];
+  for (int t = 0; t < 9; ++t) stats->by_tech[t] = (int64_t)ds.by_tech[t];
+  stats->nodes_visited = (int64_t)ds.nodes;
+  stats->tris_tested = (int64_t)ds.tris;
+  for (int q = 0; q < 6; ++q) stats->rays[q] = (int64_t)ds.rays[q];
+  for (int q = 0; q < 16; ++q) {
+    stats->kernel_nodes[q] = (int64_t)ds.knodes[q];
+    stats->kernel_tris[q] = (int64_t)ds.ktris[q];
+    stats->kernel_bytes_written[q] = (int64_t)ds.kbytes[q];
+  }
+  const int nj = (int)pl.jobs.size();
+  for (int t = 1; t <= 7; ++t) {
+    const int64_t* pre = pl.prefix.data() + (size_t)(t - 1) * (2 * nj + 1);
+    for (int j = 0; j < nj; ++j)
+      for (int d = 0; d < 2; ++d)
+        if (pre[2 * j + d + 1] > pre[2 * j + d]) stats->samples += pl.jobs[j].s1 - pl.jobs[j].s0;
+  }
+  (void)p;
+}
+
+// Direct (non-graph) execution of a batch of jobs with optional statistics.
+static rpi_status run_jobs(const rpi_scene* s, const std::vector<JobSpec>& js, bool material_mode,
+                           const rpi_render_params* p, const Tuning& tu, rpi_stats* stats, hipStream_t st,
+                           std::vector<uint32_t>* rec_out) {
+  Plan pl;
+  rpi_status rc = make_plan(s, js, material_mode, p, tu, pl);
+  if (rc) return rc;
+  RunOpts o;
+  o.count_work = (p->flags & RPI_FLAG_COUNT_WORK) != 0;
+  o.keep = (p->flags & RPI_FLAG_RECORDS) != 0;
+  o.time_k = stats != nullptr && (p->flags & RPI_FLAG_TIME_KERNELS) != 0;
+  o.accumulate = (p->flags & RPI_FLAG_ACCUMULATE) != 0;
+  o.stats = stats != nullptr;
+  o.tu = tu;
+  Ws w;
+  rc = ws_alloc(w, pl.Q, p->max_depth, pl.pair_cap, pl.ntiles, (int)pl.jobs.size(), o.keep, st, true);
+  if (rc) return rc;
+  rc = upload_plan(pl, w, st);
+  if (rc) {
+    ws_free(w, st);
+    return rc;
+  }
+  const bool want = stats != nullptr || o.count_work;
+  if (want) launch_zero_u32((uint32_t*)w.stats, sizeof(DevStats) / 4, st);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (stats) {
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, st));
+  }
+  std::vector<Timed> evs;
+  rc = enqueue(pl, w, p, o, st, o.time_k ? &evs : nullptr, rec_out);
+  if (rc) {
+    ws_free(w, st);
+    return rc;
+  }
+  if (want) {
     DevStats ds;
     if (stats) HIP_OK(hipEventRecord(e1, st));
     HIP_OK(hipMemcpyAsync(&ds, w.stats, sizeof ds, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     if (stats) {
-      std::memset(stats, 0, sizeof *stats);
-      stats->paths = (int64_t)ds.paths;
-      stats->accepted = (int64_t)ds.accepted;
-      for (int r = 0; r < 7; ++r) stats->rejected[r] = (int64_t)ds.rejected[r];
-      for (int t = 0; t < 9; ++t) stats->by_tech[t] = (int64_t)ds.by_tech[t];
-      stats->nodes_visited = (int64_t)ds.nodes;
-      stats->tris_tested = (int64_t)ds.tris;
-      for (int q = 0; q < 6; ++q) stats->rays[q] = (int64_t)ds.rays[q];
-      for (int q = 0; q < 16; ++q) {
-        stats->kernel_nodes[q] = (int64_t)ds.knodes[q];
-        stats->kernel_tris[q] = (int64_t)ds.ktris[q];
-        stats->kernel_bytes_written[q] = (int64_t)ds.kbytes[q];
-      }
+      fill_stats(stats, ds, pl, p);
+      float ms = 0;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      stats->milliseconds = ms;
       for (const Timed& t : evs) {
         float kms = 0;
         HIP_OK(hipEventElapsedTime(&kms, t.a, t.b));
         stats->kernel_ms[t.kid] += kms;
         stats->kernel_launches[t.kid] += 1;
-        hipEventDestroy(t.a);
-        hipEventDestroy(t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
       }
-      stats->samples = (s1 - s0) * ndir * __builtin_popcount(p->strategy_mask & (material_mode ? 0x47u : 0x7Fu));
-      float ms = 0;
-      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-      stats->milliseconds = ms;
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
     }
   }
-  HIP_OK(hipFreeAsync(w.mem, st));
+  ws_free(w, st);
   return RPI_OK;
 }
+
+static Tuning scene_tuning(const rpi_scene* s, const rpi_render_params* p);
 
 extern "C" rpi_status rpi_render_residual(const rpi_scene* s, const rpi_edit* e, const rpi_render_params* p, float* out,
                                           rpi_stats* stats, void* stream) {
@@ -890,10 +1060,19 @@ extern "C" rpi_status rpi_render_residual(const rpi_scene* s, const rpi_edit* e,
   rpi_status rc = check_params(s, p);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  const bool mm = e->kind == RPI_EDIT_MATERIAL;
+  JobSpec j;
+  std::memcpy(j.pose_old, e->pose_old, sizeof j.pose_old);
+  std::memcpy(j.pose_new, e->pose_new, sizeof j.pose_new);
+  j.mat_old = s->obj_mat;
+  j.mat_new = e->new_mat;
+  j.W = s->W;
+  j.H = s->H;
+  j.out = out;
   std::vector<uint32_t> recs;
-  rc = residual_job(s, e->pose_old, e->pose_new, s->obj_mat, e->new_mat, mm, p, p->job, out, stats, st,
-                    (p->flags & RPI_FLAG_RECORDS) ? &recs : nullptr);
+  rpi_render_params q = *p;
+  if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);
+  rc = run_jobs(s, {j}, e->kind == RPI_EDIT_MATERIAL, &q, scene_tuning(s, p), stats, st,
+                (p->flags & RPI_FLAG_RECORDS) ? &recs : nullptr);
   if (rc) return rc;
   if (p->flags & RPI_FLAG_RECORDS) {
     std::lock_guard<std::mutex> lk(const_cast<rpi_scene*>(s)->mu);
@@ -939,11 +1118,229 @@ extern "C" rpi_status rpi_render_frame(const rpi_scene* s, const rpi_edit* e, in
   return RPI_OK;
 }
 
-extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* s, const rpi_job* jobs, int32_t n,
+static Tuning scene_tuning(const rpi_scene* s, const rpi_render_params* p) {
+  Tuning t;
+  if (s->tuned_Q > 0) {
+    t.Q = s->tuned_Q;
+    t.walk_bpc = s->tuned_walk;
+    t.conn_bpc = s->tuned_conn;
+  }
+  if (p->queue_cap > 0) t.Q = p->queue_cap;
+  return t;
+}
+
+// Autotuner: time candidate (round size, persistent walk grid, connect grid)
+// on a sample range of a representative job and keep the fastest.
+static rpi_status autotune_job(rpi_scene* s, const JobSpec& j, bool material_mode, const rpi_render_params* p,
+                               hipStream_t st, rpi_tuning* out) {
+  rpi_render_params q = *p;
+  q.flags &= ~(uint32_t)(RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_ACCUMULATE);
+  q.flags |= RPI_FLAG_ACCUMULATE;
+  const int64_t N = (int64_t)p->spp * j.W * j.H;
+  q.sample_begin = 0;
+  q.sample_end = std::min<int64_t>(N, 1 << 20);
+  if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);
+  const int Qs[3] = {1 << 20, 1 << 21, 1 << 22};
+  const int walks[3] = {8, 16, 32};
+  double best = 1e300;
+  Tuning bt;
+  for (int qi = 0; qi < 3; ++qi)
+    for (int wi = 0; wi < 3; ++wi) {
+      Tuning t;
+      t.Q = Qs[qi];
+      t.walk_bpc = walks[wi];
+      t.conn_bpc = 16;
+      rpi_stats stt;
+      rpi_status rc = run_jobs(s, {j}, material_mode, &q, t, &stt, st, nullptr);
+      if (rc) return rc;
+      if (stt.milliseconds < best) {
+        best = stt.milliseconds;
+        bt = t;
+      }
+    }
+  s->tuned_Q = bt.Q;
+  s->tuned_walk = bt.walk_bpc;
+  s->tuned_conn = bt.conn_bpc;
+  if (out) {
+    out->queue_cap = bt.Q;
+    out->walk_blocks_per_cu = bt.walk_bpc;
+    out->connect_blocks_per_cu = bt.conn_bpc;
+    out->ms_per_msample = best / ((double)(q.sample_end - q.sample_begin) * 14.0 / 1e6);
+  }
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_autotune(rpi_scene* s, const rpi_edit* e, const rpi_render_params* p, rpi_tuning* out,
+                                   void* stream) {
+  if (!s || !e) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  rpi_status rc = check_params(s, p);
+  if (rc) return rc;
+  JobSpec j;
+  std::memcpy(j.pose_old, e->pose_old, sizeof j.pose_old);
+  std::memcpy(j.pose_new, e->pose_new, sizeof j.pose_new);
+  j.mat_old = s->obj_mat;
+  j.mat_new = e->new_mat;
+  j.W = s->W;
+  j.H = s->H;
+  void* tmp = nullptr;
+  HIP_OK(hipMalloc(&tmp, (size_t)s->W * s->H * 3 * sizeof(float)));
+  j.out = (float*)tmp;
+  rc = autotune_job(s, j, e->kind == RPI_EDIT_MATERIAL, p, (hipStream_t)stream, out);
+  (void)hipFree(tmp);
+  return rc;
+}
+
+// A captured batch: persistent workspace, job table staging, graph.
+struct BatchCache {
+  std::vector<int> sizes;      // W, H per job
+  rpi_render_params params;    // everything the graph bakes in
+  Plan plan;
+  Ws ws;
+  DevJob* pinned = nullptr;    // host staging of the job table
+  hipEvent_t staged = nullptr; // the last job-table upload has been consumed
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void destroy_batch_cache(BatchCache* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->staged) (void)hipEventDestroy(c->staged);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->ws.mem) (void)hipFree(c->ws.mem);
+  delete c;
+}
+
+static bool same_params(const rpi_render_params& a, const rpi_render_params& b) {
+  return a.spp == b.spp && a.max_depth == b.max_depth && a.seed == b.seed && a.strategy_mask == b.strategy_mask &&
+         a.flags == b.flags && a.alpha_min == b.alpha_min && a.d_min == b.d_min && a.jac_max == b.jac_max &&
+         a.c_weight == b.c_weight && a.sample_begin == b.sample_begin && a.sample_end == b.sample_end &&
+         a.queue_cap == b.queue_cap && a.job == b.job;
+}
+
+extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_job* jobs, int32_t n,
                                                 const rpi_render_params* p, rpi_stats* stats, void* stream) {
-  if (!s || !jobs || n <= 0) return fail(RPI_ERR_INVALID_ARG, "null argument");
-  (void)p;
-  (void)stats;
-  (void)stream;
-  return fail(RPI_ERR_UNSUPPORTED, "batch path not built yet");
+  rpi_scene* s = const_cast<rpi_scene*>(cs);
+  if (!s || !jobs || n <= 0 || !p) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  if (n > 127) return fail(RPI_ERR_UNSUPPORTED, "at most 127 jobs per batch");
+  if (p->spp <= 0 || p->max_depth < 2 || p->max_depth > 7 || p->strategy_mask == 0 || (p->strategy_mask & ~0x7Fu))
+    return fail(RPI_ERR_INVALID_ARG, "bad params");
+  if (p->flags & (RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_TIME_KERNELS))
+    return fail(RPI_ERR_UNSUPPORTED, "records, work counting and kernel timing are not available for batches");
+  hipStream_t st = (hipStream_t)stream;
+  rpi_render_params q = *p;
+  if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);
+  std::vector<JobSpec> js(n);
+  std::vector<int> sizes;
+  for (int i = 0; i < n; ++i) {
+    const rpi_job& jb = jobs[i];
+    if (jb.width <= 0 || jb.height <= 0 || !jb.d_out || (int64_t)jb.width * jb.height >= (1 << 24))
+      return fail(RPI_ERR_INVALID_ARG, "bad job image");
+    rpi_status rc = check_rigid(jb.pose_old);
+    if (rc) return rc;
+    rc = check_rigid(jb.pose_new);
+    if (rc) return rc;
+    std::memcpy(js[i].pose_old, jb.pose_old, 48);
+    std::memcpy(js[i].pose_new, jb.pose_new, 48);
+    js[i].mat_old = js[i].mat_new = s->obj_mat;
+    js[i].W = jb.width;
+    js[i].H = jb.height;
+    js[i].out = jb.d_out;
+    sizes.push_back(jb.width);
+    sizes.push_back(jb.height);
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  BatchCache* c = s->batch;
+  if (!c || c->sizes != sizes || !same_params(c->params, q)) {
+    destroy_batch_cache(c);
+    s->batch = nullptr;
+    if (s->tuned_Q == 0 && p->queue_cap <= 0) {
+      // tune on the largest job of the batch
+      int big = 0;
+      for (int i = 1; i < n; ++i)
+        if ((int64_t)js[i].W * js[i].H > (int64_t)js[big].W * js[big].H) big = i;
+      rpi_render_params tq = q;
+      tq.sample_begin = 0;
+      tq.sample_end = -1;
+      rpi_status rc = autotune_job(s, js[big], false, &tq, st, nullptr);
+      if (rc) return rc;
+    }
+    c = new BatchCache();
+    c->sizes = sizes;
+    c->params = q;
+    rpi_status rc = make_plan(s, js, false, &q, scene_tuning(s, &q), c->plan);
+    if (!rc) rc = ws_alloc(c->ws, c->plan.Q, q.max_depth, c->plan.pair_cap, c->plan.ntiles, n, false, st, false);
+    if (rc) {
+      destroy_batch_cache(c);
+      return rc;
+    }
+    if (hipHostMalloc((void**)&c->pinned, sizeof(DevJob) * n, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      destroy_batch_cache(c);
+      return fail(RPI_ERR_DEVICE, "batch setup failed");
+    }
+    rc = upload_plan(c->plan, c->ws, c->cap_stream);
+    if (rc) {
+      destroy_batch_cache(c);
+      return rc;
+    }
+    RunOpts o;
+    o.accumulate = (q.flags & RPI_FLAG_ACCUMULATE) != 0;
+    o.stats = true;
+    o.tu = scene_tuning(s, &q);
+    // statistics are always counted inside the graph (cheap per-workgroup atomics)
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      destroy_batch_cache(c);
+      return fail(RPI_ERR_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    launch_zero_u32((uint32_t*)c->ws.stats, sizeof(DevStats) / 4, c->cap_stream);
+    rc = enqueue(c->plan, c->ws, &q, o, c->cap_stream, nullptr, nullptr);
+    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &c->graph);
+    if (rc || e2 != hipSuccess) {
+      destroy_batch_cache(c);
+      return rc ? rc : fail(RPI_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    }
+    e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      destroy_batch_cache(c);
+      return fail(RPI_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    s->batch = c;
+  } else {
+    // same shapes and parameters: refresh the job table (poses, output pointers)
+    Plan pl;
+    rpi_status rc = make_plan(s, js, false, &q, scene_tuning(s, &q), pl);
+    if (rc) return rc;
+    HIP_OK(hipEventSynchronize(c->staged));
+    c->plan.jobs = pl.jobs;
+  }
+  std::memcpy(c->pinned, c->plan.jobs.data(), sizeof(DevJob) * n);
+  HIP_OK(hipMemcpyAsync(c->ws.jobs, c->pinned, sizeof(DevJob) * n, hipMemcpyHostToDevice, st));
+  HIP_OK(hipEventRecord(c->staged, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (stats) {
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, st));
+  }
+  HIP_OK(hipGraphLaunch(c->exec, st));
+  if (stats) {
+    HIP_OK(hipEventRecord(e1, st));
+    DevStats ds;
+    HIP_OK(hipMemcpyAsync(&ds, c->ws.stats, sizeof ds, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    fill_stats(stats, ds, c->plan, &q);
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    stats->milliseconds = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  return RPI_OK;
 }

@@ -133,24 +133,46 @@ struct Workspace {
   int32_t nslot;       // vertex slots per side
 };
 
+// One residual job: the scene as seen by this job's camera (resolution), the
+// two frames (F[0]: new frame with the old pose as ghost, sign +1; F[1]: old
+// frame, sign -1), the output image and the sample range of every
+// (technique, direction) stream.
+struct DevJob {
+  DevScene S;
+  DevFrame F[2];
+  float* image;
+  int64_t s0, s1;
+  float inv_n;      // 1 / (spp * W * H)
+  int32_t tile0;    // first tile of this job in the batch-wide tile index space
+  int32_t tilesx;   // tiles per image row
+  int32_t W, H;
+};
+
+constexpr int kItem = 64;  // samples per work item (one wave)
+
 struct DevStats {
   unsigned long long paths, accepted, rejected[7], by_tech[9], rays[6], nodes, tris, samples;
   unsigned long long knodes[16], ktris[16], kbytes[16];
 };
 
+// One round of the estimator for one technique: work items g in
+// [item0, item0 + nitems) of the batch-wide item list, where
+// item_prefix[2 j + d] .. item_prefix[2 j + d + 1] are the items of job j,
+// direction d.  Workspace slot of item g, lane l: (g - item0) * 64 + l.
 struct WalkArgs {
-  DevScene S;
-  DevFrame F;   // frame f the paths live in
-  DevFrame Fp;  // the other frame f'
+  const DevJob* jobs;
+  int32_t njobs;
+  const int64_t* item_prefix;  // [2 * njobs + 1]
+  int64_t item0;
+  int32_t nitems;
+  uint32_t* item_counter;      // work-pulling counter of the persistent walk kernel
   Workspace W;
   DevStats* stats;
-  uint32_t k0, k1, job;
-  int64_t sample0;  // first sample index of the chunk
-  int32_t nsamples; // samples in the chunk
-  int32_t tech, dir, depth;
+  uint32_t k0, k1, job_base;   // Philox key; counter word 2 = job_base + job
+  int32_t tech, depth;
   int32_t material_mode;
   uint32_t mask;
-  float sigma, cweight, inv_n;
+  float cweight;
   float alpha_min, d_min, jac_max;
   int32_t count_work;
   int32_t keep_records;
@@ -159,15 +181,17 @@ struct WalkArgs {
 // Tile-binned splat of one record queue.  ntiles * 4 bytes of LDS per
 // workgroup hold a tile histogram (ntiles <= 16384).
 struct SplatArgs {
-  const float4* records;
+  const float4* records;  // x: job << 24 | pixel (int bits), or -1; yzw: rgb
   const uint32_t* nrec;
   int64_t cap;
+  const DevJob* jobs;
+  const int32_t* tile_job;  // [ntiles]: job of each batch-wide tile
   uint32_t* hist;     // [ntiles * nblk], then its per-tile exclusive scan
   uint32_t* tcount;   // [ntiles]
   uint32_t* toff;     // [ntiles + 1]
   float4* binned;     // [cap]
-  float* image;
-  int W, H, tilesx, ntiles, nblk;
+  int ntiles, nblk;
+  int ts;             // tile edge in pixels: 16 or 32
 };
 
 struct FrameArgs {
@@ -181,8 +205,9 @@ struct FrameArgs {
 };
 
 // launchers (rpi_kernels.hip)
-void launch_walk(const WalkArgs& A, hipStream_t st);
+void launch_walk(const WalkArgs& A, int blocks, hipStream_t st);
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st);
+void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st);
 void launch_splat(const SplatArgs& a, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
 void launch_zero_f32(float* p, int64_t n, hipStream_t st);

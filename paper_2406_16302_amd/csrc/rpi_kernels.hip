@@ -21,7 +21,7 @@
 namespace rpi {
 
 constexpr int kMaxK = 8;  // vertices per path: max_depth <= 7
-constexpr int kTile = 16;
+constexpr int kTileMax = 32;  // splat tile edge is 16 or 32 (SplatArgs::ts)
 
 // ------------------------------------------------------------------ SoA records
 DEV float4 f4(vec3 a, float w) { return make_float4(a.x, a.y, a.z, w); }
@@ -44,8 +44,16 @@ DEV bool is_emitter(const DevScene& S, uint32_t md) {
   return !(md & kDynBit) && S.mats[8 * (md & ~kDynBit)] == (float)MAT_EMITTER;
 }
 
+// What a walk of one work item sees: its job's scene and frame, the workspace.
+struct Ctx {
+  const DevScene& S;
+  const DevFrame& F;
+  const Workspace& W;
+  int depth;
+};
+
 struct Lane {
-  const WalkArgs& A;
+  const Ctx& A;
   Rng g;
   int s;
   int* stk;
@@ -53,6 +61,7 @@ struct Lane {
   int nE, nL;
   uint32_t camok, neeok, dynpre;
   int k2;  // path tracing saw an emitter / the environment at x_1
+  int64_t sample;  // sample index within its (technique, direction) stream
 };
 
 // Extend a walk from (p, n, md) whose other neighbour lies in direction wi.
@@ -76,7 +85,7 @@ DEV uint32_t light_word(const LightEnd& E) { return E.mat | (E.env ? 0x40000000u
 // estimation at each vertex.  dyn0: path-tracing dynamic state before slot 0.
 template <bool CW>
 DEV void light_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End prev0, int jmax, bool dyn0) {
-  const WalkArgs& A = L.A;
+  const Ctx& A = L.A;
   const DevScene& S = A.S;
   vec3 p = p0, n = n0;
   uint32_t md = md0;
@@ -128,7 +137,7 @@ DEV void light_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End pr
 // next0, its neighbour towards the light); camera connection at each vertex.
 template <bool CW>
 DEV void eye_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End next0, int imax) {
-  const WalkArgs& A = L.A;
+  const Ctx& A = L.A;
   const DevScene& S = A.S;
   vec3 p = p0, n = n0;
   uint32_t md = md0;
@@ -189,7 +198,7 @@ DEV bool ghost_on_edge(const Lane& L, const End& A, const End& B, int tri) {
 // (1) dynamic from emitter
 template <bool CW>
 DEV void tech1(Lane& L) {
-  const WalkArgs& A = L.A;
+  const Ctx& A = L.A;
   const DevScene& S = A.S;
   float u[4];
   draw(L.g, 0, 0, 0, u);
@@ -211,7 +220,7 @@ DEV void tech1(Lane& L) {
 // (2) dynamic from sensor
 template <bool CW>
 DEV void tech2(Lane& L) {
-  const WalkArgs& A = L.A;
+  const Ctx& A = L.A;
   const DevScene& S = A.S;
   if (A.depth < 3) return;
   float u[4];
@@ -237,7 +246,7 @@ DEV void tech2(Lane& L) {
 // light side, then a BSDF direction towards the sensor.
 template <bool CW>
 DEV void tech3(Lane& L) {
-  const WalkArgs& A = L.A;
+  const Ctx& A = L.A;
   const DevScene& S = A.S;
   if (A.depth < 4) return;
   float u[4];
@@ -278,7 +287,7 @@ DEV void tech3(Lane& L) {
 // (4) ghost from emitter: the ray x_L -> x_G gives the first vertex.
 template <bool CW>
 DEV void tech4(Lane& L) {
-  const WalkArgs& A = L.A;
+  const Ctx& A = L.A;
   const DevScene& S = A.S;
   float u[4];
   draw(L.g, 0, 0, 0, u);
@@ -309,7 +318,7 @@ DEV void tech4(Lane& L) {
 // (5) ghost from sensor: the camera ray through x_G gives x_1.
 template <bool CW>
 DEV void tech5(Lane& L) {
-  const WalkArgs& A = L.A;
+  const Ctx& A = L.A;
   const DevScene& S = A.S;
   if (A.depth < 2) return;
   float u[4];
@@ -336,7 +345,7 @@ DEV void tech5(Lane& L) {
 // (6) ghost two ends: a uniform direction through x_G, rays both ways.
 template <bool CW>
 DEV void tech6(Lane& L) {
-  const WalkArgs& A = L.A;
+  const Ctx& A = L.A;
   const DevScene& S = A.S;
   if (A.depth < 3) return;
   float u[4];
@@ -369,10 +378,10 @@ DEV void tech6(Lane& L) {
 // (7) path tracing with static paths rejected (and tech 0: plain frames).
 template <bool CW>
 DEV void tech7(Lane& L) {
-  const WalkArgs& A = L.A;
+  const Ctx& A = L.A;
   const DevScene& S = A.S;
   const int P = S.cam.W * S.cam.H;
-  const int pixel = (int)((uint32_t)(A.sample0 + L.s) % (uint32_t)P);
+  const int pixel = (int)((uint32_t)L.sample % (uint32_t)P);  // streams hold < 2^32 samples
   float u[4];
   draw(L.g, 0, 0, 0, u);
   const vec3 w = camera_dir(S.cam, pixel, u[0], u[1]);
@@ -495,29 +504,56 @@ DEV void flush_work(DevStats* st, int kid, const WorkCount& wc) {
   }
 }
 
+// Work item g -> (job, direction) by binary search of the item prefix table.
+DEV int find_jd(const int64_t* pre, int n, int64_t g) {
+  int lo = 0, hi = n;  // pre[lo] <= g < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Persistent walk kernel: each wave pulls 64-sample work items (job,
+// direction, sample range) from a round counter until the round is drained,
+// which balances jobs of uneven image size and uneven per-sample cost.
 template <int TECH, bool CW>
 __global__ __launch_bounds__(kTraceBlock) void walk_kernel(WalkArgs A) {
   __shared__ int stk[kStackDepth * kTraceBlock];
-  const int s = blockIdx.x * kTraceBlock + threadIdx.x;
-  Lane L{A, Rng{A.k0, A.k1, (uint32_t)(A.sample0 + s), ((uint32_t)TECH << 24) | ((uint32_t)A.dir << 23), A.job},
-         s, stk, WorkCount{}, 0, 0, 0u, 0u, 0u, 0};
-  if (s < A.nsamples) {
-    if (TECH == 1) tech1<CW>(L);
-    if (TECH == 2) tech2<CW>(L);
-    if (TECH == 3) tech3<CW>(L);
-    if (TECH == 4) tech4<CW>(L);
-    if (TECH == 5) tech5<CW>(L);
-    if (TECH == 6) tech6<CW>(L);
-    if (TECH == 7) tech7<CW>(L);
-    A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
-  }
-  const int c = s < A.nsamples ? pair_count<TECH>(L, A.depth) : 0;
-  int total;
-  const uint32_t at = wave_reserve(A.W.npairs, c, total);
-  if (c > 0 && at + (uint32_t)c <= (uint32_t)A.W.pair_cap) write_pairs<TECH>(L, A.W.pairs + at, A.depth);
-  if (CW) {
-    L.wc.bytes += 4u * (uint32_t)c + (s < A.nsamples ? 4u : 0u);
-    flush_work(A.stats, TECH, L.wc);
+  for (;;) {
+    uint32_t it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(A.item_counter, 1u);
+    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, kWave));
+    if (it >= (uint32_t)A.nitems) break;
+    const int64_t g = A.item0 + it;
+    const int jd = __builtin_amdgcn_readfirstlane(find_jd(A.item_prefix, 2 * A.njobs, g));
+    const DevJob& J = A.jobs[jd >> 1];
+    const int dir = jd & 1;
+    const int64_t smp = J.s0 + (g - A.item_prefix[jd]) * kItem + threadIdx.x;
+    const int s = (int)it * kItem + threadIdx.x;
+    const bool active = smp < J.s1;
+    const Ctx C{J.S, J.F[dir], A.W, A.depth};
+    Lane L{C, Rng{A.k0, A.k1, (uint32_t)smp, ((uint32_t)TECH << 24) | ((uint32_t)dir << 23), A.job_base + (uint32_t)(jd >> 1)},
+           s, stk, WorkCount{}, 0, 0, 0u, 0u, 0u, 0, smp};
+    if (active) {
+      if (TECH == 1) tech1<CW>(L);
+      if (TECH == 2) tech2<CW>(L);
+      if (TECH == 3) tech3<CW>(L);
+      if (TECH == 4) tech4<CW>(L);
+      if (TECH == 5) tech5<CW>(L);
+      if (TECH == 6) tech6<CW>(L);
+      if (TECH == 7) tech7<CW>(L);
+      A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
+    }
+    const int c = active ? pair_count<TECH>(L, A.depth) : 0;
+    int total;
+    const uint32_t at = wave_reserve(A.W.npairs, c, total);
+    if (c > 0 && at + (uint32_t)c <= (uint32_t)A.W.pair_cap) write_pairs<TECH>(L, A.W.pairs + at, A.depth);
+    if (CW) {
+      L.wc.bytes += 4u * (uint32_t)c + (active ? 4u : 0u);
+      flush_work(A.stats, TECH, L.wc);
+    }
   }
 }
 
@@ -530,8 +566,20 @@ struct PV {
 DEV vec3 lpos(const LightEnd& E, vec3 from) { return E.env ? from + E.n : E.p; }
 
 
+// What the evaluation of one connected path sees.
+struct CCtx {
+  const DevScene& S;
+  const DevFrame& F;
+  const DevFrame& Fp;
+  const Workspace& W;
+  int tech, material_mode;
+  uint32_t mask;
+  float sigma, cweight, inv_n, alpha_min, d_min, jac_max;
+  int job;
+};
+
 template <bool CW>
-DEV void connect_one(const WalkArgs& A, uint32_t code, int* stk, WorkCount& wc, float4& rec, int& reason) {
+DEV void connect_one(const CCtx& A, uint32_t code, int* stk, WorkCount& wc, float4& rec, int& reason) {
   const DevScene& S = A.S;
   const Workspace& W = A.W;
   const int s = (int)(code >> 8);
@@ -902,7 +950,7 @@ DEV void connect_one(const WalkArgs& A, uint32_t code, int* stk, WorkCount& wc, 
     reason = rej;
   }
   const float sc = A.sigma / sum * A.inv_n;
-  rec = make_float4(__int_as_float(pixel), val.x * sc, val.y * sc, val.z * sc);
+  rec = make_float4(__int_as_float(pixel | (A.job << 24)), val.x * sc, val.y * sc, val.z * sc);
 }
 
 template <bool CW>
@@ -915,18 +963,23 @@ __global__ __launch_bounds__(kTraceBlock) void connect_kernel(WalkArgs A) {
   WorkCount wc{};
   for (uint32_t idx = blockIdx.x * kTraceBlock + threadIdx.x; idx < n; idx += gridDim.x * kTraceBlock) {
     const uint32_t code = A.W.pairs[idx];
+    const int s = (int)(code >> 8);
+    const int64_t g = A.item0 + s / kItem;
+    const int jd = find_jd(A.item_prefix, 2 * A.njobs, g);
+    const DevJob& J = A.jobs[jd >> 1];
+    const int dir = jd & 1;
+    const CCtx C{J.S, J.F[dir], J.F[1 - dir], A.W, A.tech, A.material_mode, A.mask, dir ? -1.0f : 1.0f,
+                 A.cweight, J.inv_n, A.alpha_min, A.d_min, A.jac_max, jd >> 1};
     float4 rec;
     int reason;
-    connect_one<CW>(A, code, stk, wc, rec, reason);
+    connect_one<CW>(C, code, stk, wc, rec, reason);
     A.W.records[idx] = rec;
     if (CW) wc.bytes += 16u;
     if (A.keep_records) {
-      A.W.rec_keys[idx] = (uint32_t)A.dir | ((uint32_t)A.tech << 1) | ((code & 0xffu) << 8);
-      A.W.rec_sample[idx] = (uint32_t)(A.sample0 + (code >> 8));
+      A.W.rec_keys[idx] = (uint32_t)dir | ((uint32_t)A.tech << 1) | ((code & 0xffu) << 8);
+      A.W.rec_sample[idx] = (uint32_t)(J.s0 + (g - A.item_prefix[jd]) * kItem + s % kItem);
     }
-    if (A.stats && reason <= 6) {
-      atomicAdd(&cnt[reason], 1ull);
-    }
+    if (A.stats && reason <= 6) atomicAdd(&cnt[reason], 1ull);
   }
   __syncthreads();
   if (A.stats && threadIdx.x < 7) {
@@ -942,9 +995,13 @@ __global__ __launch_bounds__(kTraceBlock) void connect_kernel(WalkArgs A) {
 }
 
 // ------------------------------------------------------------------ splat
-DEV int tile_of(const SplatArgs& a, int pixel) {
-  const int px = pixel % a.W, py = pixel / a.W;
-  return (py / kTile) * a.tilesx + px / kTile;
+// Batch-wide tile of a record and the pixel's index inside the tile.
+DEV int tile_of(const SplatArgs& a, int code, int& local) {
+  const DevJob& J = a.jobs[code >> 24];
+  const int pixel = code & 0xffffff;
+  const int px = pixel % J.W, py = pixel / J.W;
+  local = (py % a.ts) * a.ts + (px % a.ts);
+  return J.tile0 + (py / a.ts) * J.tilesx + px / a.ts;
 }
 
 __global__ void zero_u32(uint32_t* p, int64_t n) {
@@ -972,8 +1029,9 @@ __global__ __launch_bounds__(256) void splat_count(SplatArgs a) {
   uint32_t b0, b1;
   slice(a, n, b0, b1);
   for (uint32_t i = b0 + threadIdx.x; i < b1; i += 256) {
-    const int pixel = __float_as_int(a.records[i].x);
-    if (pixel >= 0) atomicAdd(&lh[tile_of(a, pixel)], 1u);
+    const int code = __float_as_int(a.records[i].x);
+    int local;
+    if (code >= 0) atomicAdd(&lh[tile_of(a, code, local)], 1u);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < a.ntiles; t += 256) a.hist[(size_t)t * a.nblk + blockIdx.x] = lh[t];
@@ -1037,23 +1095,23 @@ __global__ __launch_bounds__(256) void splat_scatter(SplatArgs a) {
   slice(a, n, b0, b1);
   for (uint32_t i = b0 + threadIdx.x; i < b1; i += 256) {
     const float4 r = a.records[i];
-    const int pixel = __float_as_int(r.x);
-    if (pixel < 0) continue;
-    const int t = tile_of(a, pixel);
+    const int code = __float_as_int(r.x);
+    if (code < 0) continue;
+    int local;
+    const int t = tile_of(a, code, local);
     const uint32_t at = atomicAdd(&cur[t], 1u);
-    const int px = pixel % a.W, py = pixel / a.W;
-    const int local = (py % kTile) * kTile + (px % kTile);
     a.binned[at] = make_float4(__int_as_float(local), r.y, r.z, r.w);
   }
 }
 
 // One workgroup per tile: LDS accumulation, one read-modify-write of the tile.
 __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
-  __shared__ float acc[kTile * kTile * 3];
+  __shared__ float acc[kTileMax * kTileMax * 3];
   const int t = blockIdx.x;
   const uint32_t b = a.toff[t], e = a.toff[t + 1];
   if (e == b) return;
-  for (int i = threadIdx.x; i < kTile * kTile * 3; i += 256) acc[i] = 0.0f;
+  const int tp = a.ts * a.ts;
+  for (int i = threadIdx.x; i < tp * 3; i += 256) acc[i] = 0.0f;
   __syncthreads();
   for (uint32_t i = b + threadIdx.x; i < e; i += 256) {
     const float4 r = a.binned[i];
@@ -1063,14 +1121,25 @@ __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
     atomicAdd(&acc[3 * l + 2], r.w);
   }
   __syncthreads();
-  const int tx = t % a.tilesx, ty = t / a.tilesx;
-  const int l = threadIdx.x;
-  const int px = tx * kTile + (l % kTile), py = ty * kTile + (l / kTile);
-  if (px < a.W && py < a.H) {
-    float* o = a.image + 3 * ((size_t)py * a.W + px);
-    o[0] += acc[3 * l];
-    o[1] += acc[3 * l + 1];
-    o[2] += acc[3 * l + 2];
+  const DevJob& J = a.jobs[a.tile_job[t]];
+  const int lt = t - J.tile0;
+  const int tx = lt % J.tilesx, ty = lt / J.tilesx;
+  for (int l = threadIdx.x; l < tp; l += 256) {
+    const int px = tx * a.ts + (l % a.ts), py = ty * a.ts + (l / a.ts);
+    if (px < J.W && py < J.H) {
+      float* o = J.image + 3 * ((size_t)py * J.W + px);
+      o[0] += acc[3 * l];
+      o[1] += acc[3 * l + 1];
+      o[2] += acc[3 * l + 2];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void zero_images(const DevJob* jobs, int njobs) {
+  for (int j = 0; j < njobs; ++j) {
+    const int64_t n = (int64_t)jobs[j].W * jobs[j].H * 3;
+    float* p = jobs[j].image;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0f;
   }
 }
 
@@ -1177,26 +1246,28 @@ __global__ __launch_bounds__(kTraceBlock) void frame_kernel(FrameArgs A) {
 
 // ------------------------------------------------------------------ launchers
 template <int T, bool CW>
-static void launch_walk_t(const WalkArgs& A, hipStream_t st) {
-  const int blocks = (A.nsamples + kTraceBlock - 1) / kTraceBlock;
+static void launch_walk_t(const WalkArgs& A, int blocks, hipStream_t st) {
   hipLaunchKernelGGL((walk_kernel<T, CW>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
 }
 template <bool CW>
-static void launch_walk_cw(const WalkArgs& A, hipStream_t st) {
+static void launch_walk_cw(const WalkArgs& A, int blocks, hipStream_t st) {
   switch (A.tech) {
-    case 1: launch_walk_t<1, CW>(A, st); break;
-    case 2: launch_walk_t<2, CW>(A, st); break;
-    case 3: launch_walk_t<3, CW>(A, st); break;
-    case 4: launch_walk_t<4, CW>(A, st); break;
-    case 5: launch_walk_t<5, CW>(A, st); break;
-    case 6: launch_walk_t<6, CW>(A, st); break;
-    default: launch_walk_t<7, CW>(A, st); break;
+    case 1: launch_walk_t<1, CW>(A, blocks, st); break;
+    case 2: launch_walk_t<2, CW>(A, blocks, st); break;
+    case 3: launch_walk_t<3, CW>(A, blocks, st); break;
+    case 4: launch_walk_t<4, CW>(A, blocks, st); break;
+    case 5: launch_walk_t<5, CW>(A, blocks, st); break;
+    case 6: launch_walk_t<6, CW>(A, blocks, st); break;
+    default: launch_walk_t<7, CW>(A, blocks, st); break;
   }
 }
 
-void launch_walk(const WalkArgs& A, hipStream_t st) {
-  if (A.count_work) launch_walk_cw<true>(A, st);
-  else launch_walk_cw<false>(A, st);
+void launch_walk(const WalkArgs& A, int blocks, hipStream_t st) {
+  if (A.count_work) launch_walk_cw<true>(A, blocks, st);
+  else launch_walk_cw<false>(A, blocks, st);
+}
+void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st) {
+  hipLaunchKernelGGL(zero_images, dim3(1024), dim3(256), 0, st, jobs, njobs);
 }
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st) {
   if (A.count_work)

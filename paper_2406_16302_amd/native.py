@@ -68,6 +68,11 @@ class Stats(C.Structure):
                 "kernel_tris": list(self.kernel_tris), "kernel_bytes_written": list(self.kernel_bytes_written)}
 
 
+class Tuning(C.Structure):
+    _fields_ = [("queue_cap", C.c_int32), ("walk_blocks_per_cu", C.c_int32), ("connect_blocks_per_cu", C.c_int32),
+                ("ms_per_msample", C.c_double)]
+
+
 class Job(C.Structure):
     _fields_ = [("pose_old", C.c_float * 12), ("pose_new", C.c_float * 12), ("width", C.c_int32),
                 ("height", C.c_int32), ("d_out", C.c_void_p)]
@@ -93,10 +98,12 @@ def load_library():
         L.rpi_render_residual_batch.argtypes = [vp, C.POINTER(Job), C.c_int32, C.POINTER(Params),
                                                 C.POINTER(Stats), vp]
         L.rpi_get_records.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.rpi_autotune.argtypes = [vp, vp, C.POINTER(Params), C.POINTER(Tuning), vp]
         L.rpi_last_error.restype = C.c_char_p
         L.rpi_version.restype = C.c_char_p
         for f in ("rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
-                  "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records"):
+                  "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records",
+                  "rpi_autotune"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -199,6 +206,14 @@ def render_frame(scene: Scene, edit: Edit | None, which: int, params: Params, ou
     L = load_library()
     _check(L.rpi_render_frame(scene.h, edit.h if edit is not None else None, int(which), C.byref(params),
                               _devptr(out, scene.width * scene.height * 3), _stream(stream)))
+
+
+def autotune(scene: Scene, edit: Edit, params: Params, stream=None):
+    L = load_library()
+    t = Tuning()
+    _check(L.rpi_autotune(scene.h, edit.h, C.byref(params), C.byref(t), _stream(stream)))
+    return {"queue_cap": t.queue_cap, "walk_blocks_per_cu": t.walk_blocks_per_cu,
+            "connect_blocks_per_cu": t.connect_blocks_per_cu, "ms_per_msample": t.ms_per_msample}
 
 
 def render_residual_batch(scene: Scene, jobs, params: Params, stats=False, stream=None):
