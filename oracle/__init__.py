@@ -41,6 +41,51 @@ RECORD_DTYPE = np.dtype([("dir", "<i4"), ("tech", "<i4"), ("sample", "<u4"), ("k
                          ("val", "<f8", 3), ("mis_total", "<f8"), ("mis_tech", "<f8"),
                          ("p_gen", "<f8")])
 
+MLP_NPARAM = 11368
+
+
+def mlp_init(seed=0):
+    """He-uniform weights and zero biases (object-space input of 6, hidden 64)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((6, 64), (64, 64), (64, 64), (64, 40)):
+        lim = np.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-lim, lim, (fan_in, fan_out)).astype(np.float32).ravel())
+        parts.append(np.zeros(fan_out, np.float32))
+    p = np.concatenate(parts)
+    assert p.size == MLP_NPARAM
+    return p
+
+
+def mlp_forward(params, x, bf16=True):
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 6)
+    out = np.zeros((len(x), 40))
+    pp = np.ascontiguousarray(params, np.float32)
+    lib().orc_mlp_forward(_p(pp, C.c_float), _p(x, C.c_double), len(x), int(bf16), _p(out, C.c_double))
+    return out
+
+
+def mlp_loss_grad(params, records, bf16=True):
+    rec = np.ascontiguousarray(records, np.float32).reshape(-1, 10)
+    g = np.zeros(MLP_NPARAM)
+    pp = np.ascontiguousarray(params, np.float32)
+    loss = lib().orc_mlp_loss_grad(_p(pp, C.c_float), _p(rec, C.c_float), len(rec), int(bf16), _p(g, C.c_double))
+    return loss, g
+
+
+def vmf_pdf(raw, w):
+    r = np.ascontiguousarray(raw, np.float64)
+    ww = np.ascontiguousarray(w, np.float64)
+    return lib().orc_vmf_pdf(_p(r, C.c_double), _p(ww, C.c_double))
+
+
+def vmf_sample(raw, u0, u1, u2):
+    r = np.ascontiguousarray(raw, np.float64)
+    out = np.zeros(3, np.float32)
+    lib().orc_vmf_sample(_p(r, C.c_double), u0, u1, u2, _p(out, C.c_float))
+    return out
+
+
 STAT_NAMES = ["samples", "paths", "accepted", "r1", "r2", "r3", "r4", "r5", "r6", "zero_mis",
               "t1", "t2", "t3", "t4", "t5", "t6", "t7", "t8"]
 
@@ -70,7 +115,14 @@ def lib():
         L.orc_bsdf_sample.argtypes = [f32p, f32p, f32p, C.c_float, C.c_float, f32p]
         L.orc_render_frame.argtypes = [C.c_void_p, f32p, f32p, f32p, C.c_int, C.POINTER(Params), f64p, i64p]
         L.orc_render_residual.argtypes = [C.c_void_p, f32p, f32p, f32p, C.POINTER(Params), f64p, f64p, i64p,
-                                          C.c_void_p, C.c_int64, i64p]
+                                          C.c_void_p, C.c_int64, i64p, f32p]
+        L.orc_mlp_forward.argtypes = [f32p, f64p, C.c_int, C.c_int, f64p]
+        L.orc_mlp_loss_grad.restype = C.c_double
+        L.orc_mlp_loss_grad.argtypes = [f32p, f32p, C.c_int, C.c_int, f64p]
+        L.orc_vmf_pdf.restype = C.c_double
+        L.orc_vmf_pdf.argtypes = [f64p, f64p]
+        L.orc_vmf_sample.argtypes = [f64p, C.c_float, C.c_float, C.c_float, f32p]
+        L.orc_proposal_input.argtypes = [C.c_void_p, f32p, f32p, f64p]
         L.orc_map_check.argtypes = [C.c_void_p, f32p, f32p, C.POINTER(Params), i64p]
         _lib = L
     return _lib
@@ -159,7 +211,7 @@ class OracleScene:
     def render_residual(self, spp, depth, seed, pose_old=IDENTITY, pose_new=IDENTITY, new_mat=None,
                         material_mode=False, mask=TECH_MASK_ALL, two_way=True, alpha_min=0.2, d_min=None,
                         jac_max=10.0, c_weight=0.5, s0=0, s1=-1, threads=1, job=0, per_tech=False,
-                        records=False, rec_cap=4_000_000):
+                        records=False, rec_cap=4_000_000, mlp=None):
         pm = self._params(spp, depth, mask, two_way, seed, job, alpha_min, d_min, jac_max, c_weight, s0, s1,
                           threads, material_mode)
         img = np.zeros((self.H, self.W, 3), np.float64)
@@ -170,11 +222,12 @@ class OracleScene:
         nm = None if new_mat is None else np.ascontiguousarray(new_mat, np.float32)
         recs = np.zeros(rec_cap if records else 0, RECORD_DTYPE)
         cnt = np.zeros(1, np.int64)
+        mp = None if mlp is None else np.ascontiguousarray(mlp, np.float32)
         lib().orc_render_residual(self.h, _p(po, C.c_float), _p(pn, C.c_float),
                                   None if nm is None else _p(nm, C.c_float), C.byref(pm), _p(img, C.c_double),
                                   None if timg is None else _p(timg, C.c_double), _p(st, C.c_int64),
                                   recs.ctypes.data if records else None, rec_cap if records else 0,
-                                  _p(cnt, C.c_int64))
+                                  _p(cnt, C.c_int64), None if mp is None else _p(mp, C.c_float))
         stats = {n: int(st[i]) for i, n in enumerate(STAT_NAMES)}
         out = {"image": img, "stats": stats}
         if per_tech:

@@ -763,11 +763,241 @@ static bool supported(const Scene& S, const Frame& F, const Path& P, bool check_
   return raster(S.cam, x1) >= 0;
 }
 
+// ---------------------------------------------------------------- learned proposal
+// A small MLP maps a surface point of the object (position normalised to the
+// object's bounding box, geometric normal; object space) to a mixture of 8
+// von Mises-Fisher lobes over directions (spec addition: the paper
+// names better importance sampling of the residual integrand as future work,
+// Sec. 7).  Layers 6 -> 64 -> 64 -> 64 -> 40 with ReLU; parameters in one
+// flat vector: W1[6][64], b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
+// W4[64][40], b4[40] (row-major [in][out]).
+enum { MLP_IN = 6, MLP_H = 64, MLP_OUT = 40, MLP_LOBES = 8 };
+static const int MLP_NPARAM = 6 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 * 40 + 40;
+static const int OFF_W1 = 0, OFF_B1 = 384, OFF_W2 = 448, OFF_B2 = 4544, OFF_W3 = 4608, OFF_B3 = 8704,
+                 OFF_W4 = 8768, OFF_B4 = 11328;
+
+// Round to the nearest bfloat16 (ties to even), returned as float.
+static float bf16r(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return x;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  u &= 0xffff0000u;
+  float r;
+  std::memcpy(&r, &u, 4);
+  return r;
+}
+
+// Forward pass in fp64 arithmetic.  bf16 = true rounds weights and every
+// layer input to bfloat16 (the precision of the matrix-core kernels; biases,
+// accumulation and outputs stay wide).  acts (optional) receives the inputs
+// of the four layers for back-propagation: [6 | 64 | 64 | 64] values.
+static void mlp_forward(const float* P, const double* x, bool bf16, double* out, double* acts = nullptr) {
+  double a0[MLP_IN], a1[MLP_H], a2[MLP_H], a3[MLP_H];
+  auto w = [&](int off, int i) { return bf16 ? (double)bf16r(P[off + i]) : (double)P[off + i]; };
+  auto in = [&](double v) { return bf16 ? (double)bf16r((float)v) : v; };
+  for (int i = 0; i < MLP_IN; ++i) a0[i] = in(x[i]);
+  auto layer = [&](const double* a, int n_in, int n_out, int ow, int ob, double* z, bool relu) {
+    for (int j = 0; j < n_out; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < n_in; ++i) acc += a[i] * w(ow, i * n_out + j);
+      acc += P[ob + j];
+      z[j] = relu ? (acc > 0.0 ? acc : 0.0) : acc;
+    }
+  };
+  double z1[MLP_H], z2[MLP_H], z3[MLP_H];
+  layer(a0, MLP_IN, MLP_H, OFF_W1, OFF_B1, z1, true);
+  for (int j = 0; j < MLP_H; ++j) a1[j] = in(z1[j]);
+  layer(a1, MLP_H, MLP_H, OFF_W2, OFF_B2, z2, true);
+  for (int j = 0; j < MLP_H; ++j) a2[j] = in(z2[j]);
+  layer(a2, MLP_H, MLP_H, OFF_W3, OFF_B3, z3, true);
+  for (int j = 0; j < MLP_H; ++j) a3[j] = in(z3[j]);
+  layer(a3, MLP_H, MLP_OUT, OFF_W4, OFF_B4, out, false);
+  if (acts) {
+    std::memcpy(acts, a0, sizeof a0);
+    std::memcpy(acts + 6, a1, sizeof a1);
+    std::memcpy(acts + 70, a2, sizeof a2);
+    std::memcpy(acts + 134, a3, sizeof a3);
+  }
+}
+
+// Lobe parameters from the raw outputs (fp32, as the sampler uses them):
+// mean = normalize(raw xyz), kappa = softplus(raw) + 0.01 (<= 1e4),
+// weight = softmax over lobes.
+struct Lobes {
+  float mu[MLP_LOBES][3], kappa[MLP_LOBES], w[MLP_LOBES];
+};
+static float softplusf(float x) { return x > 20.0f ? x : std::log1p(std::exp(x)); }
+static Lobes lobes_of(const double* raw) {
+  Lobes L;
+  float mx = -INFINITY;
+  for (int l = 0; l < MLP_LOBES; ++l) mx = std::max(mx, (float)raw[5 * l + 4]);
+  float sum = 0.0f;
+  for (int l = 0; l < MLP_LOBES; ++l) {
+    float x = (float)raw[5 * l], y = (float)raw[5 * l + 1], z = (float)raw[5 * l + 2];
+    float n = std::sqrt(x * x + y * y + z * z);
+    if (!(n > 0.0f)) {
+      x = 0.0f;
+      y = 0.0f;
+      z = 1.0f;
+      n = 1.0f;
+    }
+    L.mu[l][0] = x / n;
+    L.mu[l][1] = y / n;
+    L.mu[l][2] = z / n;
+    L.kappa[l] = std::min(softplusf((float)raw[5 * l + 3]) + 0.01f, 1e4f);
+    L.w[l] = std::exp((float)raw[5 * l + 4] - mx);
+    sum += L.w[l];
+  }
+  for (int l = 0; l < MLP_LOBES; ++l) L.w[l] /= sum;
+  return L;
+}
+// vMF density on the unit sphere: kappa / (2 pi (1 - e^{-2 kappa})) exp(kappa (mu.w - 1)).
+static double vmf_pdf(const Lobes& L, D3 w) {
+  double q = 0.0;
+  for (int l = 0; l < MLP_LOBES; ++l) {
+    const double k = L.kappa[l];
+    const double c = L.mu[l][0] * w.x + L.mu[l][1] * w.y + L.mu[l][2] * w.z;
+    q += L.w[l] * k / (2.0 * PI * (-std::expm1(-2.0 * k))) * std::exp(k * (c - 1.0));
+  }
+  return q;
+}
+// Jakob 2012, numerically stable vMF sampling on S^2 (fp32: it decides hits).
+static V3 vmf_sample(const Lobes& L, float u0, float u1, float u2) {
+  int l = 0;
+  float run = 0.0f;
+  for (; l < MLP_LOBES - 1; ++l) {
+    run += L.w[l];
+    if (u0 < run) break;
+  }
+  const float k = L.kappa[l];
+  const float c = 1.0f + std::log(u1 + (1.0f - u1) * std::exp(-2.0f * k)) / k;
+  const float s = std::sqrt(std::max(0.0f, 1.0f - c * c));
+  const float ph = 2.0f * PIf * u2;
+  V3 mu = mk(L.mu[l][0], L.mu[l][1], L.mu[l][2]);
+  V3 t, b;
+  onb(mu, t, b);
+  return normalize(t * (s * std::cos(ph)) + b * (s * std::sin(ph)) + mu * c);
+}
+
+struct Proposal {
+  const float* params;  // MLP_NPARAM floats, or null (technique 8 off)
+  V3 center, inv_half;  // object-space bounding box normalisation
+};
+static void proposal_input(const Proposal& Pr, V3 p_obj, V3 n_obj, double* x) {
+  x[0] = (p_obj.x - Pr.center.x) * Pr.inv_half.x;
+  x[1] = (p_obj.y - Pr.center.y) * Pr.inv_half.y;
+  x[2] = (p_obj.z - Pr.center.z) * Pr.inv_half.z;
+  x[3] = n_obj.x;
+  x[4] = n_obj.y;
+  x[5] = n_obj.z;
+}
+static Lobes proposal_lobes(const Proposal& Pr, V3 p_obj, V3 n_obj) {
+  double x[MLP_IN], raw[MLP_OUT];
+  proposal_input(Pr, p_obj, n_obj, x);
+  mlp_forward(Pr.params, x, true, raw);
+  return lobes_of(raw);
+}
+
+// Weighted negative log-likelihood of directions (the Monte Carlo KL
+// estimator of neural importance sampling) and its gradient, fp64, for
+// records {x[6], w_obj[3], weight}.
+static double mlp_loss_grad(const float* P, const float* rec, int n, bool bf16, double* grad) {
+  std::fill(grad, grad + MLP_NPARAM, 0.0);
+  double wsum = 0.0, loss = 0.0;
+  for (int r = 0; r < n; ++r) wsum += rec[10 * r + 9];
+  if (!(wsum > 0.0)) return 0.0;
+  for (int r = 0; r < n; ++r) {
+    const float* R = rec + 10 * r;
+    const double wt = R[9] / wsum;
+    if (wt == 0.0) continue;
+    double x[MLP_IN], raw[MLP_OUT], acts[198];
+    for (int i = 0; i < 6; ++i) x[i] = R[i];
+    mlp_forward(P, x, bf16, raw, acts);
+    D3 om = dmk(R[6], R[7], R[8]);
+    // mixture terms in fp64 from the raw outputs
+    double mu[MLP_LOBES][3], nrm[MLP_LOBES], kap[MLP_LOBES], sp_d[MLP_LOBES], wl[MLP_LOBES], f[MLP_LOBES];
+    double mx = -1e300;
+    for (int l = 0; l < MLP_LOBES; ++l) mx = std::max(mx, raw[5 * l + 4]);
+    double es = 0.0;
+    for (int l = 0; l < MLP_LOBES; ++l) {
+      nrm[l] = std::sqrt(raw[5 * l] * raw[5 * l] + raw[5 * l + 1] * raw[5 * l + 1] + raw[5 * l + 2] * raw[5 * l + 2]);
+      for (int a = 0; a < 3; ++a) mu[l][a] = raw[5 * l + a] / nrm[l];
+      const double t = raw[5 * l + 3];
+      const double sp = t > 30.0 ? t : std::log1p(std::exp(t));
+      sp_d[l] = 1.0 / (1.0 + std::exp(-t));
+      kap[l] = sp + 0.01;
+      wl[l] = std::exp(raw[5 * l + 4] - mx);
+      es += wl[l];
+    }
+    double q = 0.0;
+    for (int l = 0; l < MLP_LOBES; ++l) {
+      wl[l] /= es;
+      const double k = kap[l];
+      const double c = mu[l][0] * om.x + mu[l][1] * om.y + mu[l][2] * om.z;
+      f[l] = k / (2.0 * PI * (-std::expm1(-2.0 * k))) * std::exp(k * (c - 1.0));
+      q += wl[l] * f[l];
+    }
+    loss += -wt * std::log(q);
+    // d(-log q)/d raw
+    double draw_[MLP_OUT];
+    for (int l = 0; l < MLP_LOBES; ++l) {
+      const double k = kap[l];
+      const double c = mu[l][0] * om.x + mu[l][1] * om.y + mu[l][2] * om.z;
+      const double r_l = wl[l] * f[l] / q;  // responsibility
+      // d log f / d kappa = 1/k - 2 e^{-2k}/(1 - e^{-2k}) + (c - 1)
+      const double e2 = std::exp(-2.0 * k);
+      const double dlogf_dk = 1.0 / k - 2.0 * e2 / (1.0 - e2) + (c - 1.0);
+      // d log f / d mu_raw = k (om - c mu) / |raw|
+      for (int a = 0; a < 3; ++a) {
+        const double oa = a == 0 ? om.x : a == 1 ? om.y : om.z;
+        draw_[5 * l + a] = -r_l * k * (oa - c * mu[l][a]) / nrm[l];
+      }
+      draw_[5 * l + 3] = -r_l * dlogf_dk * sp_d[l];
+      draw_[5 * l + 4] = -(r_l - wl[l]);
+    }
+    // back-propagation
+    double g3[MLP_H], g2[MLP_H], g1[MLP_H];
+    const double* a0 = acts;
+    const double* a1 = acts + 6;
+    const double* a2 = acts + 70;
+    const double* a3 = acts + 134;
+    auto w = [&](int off, int i) { return bf16 ? (double)bf16r(P[off + i]) : (double)P[off + i]; };
+    for (int j = 0; j < MLP_OUT; ++j) {
+      grad[OFF_B4 + j] += wt * draw_[j];
+      for (int i = 0; i < MLP_H; ++i) grad[OFF_W4 + i * MLP_OUT + j] += wt * a3[i] * draw_[j];
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < MLP_OUT; ++j) acc += w(OFF_W4, i * MLP_OUT + j) * draw_[j];
+      g3[i] = a3[i] > 0.0 ? acc : 0.0;
+    }
+    auto back = [&](const double* a_in, const double* g_out, int n_in, int ow, int ob, double* g_in, const double* a_prev) {
+      for (int j = 0; j < MLP_H; ++j) {
+        grad[ob + j] += wt * g_out[j];
+        for (int i = 0; i < n_in; ++i) grad[ow + i * MLP_H + j] += wt * a_in[i] * g_out[j];
+      }
+      if (g_in)
+        for (int i = 0; i < n_in; ++i) {
+          double acc = 0.0;
+          for (int j = 0; j < MLP_H; ++j) acc += w(ow, i * MLP_H + j) * g_out[j];
+          g_in[i] = a_prev[i] > 0.0 ? acc : 0.0;
+        }
+    };
+    back(a2, g3, MLP_H, OFF_W3, OFF_B3, g2, a2);
+    back(a1, g2, MLP_H, OFF_W2, OFF_B2, g1, a1);
+    back(a0, g1, MLP_IN, OFF_W1, OFF_B1, nullptr, nullptr);
+  }
+  return loss;
+}
+
 // ---------------------------------------------------------------- MIS (Sec. 4.3)
 struct MisOpts {
   uint32_t mask;   // bit t-1: technique t enabled
   bool ghosts;
   double p_dir;    // technique (6) direction pdf, uniform sphere
+  const Proposal* prop;  // technique (8): learned lobes (null: off)
+  const Frame* frame;
 };
 
 // Forward pdf a_i (1 <= i <= k-3): x_i generated from x_{i+1} by BSDF
@@ -834,6 +1064,15 @@ static MisTerms mis_terms(const Scene& S, const Frame& F, const Path& P, const M
     } else {
       if (on(3)) r.by_tech[3] += pD * pdf_cos_out(S, P, m) * prod_a(S, F, P, 1, m - 1) *
                                  prod_b(S, F, P, m + 2, k - 2) * pL;
+      if (on(8) && O.prop && O.prop->params) {
+        // technique (8): the learned lobes at x_m, evaluated in object space
+        const Pose& pose = O.frame->pose;
+        Lobes Lb = proposal_lobes(*O.prop, pose_inv_apply(pose, P.v[m].p), pose_inv_rot(pose, P.v[m].n));
+        V3 wg = normalize(P.v[m + 1].p - origin(S, P, m, m + 1));
+        D3 wo = dnorm(dd(pose_inv_rot(pose, wg)));
+        r.by_tech[8] += pD * vmf_pdf(Lb, wo) * to_area(S, P, m, m + 1) * prod_a(S, F, P, 1, m - 1) *
+                        prod_b(S, F, P, m + 2, k - 2) * pL;
+      }
     }
   }
   if (O.ghosts && k >= 3) {
@@ -1254,15 +1493,51 @@ static void tech3(const Gen& g) {
   PV l0{hl.p, hl.n, hl.mat, hl.dyn};
   g.rng.draw(0, 0, 3, u);
   Material m = vertex_material(g.S, g.F, xd.mat, xd.dyn);
+  // the sensor-side BSDF sample sees the light-side neighbour x_{m+1} as its
+  // incoming direction (vertex to vertex, as the MIS tables evaluate it)
+  const V3 wi = normalize(l0.p - xd.p);
   V3 we;
-  if (!bsdf_sample(m, xd.n, wl, u[0], u[1], we)) return;
+  if (!bsdf_sample(m, xd.n, wi, u[0], u[1], we)) return;
   V3 oe = spawn_dir(g.S, xd.p, xd.n, we);
   Hit he = closest(g.S, g.F.pose, oe, we);
   if (!he.ok || (!he.dyn && g.S.mats[he.mat].type == MAT_EMITTER)) return;
   PV e0{he.p, he.n, he.mat, he.dyn};
   D3 dl = dd(l0.p) - dd(ol), de = dd(e0.p) - dd(oe);
   double pl = ddot(dd(xd.n), dd(wl)) / PI * std::fabs(ddot(dd(l0.n), dnorm(dl))) / dlen2(dl);
-  double pe = bsdf_pdf(m, dd(xd.n), dd(wl), dd(we)) * std::fabs(ddot(dd(e0.n), dnorm(de))) / dlen2(de);
+  double pe = bsdf_pdf(m, dd(xd.n), dd(wi), dd(we)) * std::fabs(ddot(dd(e0.n), dnorm(de))) / dlen2(de);
+  two_ended(g, &xd, e0, pe, normalize(xd.p - e0.p), l0, pl, normalize(xd.p - l0.p), 1.0 / g.S.obj_area, 0);
+}
+
+// (8) Learned proposal: technique (3) with the light-side direction drawn
+// from the MLP's vMF mixture at x_D (object space) instead of the cosine lobe.
+static void tech8(const Gen& g, const Proposal& Pr) {
+  float u[4];
+  g.rng.draw(0, 0, 0, u);
+  PV xd = obj_point(g.S, g.F.pose, u);
+  if (g.depth < 4 || !Pr.params) return;
+  Lobes Lb = proposal_lobes(Pr, pose_inv_apply(g.F.pose, xd.p), pose_inv_rot(g.F.pose, xd.n));
+  g.rng.draw(0, 0, 2, u);
+  V3 wobj = vmf_sample(Lb, u[0], u[1], u[2]);
+  V3 wl = normalize(pose_rot(g.F.pose, wobj));
+  V3 ol = spawn_dir(g.S, xd.p, xd.n, wl);
+  Hit hl = closest(g.S, g.F.pose, ol, wl);
+  if (!hl.ok || (!hl.dyn && g.S.mats[hl.mat].type == MAT_EMITTER)) return;
+  PV l0{hl.p, hl.n, hl.mat, hl.dyn};
+  g.rng.draw(0, 0, 3, u);
+  Material m = vertex_material(g.S, g.F, xd.mat, xd.dyn);
+  // the sensor-side BSDF sample sees the light-side neighbour x_{m+1} as its
+  // incoming direction (vertex to vertex, as the MIS tables evaluate it)
+  const V3 wi = normalize(l0.p - xd.p);
+  V3 we;
+  if (!bsdf_sample(m, xd.n, wi, u[0], u[1], we)) return;
+  V3 oe = spawn_dir(g.S, xd.p, xd.n, we);
+  Hit he = closest(g.S, g.F.pose, oe, we);
+  if (!he.ok || (!he.dyn && g.S.mats[he.mat].type == MAT_EMITTER)) return;
+  PV e0{he.p, he.n, he.mat, he.dyn};
+  D3 dl = dd(l0.p) - dd(ol), de = dd(e0.p) - dd(oe);
+  D3 wq = dnorm(dd(pose_inv_rot(g.F.pose, normalize(l0.p - ol))));
+  double pl = vmf_pdf(Lb, wq) * std::fabs(ddot(dd(l0.n), dnorm(dl))) / dlen2(dl);
+  double pe = bsdf_pdf(m, dd(xd.n), dd(wi), dd(we)) * std::fabs(ddot(dd(e0.n), dnorm(de))) / dlen2(de);
   two_ended(g, &xd, e0, pe, normalize(xd.p - e0.p), l0, pl, normalize(xd.p - l0.p), 1.0 / g.S.obj_area, 0);
 }
 
@@ -1446,10 +1721,10 @@ struct Stats {
 
 static int n_starts_for(const Scene& S, const Frame& F, const Path& P, int tech) {
   int k = P.k, n = 0;
-  if (tech >= 1 && tech <= 3) {
+  if ((tech >= 1 && tech <= 3) || tech == 8) {
     for (int m = 1; m <= k - 2; ++m)
       if (P.v[m].dyn && ((tech == 1 && m == k - 2) || (tech == 2 && m == 1 && m != k - 2) ||
-                         (tech == 3 && m >= 2 && m <= k - 3)))
+                         ((tech == 3 || tech == 8) && m >= 2 && m <= k - 3)))
         ++n;
   } else if (tech >= 4 && tech <= 6) {
     for (int a = 0; a <= k - 2; ++a) {
@@ -1466,8 +1741,8 @@ static int n_starts_for(const Scene& S, const Frame& F, const Path& P, int tech)
 
 static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int dir, int tech, double sigma,
                            const Params& Pm, int64_t s0, int64_t s1, double N, double* img, double* tech_img,
-                           Stats& st, std::vector<Record>* recs) {
-  MisOpts O{Pm.mask, F.ghosts, 1.0 / (4.0 * PI)};
+                           Stats& st, std::vector<Record>* recs, const Proposal* prop) {
+  MisOpts O{Pm.mask, F.ghosts, 1.0 / (4.0 * PI), prop, &F};
   MapParams M{Pm.alpha_min, Pm.d_min, Pm.jac_max};
   double c = Pm.material_mode ? 1.0 : (double)Pm.c_weight;
   int P = S.cam.W * S.cam.H;
@@ -1484,6 +1759,7 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
       case 5: tech5(g); break;
       case 6: tech6(g, 1.0 / (4.0 * PI)); break;
       case 7: camera_path(g, (uint32_t)s); break;
+      case 8: tech8(g, *prop); break;
       default: break;
     }
     st.samples++;
@@ -1760,10 +2036,54 @@ int orc_render_frame(void* sp, const float* pose_old, const float* pose_new, con
 // Residual I2 - I1.  Motion edits: pose_old/pose_new are the object poses of
 // the two frames.  Material edits (pm->material_mode): new_mat replaces the
 // object's material in the new frame; the poses must coincide.
+static Proposal make_proposal(const Scene& S, const float* mlp) {
+  Proposal Pr;
+  Pr.params = mlp;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (const Tri& t : S.obj)
+    for (V3 q : {t.v0, t.v0 + t.e1, t.v0 + t.e2}) {
+      const float c[3] = {q.x, q.y, q.z};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], c[a]);
+        hi[a] = std::max(hi[a], c[a]);
+      }
+    }
+  Pr.center = mk(0.5f * (lo[0] + hi[0]), 0.5f * (lo[1] + hi[1]), 0.5f * (lo[2] + hi[2]));
+  Pr.inv_half = mk(2.0f / std::max(hi[0] - lo[0], 1e-6f), 2.0f / std::max(hi[1] - lo[1], 1e-6f),
+                   2.0f / std::max(hi[2] - lo[2], 1e-6f));
+  return Pr;
+}
+
+int orc_mlp_forward(const float* params, const double* x, int n, int bf16, double* out) {
+  for (int i = 0; i < n; ++i) mlp_forward(params, x + 6 * i, bf16 != 0, out + MLP_OUT * i);
+  return MLP_NPARAM;
+}
+double orc_mlp_loss_grad(const float* params, const float* rec, int n, int bf16, double* grad) {
+  return mlp_loss_grad(params, rec, n, bf16 != 0, grad);
+}
+double orc_vmf_pdf(const double* raw, const double* w) {
+  Lobes L = lobes_of(raw);
+  return vmf_pdf(L, dmk(w[0], w[1], w[2]));
+}
+int orc_vmf_sample(const double* raw, float u0, float u1, float u2, float* w) {
+  Lobes L = lobes_of(raw);
+  V3 v = vmf_sample(L, u0, u1, u2);
+  w[0] = v.x;
+  w[1] = v.y;
+  w[2] = v.z;
+  return 0;
+}
+int orc_proposal_input(void* sp, const float* p_obj, const float* n_obj, double* x) {
+  Proposal Pr = make_proposal(*(Scene*)sp, nullptr);
+  proposal_input(Pr, mk(p_obj[0], p_obj[1], p_obj[2]), mk(n_obj[0], n_obj[1], n_obj[2]), x);
+  return 0;
+}
+
 int orc_render_residual(void* sp, const float* pose_old, const float* pose_new, const float* new_mat,
                         const Params* pm, double* img, double* tech_img, int64_t* stats_out, Record* recs,
-                        int64_t rec_cap, int64_t* rec_count) {
+                        int64_t rec_cap, int64_t* rec_count, const float* mlp) {
   Scene& S = *(Scene*)sp;
+  const Proposal prop = make_proposal(S, mlp);
   Frame F2, F1;
   F2.pose = pose_from(pose_new);
   F1.pose = pose_from(pose_old);
@@ -1784,12 +2104,14 @@ int orc_render_residual(void* sp, const float* pose_old, const float* pose_new, 
     const Frame& F = d == 0 ? F2 : F1;
     const Frame& Fp = d == 0 ? F1 : F2;
     double sigma = d == 0 ? 1.0 : -1.0;
-    for (int t = 1; t <= 7; ++t) {
+    for (int t = 1; t <= 8; ++t) {
       if (!((pm->mask >> (t - 1)) & 1u)) continue;
       if (pm->material_mode && t >= 4 && t <= 6) continue;
+      if (t == 8 && !mlp) continue;
       parallel(pm->threads, s0, s1, P, img, tech_img, 8, st,
                [&](int64_t a, int64_t b, double* im, double* ti, Stats& s) {
-                 residual_range(S, F, Fp, d, t, sigma, *pm, a, b, (double)N, im, ti, s, want ? &rv : nullptr);
+                 residual_range(S, F, Fp, d, t, sigma, *pm, a, b, (double)N, im, ti, s, want ? &rv : nullptr,
+                                &prop);
                });
     }
   }

@@ -267,8 +267,9 @@ DEV void tech3(Lane& L) {
   if (is_emitter(S, l0md)) return;
   draw(L.g, 0, 0, 3, u);
   const Material m = vmat(S, A.F, md);
+  // the sensor-side BSDF sample sees x_{m+1} as its incoming direction
   vec3 we;
-  if (!bsdf_sample(m, n, wl, u[0], u[1], we)) return;
+  if (!bsdf_sample(m, n, unit(l0 - p), u[0], u[1], we)) return;
   const vec3 oe = spawn_dir(S, p, n, we);
   const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, oe, we, L.stk, L.wc);
   if (!he.ok) return;

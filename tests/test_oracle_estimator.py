@@ -95,10 +95,15 @@ def test_white_furnace_material_edit_closed_form(oracle_lib):
 @pytest.mark.parametrize("depth", [3, 5])
 def test_generation_pdf_equals_mis_term(oracle_lib, depth):
     cases = [(scenes.cornell_motion(width=16, height=16, depth=depth), (1, 2, 3, 5, 6, 7)),
-             (scenes.ghost_plane(open_object=True), (4, 5, 6))]
+             (scenes.ghost_plane(open_object=True), (4, 5, 6)),
+             (scenes.cornell_material(width=16, height=16, depth=depth), (1, 2, 3))]  # GGX object
     for w, techs in cases:
         o = oracle_lib.OracleScene(w.scene)
-        r = o.render_residual(4, depth, 7, pose_new=w.edit.old_to_new, records=True)
+        if w.edit.kind == scenes.EDIT_MATERIAL:
+            r = o.render_residual(4, depth, 7, material_mode=True, new_mat=w.edit.new_material, mask=0x07,
+                                  two_way=False, records=True)
+        else:
+            r = o.render_residual(4, depth, 7, pose_new=w.edit.old_to_new, records=True)
         rec = r["records"]
         assert (rec["p_gen"] <= rec["mis_tech"] * (1 + 1e-5)).all()
         for t in techs:
