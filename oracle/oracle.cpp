@@ -299,6 +299,7 @@ struct Scene {
   double light_area;
   std::vector<float> obj_cdf;
   double obj_area;
+  float obj_lo[3], obj_hi[3];  // bounding box of the object's vertices as given
   Camera cam;
   float eps;
   int ntri;
@@ -1713,6 +1714,8 @@ struct Record {
   int32_t k, pixel, reason, n_starts, pad;
   double val[3];
   double mis_total, mis_tech, p_gen;
+  // technique (3) paths: proposal training record {x[6], w_obj[3], weight}
+  double train[10];
 };
 
 struct Stats {
@@ -1737,6 +1740,23 @@ static int n_starts_for(const Scene& S, const Frame& F, const Path& P, int tech)
     n = 1;
   }
   return n;
+}
+
+// Training record of a path generated by technique (3) at x_m, m = i + 2:
+// the proposal input at x_m, the direction to x_{m+1} (from the offset
+// origin, in object space) and the path's mean absolute residual
+// contribution over its generation density -- a sample of the directional
+// distribution of residual energy at x_m that technique (8) learns.
+static void train_record(const Scene& S, const Frame& F, const Proposal& Pr, const Path& X, D3 val, double* out) {
+  const int m = X.i + 2;
+  double x[MLP_IN];
+  proposal_input(Pr, pose_inv_apply(F.pose, X.v[m].p), pose_inv_rot(F.pose, X.v[m].n), x);
+  for (int a = 0; a < MLP_IN; ++a) out[a] = x[a];
+  const V3 w = pose_inv_rot(F.pose, normalize(X.v[m + 1].p - origin(S, X, m, m + 1)));
+  out[6] = w.x;
+  out[7] = w.y;
+  out[8] = w.z;
+  out[9] = (std::fabs(val.x) + std::fabs(val.y) + std::fabs(val.z)) / 3.0 / X.p_gen;
 }
 
 static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int dir, int tech, double sigma,
@@ -1784,6 +1804,7 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
         val = fx;
         st.rejected[reason]++;
       }
+      const D3 unweighted = val;
       val = val * (sigma / mt.total / N);
       st.paths++;
       st.by_tech[tech]++;
@@ -1813,6 +1834,7 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
         r.mis_total = mt.total;
         r.mis_tech = mt.by_tech[tech];
         r.p_gen = X.p_gen;
+        if (tech == 3) train_record(S, F, *prop, X, unweighted, r.train);
         recs->push_back(r);
       }
     }
@@ -1916,6 +1938,10 @@ void* orc_scene_create(const float* pos, int nv, const int* idx, int nf, const i
                           (hi[2] - lo[2]) * (hi[2] - lo[2]));
   S->eps = (float)(1e-4 * diag);
   std::vector<double> la, oa;
+  for (int ax = 0; ax < 3; ++ax) {
+    S->obj_lo[ax] = INFINITY;
+    S->obj_hi[ax] = -INFINITY;
+  }
   for (int f = 0; f < nf; ++f) {
     Tri t;
     V3 a = mk(pos[3 * idx[3 * f]], pos[3 * idx[3 * f] + 1], pos[3 * idx[3 * f] + 2]);
@@ -1933,6 +1959,13 @@ void* orc_scene_create(const float* pos, int nv, const int* idx, int nf, const i
     if (tri_obj[f]) {
       S->obj.push_back(t);
       oa.push_back(t.area);
+      for (V3 q : {a, b, c}) {
+        const float cq[3] = {q.x, q.y, q.z};
+        for (int ax = 0; ax < 3; ++ax) {
+          S->obj_lo[ax] = std::min(S->obj_lo[ax], cq[ax]);
+          S->obj_hi[ax] = std::max(S->obj_hi[ax], cq[ax]);
+        }
+      }
     } else {
       if (S->mats[t.mat].type == MAT_EMITTER) {
         S->lights.push_back((int)S->stat.size());
@@ -2039,15 +2072,8 @@ int orc_render_frame(void* sp, const float* pose_old, const float* pose_new, con
 static Proposal make_proposal(const Scene& S, const float* mlp) {
   Proposal Pr;
   Pr.params = mlp;
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (const Tri& t : S.obj)
-    for (V3 q : {t.v0, t.v0 + t.e1, t.v0 + t.e2}) {
-      const float c[3] = {q.x, q.y, q.z};
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = std::min(lo[a], c[a]);
-        hi[a] = std::max(hi[a], c[a]);
-      }
-    }
+  const float* lo = S.obj_lo;
+  const float* hi = S.obj_hi;
   Pr.center = mk(0.5f * (lo[0] + hi[0]), 0.5f * (lo[1] + hi[1]), 0.5f * (lo[2] + hi[2]));
   Pr.inv_half = mk(2.0f / std::max(hi[0] - lo[0], 1e-6f), 2.0f / std::max(hi[1] - lo[1], 1e-6f),
                    2.0f / std::max(hi[2] - lo[2], 1e-6f));
