@@ -6,7 +6,8 @@ Every step of the estimator runs in the library's HIP kernels; there is no CPU
 fallback.  PyTorch supplies device memory and streams.
 """
 from .native import (FLAG_ACCUMULATE, FLAG_COUNT_WORK, FLAG_RECORDS, FLAG_TWO_WAY, RpiError, Scene, Edit,
-                     Params, autotune, load_library, render_frame, render_residual, render_residual_batch)
+                     Params, Proposal, autotune, load_library, render_frame, render_residual, render_residual_batch)
 
-__all__ = ["Scene", "Edit", "Params", "render_residual", "render_frame", "render_residual_batch", "RpiError",
-           "load_library", "autotune", "FLAG_TWO_WAY", "FLAG_ACCUMULATE", "FLAG_COUNT_WORK", "FLAG_RECORDS"]
+__all__ = ["Scene", "Edit", "Params", "Proposal", "render_residual", "render_frame", "render_residual_batch",
+           "RpiError", "load_library", "autotune", "FLAG_TWO_WAY", "FLAG_ACCUMULATE", "FLAG_COUNT_WORK",
+           "FLAG_RECORDS"]

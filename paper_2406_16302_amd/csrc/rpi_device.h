@@ -19,9 +19,7 @@ constexpr float kPi = 3.14159265358979323846f;
 struct Rng {
   uint32_t k0, k1, sample, hi, job;
 };
-DEV void draw(const Rng& g, uint32_t side, uint32_t bounce, uint32_t slot, float u[4]) {
-  uint32_t c0 = g.sample, c1 = g.hi | (side << 22) | (bounce << 8) | slot, c2 = g.job, c3 = 0u;
-  uint32_t k0 = g.k0, k1 = g.k1;
+DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
@@ -34,11 +32,15 @@ DEV void draw(const Rng& g, uint32_t side, uint32_t bounce, uint32_t slot, float
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
+  return make_uint4(c0, c1, c2, c3);
+}
+DEV void draw(const Rng& g, uint32_t side, uint32_t bounce, uint32_t slot, float u[4]) {
+  const uint4 x = philox(g.sample, g.hi | (side << 22) | (bounce << 8) | slot, g.job, 0u, g.k0, g.k1);
   const float s = 1.0f / 16777216.0f;
-  u[0] = (float)(c0 >> 8) * s;
-  u[1] = (float)(c1 >> 8) * s;
-  u[2] = (float)(c2 >> 8) * s;
-  u[3] = (float)(c3 >> 8) * s;
+  u[0] = (float)(x.x >> 8) * s;
+  u[1] = (float)(x.y >> 8) * s;
+  u[2] = (float)(x.z >> 8) * s;
+  u[3] = (float)(x.w >> 8) * s;
 }
 
 // ------------------------------------------------------------------ materials

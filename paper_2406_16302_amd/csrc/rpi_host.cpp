@@ -10,6 +10,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -344,6 +345,14 @@ struct rpi_edit {
   Material new_mat;
 };
 
+struct rpi_proposal {
+  MlpBufs B{};
+  void* mem = nullptr;
+  vec3 center, inv_half;  // input normalisation: the object's bounding box in object space
+  int steps = 0;          // Adam steps taken
+  MlpDev view() const { return mlp_view(B, center, inv_half); }
+};
+
 static bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
 extern "C" const char* rpi_last_error(void) { return g_err.c_str(); }
@@ -614,7 +623,9 @@ static rpi_status check_params(const rpi_scene* s, const rpi_render_params* p) {
   if (!p) return fail(RPI_ERR_INVALID_ARG, "null params");
   if (p->spp <= 0) return fail(RPI_ERR_INVALID_ARG, "spp must be positive");
   if (p->max_depth < 2 || p->max_depth > 7) return fail(RPI_ERR_INVALID_ARG, "max_depth must be in [2, 7]");
-  if (p->strategy_mask == 0 || (p->strategy_mask & ~0x7Fu)) return fail(RPI_ERR_INVALID_ARG, "strategy_mask must be a non-empty subset of bits 0..6");
+  if (p->strategy_mask == 0 || (p->strategy_mask & ~0xFFu)) return fail(RPI_ERR_INVALID_ARG, "strategy_mask must be a non-empty subset of bits 0..7");
+  if ((p->strategy_mask & 0x80u) && !p->proposal) return fail(RPI_ERR_INVALID_ARG, "technique 8 needs a proposal");
+  if (p->d_train_records && p->train_capacity < 0) return fail(RPI_ERR_INVALID_ARG, "negative train_capacity");
   if (!(p->jac_max > 1.0f) || !(p->alpha_min >= 0.0f) || !(p->c_weight > 0.0f && p->c_weight < 1.0f))
     return fail(RPI_ERR_INVALID_ARG, "bad rejection / weight parameters");
   const int64_t N = (int64_t)p->spp * s->W * s->H;
@@ -633,7 +644,8 @@ int max_pairs_per_sample(int tech, int d) {
     case 2: return std::max(d - 2, 0);
     case 5: return d - 1;
     case 7: return d + 1;
-    case 3: {
+    case 3:
+    case 8: {
       int c = 0;
       for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) c += (i + j + 4 <= d);
@@ -674,15 +686,15 @@ struct Ws {
   bool async = true;
   Workspace W{};
   DevStats* stats = nullptr;
-  uint32_t *tcount, *toff, *hist, *item_counter;
+  uint32_t *tcount, *toff, *hist, *item_counter, *train_count;
   float4* binned;
   DevJob* jobs;
-  int64_t* prefix;  // [7][2 * njobs + 1]
+  int64_t* prefix;  // [kTechs][2 * njobs + 1]
   int32_t* tile_job;
   size_t bytes = 0;
 };
 
-rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep, hipStream_t st,
+rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep, bool t8, hipStream_t st,
                     bool async) {
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -700,15 +712,17 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   const size_t o_rec = take((size_t)pair_cap * sizeof(float4));
   const size_t o_keys = keep ? take((size_t)pair_cap * 4) : 0;
   const size_t o_ks = keep ? take((size_t)pair_cap * 4) : 0;
+  const size_t o_t8 = t8 ? take((size_t)pair_cap * sizeof(float4)) : 0;
   const size_t o_stats = take(sizeof(DevStats));
   const size_t o_tc = take((size_t)ntiles * 4);
   const size_t o_to = take((size_t)(ntiles + 1) * 4);
   const size_t o_hist = take((size_t)ntiles * kSplatBlocks * 4);
   const size_t o_bin = take((size_t)pair_cap * sizeof(float4));
   const size_t o_jobs = take((size_t)njobs * sizeof(DevJob));
-  const size_t o_pre = take((size_t)7 * (2 * njobs + 1) * sizeof(int64_t));
+  const size_t o_pre = take((size_t)kTechs * (2 * njobs + 1) * sizeof(int64_t));
   const size_t o_tj = take((size_t)ntiles * 4);
   const size_t o_ic = take(256);
+  const size_t o_tc2 = take(256);
   w.bytes = off;
   w.async = async;
   if (async) HIP_OK(hipMallocAsync(&w.mem, off, st));
@@ -723,6 +737,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   w.W.records = (float4*)(b + o_rec);
   w.W.rec_keys = keep ? (uint32_t*)(b + o_keys) : nullptr;
   w.W.rec_sample = keep ? (uint32_t*)(b + o_ks) : nullptr;
+  w.W.t8q = t8 ? (float4*)(b + o_t8) : nullptr;
   w.W.Q = Q;
   w.W.pair_cap = pair_cap;
   w.W.nslot = nslot;
@@ -735,6 +750,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   w.prefix = (int64_t*)(b + o_pre);
   w.tile_job = (int32_t*)(b + o_tj);
   w.item_counter = (uint32_t*)(b + o_ic);
+  w.train_count = (uint32_t*)(b + o_tc2);
   return RPI_OK;
 }
 
@@ -759,13 +775,14 @@ int device_cus() {
 // Host-side plan of a batch: job table, item prefix tables, tile map.
 struct Plan {
   std::vector<DevJob> jobs;
-  std::vector<int64_t> prefix;  // [7][2 * njobs + 1]
+  std::vector<int64_t> prefix;  // [kTechs][2 * njobs + 1]
   std::vector<int32_t> tile_job;
   int ntiles = 0;
   int ts = 16;  // splat tile edge
   int64_t pair_cap = 0;
   int Q = 0;
   bool material_mode = false;
+  vec3 obj_center, obj_inv_half;  // training-record input normalisation
 };
 
 }  // namespace
@@ -779,10 +796,20 @@ static DevScene job_scene_impl(const DevScene& base, int W, int H) {
   return S;
 }
 
+// Proposal input normalisation: centre and inverse half-extent of the
+// object's bounding box in object space.
+static void object_normalisation(const rpi_scene* s, vec3& center, vec3& inv_half) {
+  center = v3(0.5f * (s->obj_lo[0] + s->obj_hi[0]), 0.5f * (s->obj_lo[1] + s->obj_hi[1]),
+              0.5f * (s->obj_lo[2] + s->obj_hi[2]));
+  inv_half = v3(2.0f / std::max(s->obj_hi[0] - s->obj_lo[0], 1e-6f), 2.0f / std::max(s->obj_hi[1] - s->obj_lo[1], 1e-6f),
+                2.0f / std::max(s->obj_hi[2] - s->obj_lo[2], 1e-6f));
+}
+
 static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, bool material_mode,
                             const rpi_render_params* p, const Tuning& tu, Plan& pl) {
   const int nj = (int)js.size();
   pl.material_mode = material_mode;
+  object_normalisation(s, pl.obj_center, pl.obj_inv_half);
   pl.jobs.resize(nj);
   pl.ntiles = 0;
   pl.tile_job.clear();
@@ -815,10 +842,11 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
   }
   if (pl.ntiles > kMaxTiles) return fail(RPI_ERR_UNSUPPORTED, "images exceed 16384 tiles of 32x32 pixels");
   const bool two_way = !material_mode && (p->flags & RPI_FLAG_TWO_WAY);
-  pl.prefix.assign((size_t)7 * (2 * nj + 1), 0);
-  for (int t = 1; t <= 7; ++t) {
+  pl.prefix.assign((size_t)kTechs * (2 * nj + 1), 0);
+  for (int t = 1; t <= kTechs; ++t) {
     int64_t* pre = pl.prefix.data() + (size_t)(t - 1) * (2 * nj + 1);
-    const bool on = ((p->strategy_mask >> (t - 1)) & 1u) && !(material_mode && t >= 4 && t <= 6);
+    const bool on = ((p->strategy_mask >> (t - 1)) & 1u) && !(material_mode && t >= 4 && t <= 6) &&
+                    (t != 8 || p->proposal);
     int64_t run = 0;
     for (int j = 0; j < nj; ++j)
       for (int d = 0; d < 2; ++d) {
@@ -828,7 +856,7 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
     pre[2 * nj] = run;
   }
   int maxp = 0;
-  for (int t = 1; t <= 7; ++t) maxp = std::max(maxp, max_pairs_per_sample(t, p->max_depth));
+  for (int t = 1; t <= kTechs; ++t) maxp = std::max(maxp, max_pairs_per_sample(t, p->max_depth));
   int64_t total = 0;
   for (int j = 0; j < nj; ++j) total = std::max(total, pl.jobs[j].s1 - pl.jobs[j].s0);
   int64_t Q = std::min<int64_t>(tu.Q, std::max<int64_t>(total * nj * 2, kItem));
@@ -874,6 +902,22 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
   A.jac_max = p->jac_max;
   A.count_work = o.count_work ? 1 : 0;
   A.keep_records = o.keep ? 1 : 0;
+  const bool t8 = (p->strategy_mask & 0x80u) && p->proposal;
+  if (p->proposal) A.mlp = p->proposal->view();
+  if (p->d_train_records) {
+    if (!p->proposal) {
+      // the records carry the proposal's input: normalise by the object's bounds
+      // even without a proposal attached
+      MlpDev M;
+      std::memset(&M, 0, sizeof M);
+      M.center = pl.obj_center;
+      M.inv_half = pl.obj_inv_half;
+      A.mlp = M;
+    }
+    A.train = p->d_train_records;
+    A.train_cap = p->train_capacity;
+    A.train_count = w.train_count;
+  }
   SplatArgs sa;
   std::memset(&sa, 0, sizeof sa);
   sa.records = w.W.records;
@@ -905,7 +949,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
     evs->push_back(t);
     return RPI_OK;
   };
-  for (int t = 1; t <= 7; ++t) {
+  for (int t = 1; t <= kTechs; ++t) {
     const int64_t* pre_h = pl.prefix.data() + (size_t)(t - 1) * (2 * nj + 1);
     const int64_t T = pre_h[2 * nj];
     if (T == 0) continue;
@@ -917,8 +961,12 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       launch_zero_u32(w.W.npairs, 1, st);
       launch_zero_u32(w.item_counter, 1, st);
       const int blocks = std::min<int64_t>(wblocks, A.nitems);
-      rpi_status r = timed(t, [&] { launch_walk(A, blocks, st); });
+      rpi_status r = timed(t == 8 ? 11 : t, [&] { launch_walk(A, blocks, st); });
       if (r) return r;
+      if (t8) {
+        r = timed(12, [&] { launch_proposal_pdf(A, cblocks, st); });
+        if (r) return r;
+      }
       r = timed(8, [&] { launch_connect(A, cblocks, st); });
       if (r) return r;
       r = timed(9, [&] { launch_splat(sa, st); });
@@ -981,7 +1029,7 @@ static void fill_stats(rpi_stats* stats, const DevStats& ds, const Plan& pl, con
     stats->kernel_bytes_written[q] = (int64_t)ds.kbytes[q];
   }
   const int nj = (int)pl.jobs.size();
-  for (int t = 1; t <= 7; ++t) {
+  for (int t = 1; t <= kTechs; ++t) {
     const int64_t* pre = pl.prefix.data() + (size_t)(t - 1) * (2 * nj + 1);
     for (int j = 0; j < nj; ++j)
       for (int d = 0; d < 2; ++d)
@@ -1005,7 +1053,8 @@ static rpi_status run_jobs(const rpi_scene* s, const std::vector<JobSpec>& js, b
   o.stats = stats != nullptr;
   o.tu = tu;
   Ws w;
-  rc = ws_alloc(w, pl.Q, p->max_depth, pl.pair_cap, pl.ntiles, (int)pl.jobs.size(), o.keep, st, true);
+  const bool t8 = (p->strategy_mask & 0x80u) && p->proposal;
+  rc = ws_alloc(w, pl.Q, p->max_depth, pl.pair_cap, pl.ntiles, (int)pl.jobs.size(), o.keep, t8, st, true);
   if (rc) return rc;
   rc = upload_plan(pl, w, st);
   if (rc) {
@@ -1014,6 +1063,7 @@ static rpi_status run_jobs(const rpi_scene* s, const std::vector<JobSpec>& js, b
   }
   const bool want = stats != nullptr || o.count_work;
   if (want) launch_zero_u32((uint32_t*)w.stats, sizeof(DevStats) / 4, st);
+  if (p->d_train_records) launch_zero_u32(w.train_count, 1, st);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (stats) {
     HIP_OK(hipEventCreate(&e0));
@@ -1028,11 +1078,14 @@ static rpi_status run_jobs(const rpi_scene* s, const std::vector<JobSpec>& js, b
   }
   if (want) {
     DevStats ds;
+    uint32_t ntrain = 0;
     if (stats) HIP_OK(hipEventRecord(e1, st));
     HIP_OK(hipMemcpyAsync(&ds, w.stats, sizeof ds, hipMemcpyDeviceToHost, st));
+    if (p->d_train_records) HIP_OK(hipMemcpyAsync(&ntrain, w.train_count, 4, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     if (stats) {
       fill_stats(stats, ds, pl, p);
+      stats->train_records = ntrain;
       float ms = 0;
       HIP_OK(hipEventElapsedTime(&ms, e0, e1));
       stats->milliseconds = ms;
@@ -1059,6 +1112,7 @@ extern "C" rpi_status rpi_render_residual(const rpi_scene* s, const rpi_edit* e,
   if (!s || !e || !out) return fail(RPI_ERR_INVALID_ARG, "null argument");
   rpi_status rc = check_params(s, p);
   if (rc) return rc;
+  if (p->d_train_records && !stats) return fail(RPI_ERR_INVALID_ARG, "training-record collection needs stats");
   hipStream_t st = (hipStream_t)stream;
   JobSpec j;
   std::memcpy(j.pose_old, e->pose_old, sizeof j.pose_old);
@@ -1219,7 +1273,7 @@ static bool same_params(const rpi_render_params& a, const rpi_render_params& b) 
   return a.spp == b.spp && a.max_depth == b.max_depth && a.seed == b.seed && a.strategy_mask == b.strategy_mask &&
          a.flags == b.flags && a.alpha_min == b.alpha_min && a.d_min == b.d_min && a.jac_max == b.jac_max &&
          a.c_weight == b.c_weight && a.sample_begin == b.sample_begin && a.sample_end == b.sample_end &&
-         a.queue_cap == b.queue_cap && a.job == b.job;
+         a.queue_cap == b.queue_cap && a.job == b.job && a.proposal == b.proposal;
 }
 
 extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_job* jobs, int32_t n,
@@ -1227,8 +1281,10 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
   rpi_scene* s = const_cast<rpi_scene*>(cs);
   if (!s || !jobs || n <= 0 || !p) return fail(RPI_ERR_INVALID_ARG, "null argument");
   if (n > 127) return fail(RPI_ERR_UNSUPPORTED, "at most 127 jobs per batch");
-  if (p->spp <= 0 || p->max_depth < 2 || p->max_depth > 7 || p->strategy_mask == 0 || (p->strategy_mask & ~0x7Fu))
+  if (p->spp <= 0 || p->max_depth < 2 || p->max_depth > 7 || p->strategy_mask == 0 || (p->strategy_mask & ~0xFFu) ||
+      ((p->strategy_mask & 0x80u) && !p->proposal))
     return fail(RPI_ERR_INVALID_ARG, "bad params");
+  if (p->d_train_records) return fail(RPI_ERR_UNSUPPORTED, "training-record collection is not available for batches");
   if (p->flags & (RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_TIME_KERNELS))
     return fail(RPI_ERR_UNSUPPORTED, "records, work counting and kernel timing are not available for batches");
   hipStream_t st = (hipStream_t)stream;
@@ -1273,7 +1329,9 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
     c->sizes = sizes;
     c->params = q;
     rpi_status rc = make_plan(s, js, false, &q, scene_tuning(s, &q), c->plan);
-    if (!rc) rc = ws_alloc(c->ws, c->plan.Q, q.max_depth, c->plan.pair_cap, c->plan.ntiles, n, false, st, false);
+    if (!rc)
+      rc = ws_alloc(c->ws, c->plan.Q, q.max_depth, c->plan.pair_cap, c->plan.ntiles, n, false,
+                    (q.strategy_mask & 0x80u) && q.proposal, st, false);
     if (rc) {
       destroy_batch_cache(c);
       return rc;
@@ -1342,5 +1400,136 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
+  return RPI_OK;
+}
+
+// ------------------------------------------------------------------ learned proposal
+static rpi_status upload_params(rpi_proposal* pr, const float* params) {
+  for (int i = 0; i < kMlpNParam; ++i)
+    if (!std::isfinite(params[i])) return fail(RPI_ERR_INVALID_ARG, "non-finite proposal parameter");
+  HIP_OK(hipMemcpy(pr->B.master, params, kMlpNParam * sizeof(float), hipMemcpyHostToDevice));
+  HIP_OK(hipMemset(pr->B.adam_m, 0, 2 * kMlpNParam * sizeof(float)));
+  launch_mlp_pack(pr->B, nullptr);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipDeviceSynchronize());
+  pr->steps = 0;
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_proposal_create(const rpi_scene* s, const float* params, uint64_t seed, rpi_proposal** out) {
+  if (!s || !out) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  std::unique_ptr<rpi_proposal> pr(new rpi_proposal());
+  object_normalisation(s, pr->center, pr->inv_half);
+  // masters, Adam m and v, biases (4 x 64, the last 8 padding), BF16 block
+  const size_t nf = 3 * (size_t)kMlpNParam + 256;
+  const size_t bytes = nf * sizeof(float) + (size_t)kMlpHalfElems * sizeof(uint16_t);
+  if (hipMalloc(&pr->mem, bytes) != hipSuccess) return fail(RPI_ERR_OUT_OF_MEMORY, "proposal allocation failed");
+  HIP_OK(hipMemset(pr->mem, 0, bytes));  // padding rows / columns stay zero
+  float* f = (float*)pr->mem;
+  pr->B.master = f;
+  pr->B.adam_m = f + kMlpNParam;
+  pr->B.adam_v = f + 2 * kMlpNParam;
+  pr->B.bias = f + 3 * kMlpNParam;
+  pr->B.h = (uint16_t*)(f + nf);
+  std::vector<float> init;
+  if (!params) {
+    // He-uniform weights, zero biases
+    init.assign(kMlpNParam, 0.0f);
+    std::mt19937_64 rng(seed);
+    const int fan_in[4] = {6, 64, 64, 64}, off[4] = {0, 448, 4608, 8768}, cnt[4] = {384, 4096, 4096, 2560};
+    for (int L = 0; L < 4; ++L) {
+      std::uniform_real_distribution<float> U(-std::sqrt(6.0f / fan_in[L]), std::sqrt(6.0f / fan_in[L]));
+      for (int i = 0; i < cnt[L]; ++i) init[off[L] + i] = U(rng);
+    }
+    params = init.data();
+  }
+  rpi_status rc = upload_params(pr.get(), params);
+  if (rc) {
+    (void)hipFree(pr->mem);
+    return rc;
+  }
+  *out = pr.release();
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_proposal_destroy(rpi_proposal* pr) {
+  if (!pr) return RPI_OK;
+  (void)hipDeviceSynchronize();
+  if (pr->mem) (void)hipFree(pr->mem);
+  delete pr;
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_proposal_set_weights(rpi_proposal* pr, const float* params) {
+  if (!pr || !params) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  HIP_OK(hipDeviceSynchronize());
+  return upload_params(pr, params);
+}
+
+extern "C" rpi_status rpi_proposal_get_weights(const rpi_proposal* pr, float* params) {
+  if (!pr || !params) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(params, pr->B.master, kMlpNParam * sizeof(float), hipMemcpyDeviceToHost));
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_proposal_forward(const rpi_proposal* pr, const float* x, int64_t n, float* out,
+                                          void* stream) {
+  if (!pr || (n > 0 && (!x || !out))) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  if (n < 0) return fail(RPI_ERR_INVALID_ARG, "negative row count");
+  if (n == 0) return RPI_OK;
+  launch_mlp_forward(pr->view(), x, n, out, (hipStream_t)stream);
+  HIP_OK(hipGetLastError());
+  return RPI_OK;
+}
+
+namespace {
+constexpr int kMaxGradBlocks = 1024;
+int grad_blocks(int64_t rows) { return (int)std::min<int64_t>((rows + 63) / 64, kMaxGradBlocks); }
+}  // namespace
+
+extern "C" rpi_status rpi_proposal_loss_grad(const rpi_proposal* pr, const float* rec, int64_t n, float* grad,
+                                            float* loss, void* stream) {
+  if (!pr || !rec || !grad) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  if (n < 1) return fail(RPI_ERR_INVALID_ARG, "need at least one record");
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = grad_blocks(n);
+  float* partial = nullptr;
+  HIP_OK(hipMallocAsync((void**)&partial, (size_t)blocks * kMlpPartial * sizeof(float), st));
+  launch_mlp_grad(pr->view(), rec, n, n, 0, 0u, 0u, 0u, partial, blocks, st);
+  launch_mlp_reduce(partial, blocks, grad, loss, st);
+  hipError_t le = hipGetLastError();
+  (void)hipFreeAsync(partial, st);
+  if (le != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_proposal_train(rpi_proposal* pr, const float* rec, int64_t n, const rpi_train_params* tp,
+                                        float* losses, void* stream) {
+  if (!pr || !rec || !tp) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  if (n < 1 || n > 0xffffffffLL) return fail(RPI_ERR_INVALID_ARG, "record count must be in [1, 2^32)");
+  if (tp->steps < 0 || tp->batch < 64 || tp->batch % 64 || tp->batch > (1 << 20))
+    return fail(RPI_ERR_INVALID_ARG, "batch must be a positive multiple of 64 up to 2^20");
+  if (!(tp->lr > 0.0f) || !(tp->beta1 >= 0.0f && tp->beta1 < 1.0f) || !(tp->beta2 >= 0.0f && tp->beta2 < 1.0f) ||
+      !(tp->eps > 0.0f))
+    return fail(RPI_ERR_INVALID_ARG, "bad Adam parameters");
+  if (tp->steps == 0) return RPI_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = grad_blocks(tp->batch);
+  float* partial = nullptr;
+  HIP_OK(hipMallocAsync((void**)&partial, (size_t)blocks * kMlpPartial * sizeof(float), st));
+  const MlpDev M = pr->view();
+  for (int t = 1; t <= tp->steps; ++t) {
+    const int step = pr->steps + t;
+    launch_mlp_grad(M, rec, n, tp->batch, 1, (uint32_t)tp->seed, (uint32_t)(tp->seed >> 32), (uint32_t)step, partial,
+                    blocks, st);
+    launch_mlp_adam(partial, blocks, pr->B, tp->lr, tp->beta1, tp->beta2, tp->eps, step,
+                    losses ? losses + (t - 1) : nullptr, st);
+  }
+  pr->steps += tp->steps;
+  hipError_t le = hipGetLastError();
+  (void)hipFreeAsync(partial, st);
+  if (le != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
   return RPI_OK;
 }

@@ -128,6 +128,8 @@ struct Workspace {
   float4* records;     // per queued path: pixel (int bits), rgb
   uint32_t* rec_keys;  // optional: dir | tech << 1 | pair << 8  (debug records)
   uint32_t* rec_sample;
+  float4* t8q;         // technique (8) on: per queued path, the proposal's solid-angle
+                       // density at interior vertices x_2 .. x_5 (0 where not dynamic)
   int32_t Q;           // samples per chunk
   int64_t pair_cap;
   int32_t nslot;       // vertex slots per side
@@ -149,6 +151,25 @@ struct DevJob {
 };
 
 constexpr int kItem = 64;  // samples per work item (one wave)
+constexpr int kTechs = 8;  // techniques 1..6 of Sec. 4, 7 = path tracing, 8 = learned proposal
+
+// Device view of a learned proposal (technique 8): the MLP's BF16 weights in
+// the two layouts its kernels read, FP32 biases, and the normalisation of its
+// position input to the object's bounding box in object space.
+struct MlpDev {
+  const uint16_t* wt1;  // [64][16]  layer 1 transposed ([out][in], inputs 6..15 zero)
+  const uint16_t* wt2;  // [64][64]  transposed
+  const uint16_t* wt3;  // [64][64]  transposed
+  const uint16_t* wt4;  // [48][64]  transposed (outputs 40..47 zero)
+  const uint16_t* w2;   // [64][64]  [in][out]
+  const uint16_t* w3;   // [64][64]  [in][out]
+  const uint16_t* w4;   // [64][48]  [in][out] (outputs 40..47 zero)
+  const float* b1;      // [64]
+  const float* b2;      // [64]
+  const float* b3;      // [64]
+  const float* b4;      // [48]
+  vec3 center, inv_half;
+};
 
 struct DevStats {
   unsigned long long paths, accepted, rejected[7], by_tech[9], rays[6], nodes, tris, samples;
@@ -176,6 +197,10 @@ struct WalkArgs {
   float alpha_min, d_min, jac_max;
   int32_t count_work;
   int32_t keep_records;
+  MlpDev mlp;                  // technique (8) and its MIS term (mask bit 7)
+  float* train;                // technique (3) paths -> proposal training records (or null)
+  uint32_t* train_count;
+  int64_t train_cap;
 };
 
 // Tile-binned splat of one record queue.  ntiles * 4 bytes of LDS per
@@ -212,5 +237,29 @@ void launch_splat(const SplatArgs& a, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
 void launch_zero_f32(float* p, int64_t n, hipStream_t st);
 void launch_frame(const FrameArgs& A, hipStream_t st);
+void launch_proposal_pdf(const WalkArgs& A, int blocks, hipStream_t st);
+
+// learned proposal (rpi_train.hip)
+constexpr int kMlpNParam = 11368;
+constexpr int kMlpHalfElems = 64 * 16 + 64 * 64 + 64 * 64 + 48 * 64 + 64 * 64 + 64 * 64 + 64 * 48;  // BF16 block
+constexpr int kMlpPartial = kMlpNParam + 2;  // per-block gradient partial: params, weighted loss, weight sum
+struct MlpBufs {  // one device allocation per proposal
+  float* master;  // [kMlpNParam] FP32 parameters (flat layout)
+  float* adam_m;  // [kMlpNParam]
+  float* adam_v;  // [kMlpNParam]
+  float* bias;    // b1[64] b2[64] b3[64] b4[48]
+  uint16_t* h;    // wt1 wt2 wt3 wt4 w2 w3 w4 (BF16)
+};
+MlpDev mlp_view(const MlpBufs& B, vec3 center, vec3 inv_half);
+void launch_mlp_pack(const MlpBufs& B, hipStream_t st);
+void launch_mlp_forward(const MlpDev& M, const float* x, int64_t n, float* out, hipStream_t st);
+// Gradient partials of the weighted NLL over `rows` rows into partial[blocks][kMlpPartial]
+// (zeroed here).  sampled = 0: row r is record r; else row r draws its record
+// uniformly from [0, nrec) by Philox (key k0,k1; counter (r, step)).
+void launch_mlp_grad(const MlpDev& M, const float* rec, int64_t nrec, int64_t rows, int sampled, uint32_t k0,
+                     uint32_t k1, uint32_t step, float* partial, int blocks, hipStream_t st);
+void launch_mlp_reduce(const float* partial, int blocks, float* grad, float* loss, hipStream_t st);
+void launch_mlp_adam(const float* partial, int blocks, const MlpBufs& B, float lr, float beta1, float beta2,
+                     float eps, int t, float* loss_out, hipStream_t st);
 
 }  // namespace rpi

@@ -17,6 +17,7 @@
 //                      tile once (no float atomics on the image in HBM).
 // frame_kernel renders a frame by plain path tracing (Sec. 3.1).
 #include "rpi_device.h"
+#include "rpi_mlp.h"
 
 namespace rpi {
 
@@ -285,6 +286,56 @@ DEV void tech3(Lane& L) {
   eye_walk<CW>(L, e0, e0n, e0md, ce, xd, A.depth - 4);
 }
 
+// (8) learned proposal: technique (3) with the light-side direction drawn
+// from the MLP's vMF mixture at x_D (object space) instead of the cosine
+// lobe.  Called by every lane of the wave (the MLP runs on the matrix cores
+// for the whole wave); lanes without a sample pass active = false.
+template <bool CW>
+DEV void tech8(Lane& L, bool active, const MlpDev& M, void* lds) {
+  const Ctx& A = L.A;
+  const DevScene& S = A.S;
+  float u[4];
+  vec3 p = v3(0.f, 0.f, 0.f), n = v3(0.f, 0.f, 1.f);
+  uint32_t md = 0u;
+  float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (active) {
+    draw(L.g, 0, 0, 0, u);
+    int tri;
+    object_point(S, A.F.pose, u, p, n, md, tri);
+    mlp_input(M, pose_inv_apply(A.F.pose, p), pose_inv_rot(A.F.pose, n), x);
+  }
+  if (A.depth < 4) return;  // uniform across the launch
+  const float* raw = mlp_forward_wave(M, x, lds);
+  if (!active) return;
+  draw(L.g, 0, 0, 2, u);
+  const vec3 wobj = vmf_mix_sample(raw, u[0], u[1], u[2]);
+  const vec3 wl = unit(pose_rot(A.F.pose, wobj));
+  const vec3 ol = spawn_dir(S, p, n, wl);
+  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, ol, wl, L.stk, L.wc);
+  if (!hl.ok) return;
+  vec3 l0, l0n;
+  uint32_t l0md;
+  hit_vertex(S, A.F.pose, hl, ol, wl, l0, l0n, l0md);
+  if (is_emitter(S, l0md)) return;
+  draw(L.g, 0, 0, 3, u);
+  const Material m = vmat(S, A.F, md);
+  vec3 we;
+  if (!bsdf_sample(m, n, unit(l0 - p), u[0], u[1], we)) return;
+  const vec3 oe = spawn_dir(S, p, n, we);
+  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, oe, we, L.stk, L.wc);
+  if (!he.ok) return;
+  vec3 e0, e0n;
+  uint32_t e0md;
+  hit_vertex(S, A.F.pose, he, oe, we, e0, e0n, e0md);
+  if (is_emitter(S, e0md)) return;
+  const End xd = end_surf(p, n);
+  store_mid(L, p, n, md, no_cross(), 1u);
+  const Cross ce = edge_cross<CW>(S, A.F, end_surf(e0, e0n), xd, L.stk, L.wc);
+  const Cross cl = edge_cross<CW>(S, A.F, xd, end_surf(l0, l0n), L.stk, L.wc);
+  light_walk<CW>(L, l0, l0n, l0md, cl, xd, A.depth - 4, false);
+  eye_walk<CW>(L, e0, e0n, e0md, ce, xd, A.depth - 4);
+}
+
 // (4) ghost from emitter: the ray x_L -> x_G gives the first vertex.
 template <bool CW>
 DEV void tech4(Lane& L) {
@@ -435,7 +486,7 @@ DEV int pair_count(const Lane& L, int depth) {
   } else if (TECH == 7) {
     c = __popc(L.neeok & L.dynpre) + L.k2;
   } else {
-    const int extra = TECH == 3 ? 4 : 3;
+    const int extra = (TECH == 3 || TECH == 8) ? 4 : 3;
     for (int i = 0; i < L.nE; ++i)
       if (L.camok >> i & 1u)
         for (int j = 0; j < L.nL; ++j)
@@ -457,7 +508,7 @@ DEV void write_pairs(const Lane& L, uint32_t* out, int depth) {
     for (int j = 0; j < L.nL; ++j)
       if (m >> j & 1u) out[w++] = pair_code(L.s, -1, j);
   } else {
-    const int extra = TECH == 3 ? 4 : 3;
+    const int extra = (TECH == 3 || TECH == 8) ? 4 : 3;
     for (int i = 0; i < L.nE; ++i)
       if (L.camok >> i & 1u)
         for (int j = 0; j < L.nL; ++j)
@@ -521,7 +572,8 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 // which balances jobs of uneven image size and uneven per-sample cost.
 template <int TECH, bool CW>
 __global__ __launch_bounds__(kTraceBlock) void walk_kernel(WalkArgs A) {
-  __shared__ int stk[kStackDepth * kTraceBlock];
+  __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
+  static_assert(sizeof(stk) >= kMlpLdsBytes, "one MLP pass fits the traversal stack");
   for (;;) {
     uint32_t it = 0;
     if (threadIdx.x == 0) it = atomicAdd(A.item_counter, 1u);
@@ -545,15 +597,16 @@ __global__ __launch_bounds__(kTraceBlock) void walk_kernel(WalkArgs A) {
       if (TECH == 5) tech5<CW>(L);
       if (TECH == 6) tech6<CW>(L);
       if (TECH == 7) tech7<CW>(L);
-      A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
     }
+    if (TECH == 8) tech8<CW>(L, active, A.mlp, stk);
+    if (active) A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
     const int c = active ? pair_count<TECH>(L, A.depth) : 0;
     int total;
     const uint32_t at = wave_reserve(A.W.npairs, c, total);
     if (c > 0 && at + (uint32_t)c <= (uint32_t)A.W.pair_cap) write_pairs<TECH>(L, A.W.pairs + at, A.depth);
     if (CW) {
       L.wc.bytes += 4u * (uint32_t)c + (active ? 4u : 0u);
-      flush_work(A.stats, TECH, L.wc);
+      flush_work(A.stats, TECH == 8 ? 11 : TECH, L.wc);
     }
   }
 }
@@ -567,6 +620,32 @@ struct PV {
 DEV vec3 lpos(const LightEnd& E, vec3 from) { return E.env ? from + E.n : E.p; }
 
 
+// Path vertex q (1 <= q <= number of scattering vertices) of connected path
+// (s, i, j): eye slots i..0, then the start vertex x_D (techniques 2, 3, 8),
+// then light slots 0..j.
+DEV PV path_vertex(const Workspace& W, int s, int i, bool mid, int q) {
+  float4 a, b;
+  if (q <= i + 1) {
+    a = EYE(W, i + 1 - q, 0, s);
+    b = EYE(W, i + 1 - q, 1, s);
+  } else if (mid && q == i + 2) {
+    a = STA(W, 0, s);
+    b = STA(W, 1, s);
+  } else {
+    const int bb = q - (i + 1) - (mid ? 1 : 0) - 1;
+    a = LIT(W, bb, 0, s);
+    b = LIT(W, bb, 1, s);
+  }
+  return PV{xyz(a), xyz(b), __float_as_uint(a.w)};
+}
+DEV bool has_mid(int tech) { return tech == 2 || tech == 3 || tech == 8; }
+
+// Proposal training record of a technique-(3) path: the MLP input at x_D, the
+// light-side direction in object space, and |residual contribution| / p_gen.
+struct TrainRec {
+  float x[6], w[3], weight;
+};
+
 // What the evaluation of one connected path sees.
 struct CCtx {
   const DevScene& S;
@@ -577,21 +656,25 @@ struct CCtx {
   uint32_t mask;
   float sigma, cweight, inv_n, alpha_min, d_min, jac_max;
   int job;
+  const MlpDev* mlp;  // training-record input normalisation (collection on), else null
 };
 
+// q8: the proposal's densities at x_2..x_5 (technique (8) in the mask).
 template <bool CW>
-DEV void connect_one(const CCtx& A, uint32_t code, int* stk, WorkCount& wc, float4& rec, int& reason) {
+DEV void connect_one(const CCtx& A, uint32_t code, float4 q8, int* stk, WorkCount& wc, float4& rec, int& reason,
+                     TrainRec& tr) {
   const DevScene& S = A.S;
   const Workspace& W = A.W;
   const int s = (int)(code >> 8);
   const int i = (int)((code >> 4) & 15u) - 1;
   const int j = (int)(code & 15u) - 1;
   const int T = A.tech;
-  const bool mid = (T == 2 || T == 3);
+  const bool mid = has_mid(T);
   const int nsc = (i + 1) + (mid ? 1 : 0) + (j + 1);  // scattering vertices
   const int k = nsc + 2;
   reason = 0;
   rec = make_float4(__int_as_float(-1), 0.f, 0.f, 0.f);
+  tr.weight = 0.0f;
 
   // ---- assemble x_0 .. x_{k-1}
   PV v[kMaxK];
@@ -600,19 +683,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, int* stk, WorkCount& wc, floa
 #pragma unroll
   for (int q = 1; q < kMaxK - 1; ++q) {
     if (q > nsc) break;
-    float4 a, b;
-    if (q <= i + 1) {
-      a = EYE(W, i + 1 - q, 0, s);
-      b = EYE(W, i + 1 - q, 1, s);
-    } else if (mid && q == i + 2) {
-      a = STA(W, 0, s);
-      b = STA(W, 1, s);
-    } else {
-      const int bb = q - (i + 1) - (mid ? 1 : 0) - 1;
-      a = LIT(W, bb, 0, s);
-      b = LIT(W, bb, 1, s);
-    }
-    v[q] = PV{xyz(a), xyz(b), __float_as_uint(a.w)};
+    v[q] = path_vertex(W, s, i, mid, q);
   }
   LightEnd E;
   {
@@ -779,6 +850,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, int* stk, WorkCount& wc, floa
   for (int q = kMaxK - 2; q >= 2; --q) Bsuf[q] = (q <= k - 2) ? Bsuf[q + 1] * gen(q - 1, q, q - 2) : 1.0f;
   auto on = [&](int t) { return (A.mask >> (t - 1)) & 1u; };
   float sum = 0.0f;
+  float pgen3 = 0.0f;  // technique (3): density of the generating strategy
   if (on(7)) sum += k == 2 ? pcam : pcam * Bsuf[2] * pL;
 #pragma unroll
   for (int m = 1; m < kMaxK - 1; ++m) {
@@ -787,11 +859,17 @@ DEV void connect_one(const CCtx& A, uint32_t code, int* stk, WorkCount& wc, floa
       if (on(1)) sum += pL * pD * Apre[m - 1];
     } else if (m == 1) {
       if (on(2) && k >= 4) sum += pD * Bsuf[2] * pL;
-    } else if (on(3)) {
+    } else if (on(3) || on(8)) {
       const vec3 o = origin(m, m + 1);
       const vec3 w = unit(v[m + 1].p - o);
+      const float rest3 = to_area(m, m + 1, o) * Apre[m - 1] * Bsuf[m + 2] * pL;
       const float c = dot(v[m].n, w);
-      if (c > 0.0f) sum += pD * (c / kPi) * to_area(m, m + 1, o) * Apre[m - 1] * Bsuf[m + 2] * pL;
+      if (on(3) && c > 0.0f) {
+        const float t3 = pD * (c / kPi) * rest3;
+        sum += t3;
+        if (T == 3 && m == i + 2) pgen3 = t3;
+      }
+      if (on(8)) sum += pD * (m == 2 ? q8.x : m == 3 ? q8.y : m == 4 ? q8.z : q8.w) * rest3;
     }
   }
   if (motion && k >= 3) {
@@ -952,35 +1030,68 @@ DEV void connect_one(const CCtx& A, uint32_t code, int* stk, WorkCount& wc, floa
   }
   const float sc = A.sigma / sum * A.inv_n;
   rec = make_float4(__int_as_float(pixel | (A.job << 24)), val.x * sc, val.y * sc, val.z * sc);
+  if (A.mlp && T == 3 && pgen3 > 0.0f) {
+    const int m = i + 2;
+    const vec3 o = origin(m, m + 1);
+    const vec3 w = pose_inv_rot(A.F.pose, unit(v[m + 1].p - o));
+    mlp_input(*A.mlp, pose_inv_apply(A.F.pose, v[m].p), pose_inv_rot(A.F.pose, v[m].n), tr.x);
+    tr.w[0] = w.x;
+    tr.w[1] = w.y;
+    tr.w[2] = w.z;
+    tr.weight = (fabsf(val.x) + fabsf(val.y) + fabsf(val.z)) * (1.0f / 3.0f) / pgen3;
+  }
 }
 
 template <bool CW>
 __global__ __launch_bounds__(kTraceBlock) void connect_kernel(WalkArgs A) {
-  __shared__ int stk[kStackDepth * kTraceBlock];
+  __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   __shared__ unsigned long long cnt[16];
   if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t n = min((uint32_t)A.W.pair_cap, *A.W.npairs);
   WorkCount wc{};
-  for (uint32_t idx = blockIdx.x * kTraceBlock + threadIdx.x; idx < n; idx += gridDim.x * kTraceBlock) {
-    const uint32_t code = A.W.pairs[idx];
-    const int s = (int)(code >> 8);
-    const int64_t g = A.item0 + s / kItem;
-    const int jd = find_jd(A.item_prefix, 2 * A.njobs, g);
-    const DevJob& J = A.jobs[jd >> 1];
-    const int dir = jd & 1;
-    const CCtx C{J.S, J.F[dir], J.F[1 - dir], A.W, A.tech, A.material_mode, A.mask, dir ? -1.0f : 1.0f,
-                 A.cweight, J.inv_n, A.alpha_min, A.d_min, A.jac_max, jd >> 1};
-    float4 rec;
-    int reason;
-    connect_one<CW>(C, code, stk, wc, rec, reason);
-    A.W.records[idx] = rec;
-    if (CW) wc.bytes += 16u;
-    if (A.keep_records) {
-      A.W.rec_keys[idx] = (uint32_t)dir | ((uint32_t)A.tech << 1) | ((code & 0xffu) << 8);
-      A.W.rec_sample[idx] = (uint32_t)(J.s0 + (g - A.item_prefix[jd]) * kItem + s % kItem);
+  // wave-uniform trip count (one wave per workgroup): the training-record
+  // queue reservation below is a wave-wide prefix sum
+  for (uint32_t base = blockIdx.x * kTraceBlock; base < n; base += gridDim.x * kTraceBlock) {
+    const uint32_t idx = base + threadIdx.x;
+    const bool act = idx < n;
+    TrainRec tr;
+    tr.weight = 0.0f;
+    if (act) {
+      const uint32_t code = A.W.pairs[idx];
+      const int s = (int)(code >> 8);
+      const int64_t g = A.item0 + s / kItem;
+      const int jd = find_jd(A.item_prefix, 2 * A.njobs, g);
+      const DevJob& J = A.jobs[jd >> 1];
+      const int dir = jd & 1;
+      const CCtx C{J.S, J.F[dir], J.F[1 - dir], A.W, A.tech, A.material_mode, A.mask, dir ? -1.0f : 1.0f,
+                   A.cweight, J.inv_n, A.alpha_min, A.d_min, A.jac_max, jd >> 1, A.train ? &A.mlp : nullptr};
+      const float4 q8 = A.W.t8q ? A.W.t8q[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 rec;
+      int reason;
+      connect_one<CW>(C, code, q8, stk, wc, rec, reason, tr);
+      A.W.records[idx] = rec;
+      if (CW) wc.bytes += 16u;
+      if (A.keep_records) {
+        A.W.rec_keys[idx] = (uint32_t)dir | ((uint32_t)A.tech << 1) | ((code & 0xffu) << 8);
+        A.W.rec_sample[idx] = (uint32_t)(J.s0 + (g - A.item_prefix[jd]) * kItem + s % kItem);
+      }
+      if (A.stats && reason <= 6) atomicAdd(&cnt[reason], 1ull);
     }
-    if (A.stats && reason <= 6) atomicAdd(&cnt[reason], 1ull);
+    if (A.train) {
+      const int c = tr.weight > 0.0f ? 1 : 0;
+      int total;
+      const uint32_t at = wave_reserve(A.train_count, c, total);
+      if (c && (int64_t)at < A.train_cap) {
+        float* o = A.train + (size_t)at * 10;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[q] = tr.x[q];
+        o[6] = tr.w[0];
+        o[7] = tr.w[1];
+        o[8] = tr.w[2];
+        o[9] = tr.weight;
+      }
+    }
   }
   __syncthreads();
   if (A.stats && threadIdx.x < 7) {
@@ -993,6 +1104,55 @@ __global__ __launch_bounds__(kTraceBlock) void connect_kernel(WalkArgs A) {
     }
   }
   if (CW) flush_work(A.stats, 8, wc);
+}
+
+// Technique (8)'s MIS term needs the proposal at every interior dynamic
+// vertex x_m (2 <= m <= k-3) of every queued path: one MLP pass per vertex
+// position over the wave's 64 paths (matrix cores), then the mixture density
+// of the object-space direction x_m -> x_{m+1} (from the offset origin, as
+// the other MIS terms measure it).
+__global__ __launch_bounds__(kTraceBlock) void proposal_pdf_kernel(WalkArgs A) {
+  __shared__ __attribute__((aligned(16))) float lds[kMlpLdsBytes / 4];
+  const uint32_t n = min((uint32_t)A.W.pair_cap, *A.W.npairs);
+  const MlpDev& M = A.mlp;
+  for (uint32_t base = blockIdx.x * kTraceBlock; base < n; base += gridDim.x * kTraceBlock) {
+    const uint32_t idx = base + threadIdx.x;
+    const bool act = idx < n;
+    int s = 0, i = 0, k = 0, dir = 0;
+    const DevJob* J = A.jobs;
+    if (act) {
+      const uint32_t code = A.W.pairs[idx];
+      s = (int)(code >> 8);
+      i = (int)((code >> 4) & 15u) - 1;
+      const int j = (int)(code & 15u) - 1;
+      k = (i + 1) + (has_mid(A.tech) ? 1 : 0) + (j + 1) + 2;
+      const int jd = find_jd(A.item_prefix, 2 * A.njobs, A.item0 + s / kItem);
+      J = A.jobs + (jd >> 1);
+      dir = jd & 1;
+    }
+    const Pose& pose = J->F[dir].pose;
+    float q[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int m = 2; m <= kMaxK - 3; ++m) {
+      PV x = PV{v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 1.f), 0u}, y = x;
+      bool need = act && m <= k - 3;
+      if (need) {
+        x = path_vertex(A.W, s, i, has_mid(A.tech), m);
+        need = (x.md & kDynBit) != 0u;
+        if (need) y = path_vertex(A.W, s, i, has_mid(A.tech), m + 1);
+      }
+      if (__ballot(need) == 0ull) continue;  // wave-uniform
+      float in[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (need) mlp_input(M, pose_inv_apply(pose, x.p), pose_inv_rot(pose, x.n), in);
+      const float* raw = mlp_forward_wave(M, in, lds);
+      if (need) {
+        const vec3 o = spawn(J->S, x.p, x.n, y.p);
+        q[m - 2] = vmf_mix_pdf(raw, pose_inv_rot(pose, unit(y.p - o)));
+      }
+      __syncthreads();  // the next pass overwrites the outputs
+    }
+    if (act) A.W.t8q[idx] = make_float4(q[0], q[1], q[2], q[3]);
+  }
 }
 
 // ------------------------------------------------------------------ splat
@@ -1148,7 +1308,7 @@ __global__ __launch_bounds__(256) void zero_images(const DevJob* jobs, int njobs
 // One lane per pixel; samples s = pixel + m * P (the residual technique (7)
 // uses the same pixel-of-sample rule).
 __global__ __launch_bounds__(kTraceBlock) void frame_kernel(FrameArgs A) {
-  __shared__ int stk[kStackDepth * kTraceBlock];
+  __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   const DevScene& S = A.S;
   const DevCamera& C = S.cam;
   const int P = C.W * C.H;
@@ -1259,6 +1419,7 @@ static void launch_walk_cw(const WalkArgs& A, int blocks, hipStream_t st) {
     case 4: launch_walk_t<4, CW>(A, blocks, st); break;
     case 5: launch_walk_t<5, CW>(A, blocks, st); break;
     case 6: launch_walk_t<6, CW>(A, blocks, st); break;
+    case 8: launch_walk_t<8, CW>(A, blocks, st); break;
     default: launch_walk_t<7, CW>(A, blocks, st); break;
   }
 }
@@ -1270,6 +1431,10 @@ void launch_walk(const WalkArgs& A, int blocks, hipStream_t st) {
 void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st) {
   hipLaunchKernelGGL(zero_images, dim3(1024), dim3(256), 0, st, jobs, njobs);
 }
+void launch_proposal_pdf(const WalkArgs& A, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(proposal_pdf_kernel, dim3(blocks), dim3(kTraceBlock), 0, st, A);
+}
+
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st) {
   if (A.count_work)
     hipLaunchKernelGGL((connect_kernel<true>), dim3(blocks), dim3(kTraceBlock), 0, st, A);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "librpi.so")
 RPI_OK = 0
 EDIT_RIGID, EDIT_MATERIAL = 0, 1
 FLAG_TWO_WAY, FLAG_ACCUMULATE, FLAG_COUNT_WORK, FLAG_RECORDS, FLAG_TIME_KERNELS = 1, 2, 4, 8, 16
+PROPOSAL_NPARAM, TRAIN_RECORD_FLOATS = 11368, 10
 
 
 class RpiError(RuntimeError):
@@ -42,13 +43,24 @@ class Params(C.Structure):
                 ("strategy_mask", C.c_uint32), ("flags", C.c_uint32), ("alpha_min", C.c_float),
                 ("d_min", C.c_float), ("jac_max", C.c_float), ("c_weight", C.c_float),
                 ("sample_begin", C.c_int64), ("sample_end", C.c_int64), ("queue_cap", C.c_int32),
-                ("job", C.c_uint32)]
+                ("job", C.c_uint32), ("proposal", C.c_void_p), ("d_train_records", C.c_void_p),
+                ("train_capacity", C.c_int64)]
 
     @staticmethod
     def make(spp, depth, seed, mask=0x7F, flags=FLAG_TWO_WAY, alpha_min=0.2, d_min=-1.0, jac_max=10.0,
-             c_weight=0.5, sample_begin=0, sample_end=-1, queue_cap=0, job=0):
-        return Params(spp, depth, seed, mask, flags, alpha_min, d_min, jac_max, c_weight, sample_begin,
-                      sample_end, queue_cap, job)
+             c_weight=0.5, sample_begin=0, sample_end=-1, queue_cap=0, job=0, proposal=None, train_records=None):
+        """proposal: a Proposal (technique 8 with mask bit 7); train_records: a
+        float32 device tensor [cap, 10] receiving technique-3 training records."""
+        p = Params(spp, depth, seed, mask, flags, alpha_min, d_min, jac_max, c_weight, sample_begin,
+                   sample_end, queue_cap, job)
+        if proposal is not None:
+            p.proposal = proposal.h.value
+            p._proposal_ref = proposal
+        if train_records is not None:
+            cap = train_records.shape[0]
+            p.d_train_records = _devptr(train_records, cap * TRAIN_RECORD_FLOATS).value
+            p.train_capacity = cap
+        return p
 
 
 class Stats(C.Structure):
@@ -57,7 +69,7 @@ class Stats(C.Structure):
                 ("nodes_visited", C.c_int64), ("tris_tested", C.c_int64), ("milliseconds", C.c_double),
                 ("kernel_ms", C.c_double * 16), ("kernel_launches", C.c_int64 * 16),
                 ("kernel_nodes", C.c_int64 * 16), ("kernel_tris", C.c_int64 * 16),
-                ("kernel_bytes_written", C.c_int64 * 16)]
+                ("kernel_bytes_written", C.c_int64 * 16), ("train_records", C.c_int64)]
 
     def as_dict(self):
         return {"samples": self.samples, "paths": self.paths, "accepted": self.accepted,
@@ -65,12 +77,18 @@ class Stats(C.Structure):
                 "nodes_visited": self.nodes_visited, "tris_tested": self.tris_tested,
                 "milliseconds": self.milliseconds, "kernel_ms": list(self.kernel_ms),
                 "kernel_launches": list(self.kernel_launches), "kernel_nodes": list(self.kernel_nodes),
-                "kernel_tris": list(self.kernel_tris), "kernel_bytes_written": list(self.kernel_bytes_written)}
+                "kernel_tris": list(self.kernel_tris), "kernel_bytes_written": list(self.kernel_bytes_written),
+                "train_records": self.train_records}
 
 
 class Tuning(C.Structure):
     _fields_ = [("queue_cap", C.c_int32), ("walk_blocks_per_cu", C.c_int32), ("connect_blocks_per_cu", C.c_int32),
                 ("ms_per_msample", C.c_double)]
+
+
+class TrainParams(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
 
 
 class Job(C.Structure):
@@ -99,11 +117,20 @@ def load_library():
                                                 C.POINTER(Stats), vp]
         L.rpi_get_records.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.rpi_autotune.argtypes = [vp, vp, C.POINTER(Params), C.POINTER(Tuning), vp]
+        L.rpi_proposal_create.argtypes = [vp, vp, C.c_uint64, C.POINTER(vp)]
+        L.rpi_proposal_destroy.argtypes = [vp]
+        L.rpi_proposal_set_weights.argtypes = [vp, vp]
+        L.rpi_proposal_get_weights.argtypes = [vp, vp]
+        L.rpi_proposal_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.rpi_proposal_loss_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
+        L.rpi_proposal_train.argtypes = [vp, vp, C.c_int64, C.POINTER(TrainParams), vp, vp]
         L.rpi_last_error.restype = C.c_char_p
         L.rpi_version.restype = C.c_char_p
         for f in ("rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
                   "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records",
-                  "rpi_autotune"):
+                  "rpi_autotune", "rpi_proposal_create", "rpi_proposal_destroy", "rpi_proposal_set_weights",
+                  "rpi_proposal_get_weights", "rpi_proposal_forward", "rpi_proposal_loss_grad",
+                  "rpi_proposal_train"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -233,3 +260,58 @@ def render_residual_batch(scene: Scene, jobs, params: Params, stats=False, strea
     _check(L.rpi_render_residual_batch(scene.h, arr, len(jobs), C.byref(params),
                                        C.byref(st) if st is not None else None, _stream(stream)))
     return st.as_dict() if st is not None else None
+
+
+def _devptr_any(t, n):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise RpiError(-1, "expected a contiguous float32 device tensor")
+    if t.numel() < n:
+        raise RpiError(-1, "tensor has %d elements, need %d" % (t.numel(), n))
+    return C.c_void_p(t.data_ptr())
+
+
+class Proposal:
+    """rpi_proposal_*: the learned proposal of technique 8 (MLP weights on the device)."""
+
+    def __init__(self, scene: Scene, params=None, seed=0):
+        L = load_library()
+        h = C.c_void_p()
+        if params is not None:
+            params = np.ascontiguousarray(params, np.float32).reshape(PROPOSAL_NPARAM)
+        _check(L.rpi_proposal_create(scene.h, params.ctypes.data_as(C.c_void_p) if params is not None else None,
+                                     int(seed), C.byref(h)))
+        self.h = h
+        self.scene = scene
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.rpi_proposal_destroy(self.h)
+            self.h = None
+
+    def set_weights(self, params):
+        params = np.ascontiguousarray(params, np.float32).reshape(PROPOSAL_NPARAM)
+        _check(load_library().rpi_proposal_set_weights(self.h, params.ctypes.data_as(C.c_void_p)))
+
+    def get_weights(self):
+        out = np.zeros(PROPOSAL_NPARAM, np.float32)
+        _check(load_library().rpi_proposal_get_weights(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def forward(self, x, out, stream=None):
+        n = x.shape[0]
+        _check(load_library().rpi_proposal_forward(self.h, _devptr_any(x, 6 * n), n, _devptr_any(out, 40 * n),
+                                                   _stream(stream)))
+
+    def loss_grad(self, records, grad, loss=None, stream=None):
+        n = records.shape[0]
+        _check(load_library().rpi_proposal_loss_grad(
+            self.h, _devptr_any(records, TRAIN_RECORD_FLOATS * n), n, _devptr_any(grad, PROPOSAL_NPARAM),
+            _devptr_any(loss, 1) if loss is not None else None, _stream(stream)))
+
+    def train(self, records, n, steps, batch=16384, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0,
+              losses=None, stream=None):
+        tp = TrainParams(int(steps), int(batch), lr, beta1, beta2, eps, int(seed))
+        _check(load_library().rpi_proposal_train(
+            self.h, _devptr_any(records, TRAIN_RECORD_FLOATS * n), int(n), C.byref(tp),
+            _devptr_any(losses, steps) if losses is not None else None, _stream(stream)))

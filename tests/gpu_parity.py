@@ -7,7 +7,7 @@ from paper_2406_16302_amd.scenes import EDIT_MATERIAL
 
 
 def gpu_residual(ws, spp=None, depth=None, seed=None, mask=None, s0=0, s1=-1, records=False, queue_cap=0,
-                 stats=False, scene=None):
+                 stats=False, scene=None, mlp=None, proposal=None, train_records=None):
     import torch
     sc = scene or native.Scene(ws.scene)
     ed = native.Edit(sc, ws.edit)
@@ -16,8 +16,12 @@ def gpu_residual(ws, spp=None, depth=None, seed=None, mask=None, s0=0, s1=-1, re
         flags |= native.FLAG_TWO_WAY
     if records:
         flags |= native.FLAG_RECORDS
+    if mlp is not None and proposal is None:
+        proposal = native.Proposal(sc, mlp)
     p = native.Params.make(spp or ws.spp, depth or ws.depth, seed if seed is not None else ws.seed,
-                           mask=mask or ws.mask, flags=flags, sample_begin=s0, sample_end=s1, queue_cap=queue_cap)
+                           mask=mask or ws.mask, flags=flags, sample_begin=s0, sample_end=s1, queue_cap=queue_cap,
+                           proposal=proposal, train_records=train_records)
+    stats = stats or train_records is not None
     out = torch.zeros((sc.height, sc.width, 3), dtype=torch.float32, device="cuda")
     st = native.render_residual(sc, ed, p, out, stats=stats)
     torch.cuda.synchronize()
@@ -27,10 +31,10 @@ def gpu_residual(ws, spp=None, depth=None, seed=None, mask=None, s0=0, s1=-1, re
     return res
 
 
-def oracle_residual(ws, spp=None, depth=None, seed=None, mask=None, s0=0, s1=-1, records=False, threads=8):
+def oracle_residual(ws, spp=None, depth=None, seed=None, mask=None, s0=0, s1=-1, records=False, threads=8, mlp=None):
     o = oracle.OracleScene(ws.scene)
     kw = dict(spp=spp or ws.spp, depth=depth or ws.depth, seed=seed if seed is not None else ws.seed,
-              mask=mask or ws.mask, s0=s0, s1=s1, threads=1 if records else threads, records=records)
+              mask=mask or ws.mask, s0=s0, s1=s1, threads=1 if records else threads, records=records, mlp=mlp)
     return oracle.residual_for(ws, o, **kw)
 
 

@@ -1,0 +1,192 @@
+"""Learned proposal (technique 8) on the GPU against the oracle: MLP
+inference (BF16 matrix cores, FP32 accumulation) and the gradient of the
+weighted NLL, technique 8 inside the estimator (its samples and its MIS term
+in every path) on the same Philox streams, training-record collection, and
+training by the library's own kernels."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_16302_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+@pytest.fixture(scope="module")
+def small_scene():
+    from paper_2406_16302_amd import native
+    return native.Scene(scenes.cornell_material(width=16, height=16).scene)
+
+
+def _inputs(rng, n):
+    x = np.zeros((n, 6), np.float32)
+    x[:, :3] = rng.uniform(-1, 1, (n, 3))
+    nn = rng.normal(size=(n, 3))
+    x[:, 3:] = nn / np.linalg.norm(nn, axis=1, keepdims=True)
+    return x
+
+
+def _records(rng, n):
+    rec = np.zeros((n, 10), np.float32)
+    rec[:, :6] = _inputs(rng, n)
+    w = rng.normal(size=(n, 3))
+    rec[:, 6:9] = w / np.linalg.norm(w, axis=1, keepdims=True)
+    rec[:, 9] = rng.uniform(0.0, 2.0, n)
+    rec[rng.random(n) < 0.1, 9] = 0.0  # records without weight take no part
+    return rec
+
+
+def test_weights_round_trip(small_scene):
+    from paper_2406_16302_amd import native
+    P = oracle.mlp_init(3)
+    pr = native.Proposal(small_scene, P)
+    assert np.array_equal(pr.get_weights(), P)
+    Q = oracle.mlp_init(4)
+    pr.set_weights(Q)
+    assert np.array_equal(pr.get_weights(), Q)
+
+
+@pytest.mark.parametrize("n", [1, 64, 1000])
+def test_forward_matches_oracle(small_scene, n):
+    from paper_2406_16302_amd import native
+    rng = np.random.default_rng(n)
+    P = oracle.mlp_init(5)
+    x = _inputs(rng, n)
+    pr = native.Proposal(small_scene, P)
+    out = torch.zeros((n, 40), dtype=torch.float32, device="cuda")
+    pr.forward(torch.from_numpy(x).cuda(), out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().astype(np.float64)
+    ref = oracle.mlp_forward(P, x, bf16=True)
+    err = np.abs(g - ref)
+    rel = np.sqrt((err ** 2).sum() / (ref ** 2).sum())
+    print("n=%d rel_l2=%.3g max_abs=%.3g" % (n, rel, err.max()))
+    # BF16 operands on both sides; the kernel accumulates in FP32 (the oracle
+    # in FP64), so an activation can round to the neighbouring BF16 value
+    assert rel < 2e-3
+    assert err.max() < 2e-2 * max(1.0, np.abs(ref).max())
+    # and BF16 inference stays close to the full-precision network
+    full = oracle.mlp_forward(P, x, bf16=False)
+    assert np.sqrt(((g - full) ** 2).sum() / (full ** 2).sum()) < 3e-2
+
+
+@pytest.mark.parametrize("n", [64, 777])
+def test_gradient_matches_oracle(small_scene, n):
+    from paper_2406_16302_amd import native
+    rng = np.random.default_rng(100 + n)
+    P = oracle.mlp_init(6)
+    rec = _records(rng, n)
+    pr = native.Proposal(small_scene, P)
+    grad = torch.zeros(native.PROPOSAL_NPARAM, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    pr.loss_grad(torch.from_numpy(rec).cuda(), grad, loss)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    lref, gref = oracle.mlp_loss_grad(P, rec, bf16=True)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    print("n=%d loss gpu %.6g oracle %.6g grad rel_l2 %.3g" % (n, float(loss.item()), lref, rel))
+    assert abs(float(loss.item()) - lref) <= 2e-3 * abs(lref)
+    # back-propagated signals are rounded to BF16 for the matrix cores
+    assert rel < 2e-2
+    # every parameter block is covered (a dropped layer would show here)
+    for lo, hi in ((0, 384), (384, 448), (448, 4544), (4544, 4608), (4608, 8704), (8704, 8768), (8768, 11328),
+                   (11328, 11368)):
+        rb = np.linalg.norm(g[lo:hi] - gref[lo:hi]) / max(np.linalg.norm(gref[lo:hi]), 1e-30)
+        assert rb < 5e-2, (lo, hi, rb)
+
+
+def _t8_parity(ws, mask, seed_mlp):
+    from gpu_parity import compare_records, gpu_residual, oracle_residual, rel_l2
+    P = oracle.mlp_init(seed_mlp)
+    g = gpu_residual(ws, mask=mask, records=True, mlp=P, stats=True)
+    o = oracle_residual(ws, mask=mask, records=True, mlp=P)
+    c = compare_records(g["records"], o["records"])
+    rel = rel_l2(g["image"], o["image"])
+    div = (c["value_mismatch"] + c["missing_on_gpu"] + c["extra_on_gpu"]) / max(c["oracle"], 1)
+    n8 = int((o["records"]["tech"] == 8).sum())
+    print(ws.name, "rel_l2=%.3g" % rel, c, "t8 paths", n8, "gpu t8", g["stats"]["by_tech"][8])
+    assert n8 > 100 and g["stats"]["by_tech"][8] > 100
+    assert div <= 1e-3, c
+    assert rel <= 1e-3, rel
+    return g, o
+
+
+def test_technique8_parity_material_edit():
+    _t8_parity(scenes.cornell_material(width=32, height=32, spp=4, depth=5), 0x87, 21)
+
+
+def test_technique8_parity_motion_all_strategies():
+    _t8_parity(scenes.cornell_motion(width=32, height=32, spp=4, depth=5), 0xFF, 22)
+
+
+def test_training_records_match_oracle():
+    from gpu_parity import gpu_residual, oracle_residual
+    ws = scenes.cornell_material(width=32, height=32, spp=4, depth=5)
+    cap = 200000
+    buf = torch.zeros((cap, 10), dtype=torch.float32, device="cuda")
+    g = gpu_residual(ws, mask=0x07, train_records=buf)
+    n = g["stats"]["train_records"]
+    o = oracle_residual(ws, mask=0x07, records=True)
+    ro = o["records"]
+    ro = ro[(ro["tech"] == 3) & (ro["train"][:, 9] > 0)]
+    rg = buf[:min(n, cap)].cpu().numpy().astype(np.float64)
+    rg = rg[rg[:, 9] > 0]
+    print("records gpu %d (nonzero %d) oracle %d" % (n, len(rg), len(ro)))
+    assert len(ro) > 500
+    assert abs(len(rg) - len(ro)) <= 1e-3 * len(ro) + 1
+    # group by the (unique per sample) start position and compare weight sums
+    def groups(r):
+        d = {}
+        for row in r:
+            key = tuple(np.round(row[:3], 4))
+            d.setdefault(key, [0.0, row[:9]])
+            d[key][0] += row[9]
+        return d
+    dg, do = groups(rg), groups(ro["train"])
+    common = set(dg) & set(do)
+    assert len(common) >= 0.995 * len(do)
+    wg = np.array([dg[k][0] for k in common])
+    wo = np.array([do[k][0] for k in common])
+    assert np.quantile(np.abs(wg / wo - 1), 0.99) < 1e-3
+    xg = np.array([dg[k][1] for k in common])
+    xo = np.array([do[k][1] for k in common])
+    assert np.quantile(np.abs(xg - xo).max(1), 0.99) < 1e-4
+
+
+def test_training_lowers_the_loss():
+    from gpu_parity import gpu_residual
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_material(width=32, height=32, spp=8, depth=5)
+    cap = 400000
+    buf = torch.zeros((cap, 10), dtype=torch.float32, device="cuda")
+    sc = native.Scene(ws.scene)
+    g = gpu_residual(ws, mask=0x07, train_records=buf, scene=sc)
+    n = min(g["stats"]["train_records"], cap)
+    assert n > 2000
+    pr = native.Proposal(sc, oracle.mlp_init(9))
+    steps = 300
+    losses = torch.zeros(steps, dtype=torch.float32, device="cuda")
+    pr.train(buf, n, steps, batch=4096, lr=2e-3, seed=5, losses=losses)
+    torch.cuda.synchronize()
+    L = losses.cpu().numpy()
+    print("loss first %.4f last %.4f" % (L[:10].mean(), L[-10:].mean()))
+    assert np.isfinite(L).all()
+    assert L[-20:].mean() < L[:20].mean() - 0.3
+    # the trained weights still agree with the oracle's forward pass
+    W = pr.get_weights()
+    assert np.isfinite(W).all()
+    x = np.ascontiguousarray(buf[:256, :6].cpu().numpy())
+    out = torch.zeros((256, 40), dtype=torch.float32, device="cuda")
+    pr.forward(torch.from_numpy(x).cuda(), out)
+    torch.cuda.synchronize()
+    ref = oracle.mlp_forward(W, x, bf16=True)
+    gg = out.cpu().numpy()
+    assert np.sqrt(((gg - ref) ** 2).sum() / (ref ** 2).sum()) < 5e-3
