@@ -1040,6 +1040,16 @@ struct MisTerms {
   double by_tech[9];
 };
 
+// Technique (8)'s density of x_{m+1} given x_m: the learned lobes at x_m
+// (object space) for the direction from the offset origin, in area measure.
+static double t8_dir_pdf(const Scene& S, const Path& P, const MisOpts& O, int m) {
+  const Pose& pose = O.frame->pose;
+  Lobes Lb = proposal_lobes(*O.prop, pose_inv_apply(pose, P.v[m].p), pose_inv_rot(pose, P.v[m].n));
+  V3 wg = normalize(P.v[m + 1].p - origin(S, P, m, m + 1));
+  D3 wo = dnorm(dd(pose_inv_rot(pose, wg)));
+  return vmf_pdf(Lb, wo) * to_area(S, P, m, m + 1);
+}
+
 // Sum over every strategy able to produce the path: one per dynamic vertex
 // (techniques 1/2/3 by position), one per ghost crossing (4/5/6 by edge),
 // plus path tracing (7).  Each strategy pdf is written out as the full
@@ -1062,18 +1072,12 @@ static MisTerms mis_terms(const Scene& S, const Frame& F, const Path& P, const M
       if (on(1)) r.by_tech[1] += pL * pD * prod_a(S, F, P, 1, m - 1);
     } else if (m == 1) {
       if (on(2) && k >= 4) r.by_tech[2] += pD * prod_b(S, F, P, 2, k - 2) * pL;
+      if (on(8) && O.prop && O.prop->params) r.by_tech[8] += pD * t8_dir_pdf(S, P, O, 1) * prod_b(S, F, P, 3, k - 2) * pL;
     } else {
       if (on(3)) r.by_tech[3] += pD * pdf_cos_out(S, P, m) * prod_a(S, F, P, 1, m - 1) *
                                  prod_b(S, F, P, m + 2, k - 2) * pL;
-      if (on(8) && O.prop && O.prop->params) {
-        // technique (8): the learned lobes at x_m, evaluated in object space
-        const Pose& pose = O.frame->pose;
-        Lobes Lb = proposal_lobes(*O.prop, pose_inv_apply(pose, P.v[m].p), pose_inv_rot(pose, P.v[m].n));
-        V3 wg = normalize(P.v[m + 1].p - origin(S, P, m, m + 1));
-        D3 wo = dnorm(dd(pose_inv_rot(pose, wg)));
-        r.by_tech[8] += pD * vmf_pdf(Lb, wo) * to_area(S, P, m, m + 1) * prod_a(S, F, P, 1, m - 1) *
-                        prod_b(S, F, P, m + 2, k - 2) * pL;
-      }
+      if (on(8) && O.prop && O.prop->params)
+        r.by_tech[8] += pD * t8_dir_pdf(S, P, O, m) * prod_a(S, F, P, 1, m - 1) * prod_b(S, F, P, m + 2, k - 2) * pL;
     }
   }
   if (O.ghosts && k >= 3) {
@@ -1438,14 +1442,20 @@ struct SubPath {
   double pl[MAXV];       // light pdf of L[i]
 };
 
-static void two_ended(const Gen& g, const PV* mid, PV e0, double pe0, V3 wie, PV l0, double pl0, V3 wil,
-                      double pstart, int start) {
+// Paths of a sample with a light-side vertex l0 and (eye = true) a
+// sensor-side vertex e0 on either side of the start (mid: x_D, or none for
+// a ghost start): light walk from l0 with next-event estimation, eye walk
+// from e0 with a camera connection at each vertex, every valid pairing.
+// mid_cam: the sensor sees the start vertex directly, which adds the paths
+// x_0 -> x_D -> l0 ... (the light walk then goes one bounce further).
+static void two_ended(const Gen& g, const PV* mid, bool eye, PV e0, double pe0, V3 wie, PV l0, double pl0, V3 wil,
+                      double pstart, int start, bool mid_cam = false) {
   // light side: l[0..], NEE at each vertex
   SubPath Ls, Es;
   Ls.n = 0;
   Es.n = 0;
   int extra = mid ? 1 : 0;
-  int jmax = g.depth - 3 - extra;  // i = 0 partner
+  int jmax = g.depth - 3 - extra + (mid_cam ? 1 : 0);  // i = 0 partner, or the sensor at x_D
   int imax = g.depth - 3 - extra;
   Ls.v[0] = l0;
   light_walk(g, Ls.v, wil, pl0, jmax, [&](int j, bool ok, const LightPt& L, double p) {
@@ -1454,6 +1464,14 @@ static void two_ended(const Gen& g, const PV* mid, PV e0, double pe0, V3 wie, PV
     Ls.pl[j] = p;
     Ls.conn[j] = ok;
   });
+  if (mid_cam)
+    for (int j = 0; j < Ls.n; ++j) {
+      if (!Ls.conn[j]) continue;
+      Path Q;
+      if (!assemble(g, nullptr, -1, mid, Ls.v, j, Ls.L[j], pstart * Ls.pl[j], start, Q)) continue;
+      if (light_edge_ok(g, Q)) emit(g, Q);
+    }
+  if (!eye) return;
   Es.v[0] = e0;
   eye_walk(g, Es.v, wie, pe0, imax, [&](int i, double p) {
     Es.n = i + 1;
@@ -1506,16 +1524,19 @@ static void tech3(const Gen& g) {
   D3 dl = dd(l0.p) - dd(ol), de = dd(e0.p) - dd(oe);
   double pl = ddot(dd(xd.n), dd(wl)) / PI * std::fabs(ddot(dd(l0.n), dnorm(dl))) / dlen2(dl);
   double pe = bsdf_pdf(m, dd(xd.n), dd(wi), dd(we)) * std::fabs(ddot(dd(e0.n), dnorm(de))) / dlen2(de);
-  two_ended(g, &xd, e0, pe, normalize(xd.p - e0.p), l0, pl, normalize(xd.p - l0.p), 1.0 / g.S.obj_area, 0);
+  two_ended(g, &xd, true, e0, pe, normalize(xd.p - e0.p), l0, pl, normalize(xd.p - l0.p), 1.0 / g.S.obj_area, 0);
 }
 
-// (8) Learned proposal: technique (3) with the light-side direction drawn
-// from the MLP's vMF mixture at x_D (object space) instead of the cosine lobe.
+// (8) Learned proposal: a start x_D on the object whose light-side direction
+// is drawn from the MLP's vMF mixture at x_D (object space).  On the sensor
+// side x_D is either seen by the camera directly (the paths of technique
+// (2), whose BSDF direction the mixture replaces) or followed, as in
+// technique (3), by a BSDF direction towards the sensor and an eye walk.
 static void tech8(const Gen& g, const Proposal& Pr) {
   float u[4];
   g.rng.draw(0, 0, 0, u);
   PV xd = obj_point(g.S, g.F.pose, u);
-  if (g.depth < 4 || !Pr.params) return;
+  if (g.depth < 3 || !Pr.params) return;
   Lobes Lb = proposal_lobes(Pr, pose_inv_apply(g.F.pose, xd.p), pose_inv_rot(g.F.pose, xd.n));
   g.rng.draw(0, 0, 2, u);
   V3 wobj = vmf_sample(Lb, u[0], u[1], u[2]);
@@ -1524,22 +1545,42 @@ static void tech8(const Gen& g, const Proposal& Pr) {
   Hit hl = closest(g.S, g.F.pose, ol, wl);
   if (!hl.ok || (!hl.dyn && g.S.mats[hl.mat].type == MAT_EMITTER)) return;
   PV l0{hl.p, hl.n, hl.mat, hl.dyn};
-  g.rng.draw(0, 0, 3, u);
-  Material m = vertex_material(g.S, g.F, xd.mat, xd.dyn);
-  // the sensor-side BSDF sample sees the light-side neighbour x_{m+1} as its
-  // incoming direction (vertex to vertex, as the MIS tables evaluate it)
-  const V3 wi = normalize(l0.p - xd.p);
-  V3 we;
-  if (!bsdf_sample(m, xd.n, wi, u[0], u[1], we)) return;
-  V3 oe = spawn_dir(g.S, xd.p, xd.n, we);
-  Hit he = closest(g.S, g.F.pose, oe, we);
-  if (!he.ok || (!he.dyn && g.S.mats[he.mat].type == MAT_EMITTER)) return;
-  PV e0{he.p, he.n, he.mat, he.dyn};
-  D3 dl = dd(l0.p) - dd(ol), de = dd(e0.p) - dd(oe);
+  D3 dl = dd(l0.p) - dd(ol);
   D3 wq = dnorm(dd(pose_inv_rot(g.F.pose, normalize(l0.p - ol))));
   double pl = vmf_pdf(Lb, wq) * std::fabs(ddot(dd(l0.n), dnorm(dl))) / dlen2(dl);
-  double pe = bsdf_pdf(m, dd(xd.n), dd(wi), dd(we)) * std::fabs(ddot(dd(e0.n), dnorm(de))) / dlen2(de);
-  two_ended(g, &xd, e0, pe, normalize(xd.p - e0.p), l0, pl, normalize(xd.p - l0.p), 1.0 / g.S.obj_area, 0);
+  // the sensor sees x_D (the support test of the assembled paths checks the sides)
+  Path C;
+  C.v[0] = PV{g.S.cam.eye, g.S.cam.fwd, -1, false};
+  C.v[1] = xd;
+  C.k = 3;
+  C.L.env = false;
+  C.L.p = xd.p;  // placeholder end for the camera-edge test
+  C.L.n = xd.n;
+  const bool cam = raster(g.S.cam, xd.p) >= 0 && path_visible(g.S, g.F.pose, C, 0);
+  // or a BSDF direction towards the sensor: its incoming direction is the
+  // light-side neighbour x_{m+1} (vertex to vertex, as the MIS tables evaluate it)
+  bool eye = false;
+  PV e0{};
+  double pe = 0.0;
+  V3 oe{};
+  if (g.depth >= 4) {
+    g.rng.draw(0, 0, 3, u);
+    Material m = vertex_material(g.S, g.F, xd.mat, xd.dyn);
+    const V3 wi = normalize(l0.p - xd.p);
+    V3 we;
+    if (bsdf_sample(m, xd.n, wi, u[0], u[1], we)) {
+      oe = spawn_dir(g.S, xd.p, xd.n, we);
+      Hit he = closest(g.S, g.F.pose, oe, we);
+      if (he.ok && !(!he.dyn && g.S.mats[he.mat].type == MAT_EMITTER)) {
+        e0 = PV{he.p, he.n, he.mat, he.dyn};
+        D3 de = dd(e0.p) - dd(oe);
+        pe = bsdf_pdf(m, dd(xd.n), dd(wi), dd(we)) * std::fabs(ddot(dd(e0.n), dnorm(de))) / dlen2(de);
+        eye = true;
+      }
+    }
+  }
+  two_ended(g, &xd, eye, e0, pe, eye ? normalize(xd.p - e0.p) : V3{}, l0, pl, normalize(xd.p - l0.p),
+            1.0 / g.S.obj_area, 0, cam);
 }
 
 // (4) Ghost from emitter: the ray x_L -> x_G gives x_1 (eq. vertex1pdf).
@@ -1643,7 +1684,7 @@ static void tech6(const Gen& g, double p_dir) {
   D3 wu = dnorm(d);
   double G = std::fabs(ddot(dd(e0.n), wu)) * std::fabs(ddot(dd(l0.n), wu)) / dlen2(d);
   double pg = (1.0 / g.S.obj_area) * p_dir * G / std::fabs(ddot(dd(xg.n), wu));
-  two_ended(g, nullptr, e0, 1.0, normalize(l0.p - e0.p), l0, 1.0, normalize(e0.p - l0.p), pg, 0);
+  two_ended(g, nullptr, true, e0, 1.0, normalize(l0.p - e0.p), l0, 1.0, normalize(e0.p - l0.p), pg, 0);
 }
 
 // Camera path: jittered pixel ray; emission at x_1; NEE at every vertex.
@@ -1727,7 +1768,7 @@ static int n_starts_for(const Scene& S, const Frame& F, const Path& P, int tech)
   if ((tech >= 1 && tech <= 3) || tech == 8) {
     for (int m = 1; m <= k - 2; ++m)
       if (P.v[m].dyn && ((tech == 1 && m == k - 2) || (tech == 2 && m == 1 && m != k - 2) ||
-                         ((tech == 3 || tech == 8) && m >= 2 && m <= k - 3)))
+                         (tech == 3 && m >= 2 && m <= k - 3) || (tech == 8 && m <= k - 3)))
         ++n;
   } else if (tech >= 4 && tech <= 6) {
     for (int a = 0; a <= k - 2; ++a) {
@@ -1742,7 +1783,8 @@ static int n_starts_for(const Scene& S, const Frame& F, const Path& P, int tech)
   return n;
 }
 
-// Training record of a path generated by technique (3) at x_m, m = i + 2:
+// Training record of a path generated by technique (2) or (3) at x_m,
+// m = i + 2 (m = 1 for technique (2)):
 // the proposal input at x_m, the direction to x_{m+1} (from the offset
 // origin, in object space) and the path's mean absolute residual
 // contribution over its generation density -- a sample of the directional
@@ -1834,7 +1876,7 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
         r.mis_total = mt.total;
         r.mis_tech = mt.by_tech[tech];
         r.p_gen = X.p_gen;
-        if (tech == 3) train_record(S, F, *prop, X, unweighted, r.train);
+        if (tech == 2 || tech == 3) train_record(S, F, *prop, X, unweighted, r.train);
         recs->push_back(r);
       }
     }

@@ -93,6 +93,8 @@ def test_technique8_generation_density_equals_mis_term(oracle_lib):
     rec = r["records"]
     s = rec[(rec["tech"] == 8) & (rec["n_starts"] == 1)]
     assert len(s) > 50
+    # both sensor sides occur: the camera sees x_D (i = -1) and eye walks (i >= 0)
+    assert ((s["pair"] >> 4) == 0).sum() > 20 and ((s["pair"] >> 4) > 0).sum() > 20
     rel = np.abs(s["p_gen"] / s["mis_tech"] - 1)
     assert np.quantile(rel, 0.99) < 1e-4 and rel.max() < 1e-2, rel.max()
     assert (rec["p_gen"] <= rec["mis_tech"] * (1 + 1e-4)).all()
