@@ -91,12 +91,14 @@ typedef struct {
   int32_t queue_cap;      /* samples per chunk (0: automatic) */
   uint32_t job;           /* third Philox counter word (distinct jobs get independent streams) */
   /* Learned proposal (spec addition, not in the paper): with a non-NULL
-   * proposal, strategy_mask bit 7 enables technique 8 -- technique 3 with the
-   * light-side direction drawn from the proposal's lobes -- and its term in
+   * proposal, strategy_mask bit 7 enables technique 8 -- a start x_D on the
+   * object whose light-side direction is drawn from the proposal's lobes,
+   * seen by the camera directly (the paths of technique 2) or followed by a
+   * BSDF direction and an eye walk (those of technique 3) -- and its term in
    * every path's MIS sum.  The proposal's weights are read when the kernels
    * run (a training step enqueued before the call is seen by it). */
   const rpi_proposal* proposal;
-  /* Training-record collection: every path generated by technique 3 appends
+  /* Training-record collection: every path generated by technique 2 or 3 appends
    * one record {x[6], w_obj[3], weight} (10 float32) to d_train_records
    * (device memory, train_capacity records): the proposal input at x_D, the
    * direction x_D -> x_{D+1} in object space, and the mean absolute residual
@@ -105,6 +107,11 @@ typedef struct {
    * the capacity are dropped).  NULL: off. */
   float* d_train_records;
   int64_t train_capacity;
+  /* Record weight: 0 = |f| / p_gen (the directional distribution of residual
+   * energy at x_D); 1 = |f|^2 / (p_gen * sum of the path's strategy
+   * densities) (its second-moment contribution under the MIS combination:
+   * directions the other strategies sample poorly weigh more). */
+  int32_t train_weighting;
 } rpi_render_params;
 
 typedef struct {
@@ -120,7 +127,7 @@ typedef struct {
   double milliseconds;    /* device time of the call (when stats are requested) */
   /* Per kernel: index t = 1..7 walk kernel of technique t, 8 connect, 9 splat
    * (all splat kernels of a chunk), 10 frame, 11 walk kernel of technique 8,
-   * 12 proposal densities for the MIS sums.  ms/launches with
+   * 12 proposal densities for the MIS sums, 13 technique-8 starts (MLP).  ms/launches with
    * RPI_FLAG_TIME_KERNELS; node/triangle fetches and record bytes written
    * with RPI_FLAG_COUNT_WORK. */
   double kernel_ms[16];

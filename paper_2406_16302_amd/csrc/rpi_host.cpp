@@ -626,6 +626,7 @@ static rpi_status check_params(const rpi_scene* s, const rpi_render_params* p) {
   if (p->strategy_mask == 0 || (p->strategy_mask & ~0xFFu)) return fail(RPI_ERR_INVALID_ARG, "strategy_mask must be a non-empty subset of bits 0..7");
   if ((p->strategy_mask & 0x80u) && !p->proposal) return fail(RPI_ERR_INVALID_ARG, "technique 8 needs a proposal");
   if (p->d_train_records && p->train_capacity < 0) return fail(RPI_ERR_INVALID_ARG, "negative train_capacity");
+  if (p->train_weighting != 0 && p->train_weighting != 1) return fail(RPI_ERR_INVALID_ARG, "train_weighting must be 0 or 1");
   if (!(p->jac_max > 1.0f) || !(p->alpha_min >= 0.0f) || !(p->c_weight > 0.0f && p->c_weight < 1.0f))
     return fail(RPI_ERR_INVALID_ARG, "bad rejection / weight parameters");
   const int64_t N = (int64_t)p->spp * s->W * s->H;
@@ -646,7 +647,7 @@ int max_pairs_per_sample(int tech, int d) {
     case 7: return d + 1;
     case 3:
     case 8: {
-      int c = 0;
+      int c = tech == 8 ? std::max(d - 2, 0) : 0;  // technique 8: the camera sees x_D
       for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) c += (i + j + 4 <= d);
       return c;
@@ -712,7 +713,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   const size_t o_rec = take((size_t)pair_cap * sizeof(float4));
   const size_t o_keys = keep ? take((size_t)pair_cap * 4) : 0;
   const size_t o_ks = keep ? take((size_t)pair_cap * 4) : 0;
-  const size_t o_t8 = t8 ? take((size_t)pair_cap * sizeof(float4)) : 0;
+  const size_t o_t8 = t8 ? take((size_t)pair_cap * 2 * sizeof(float4)) : 0;
   const size_t o_stats = take(sizeof(DevStats));
   const size_t o_tc = take((size_t)ntiles * 4);
   const size_t o_to = take((size_t)(ntiles + 1) * 4);
@@ -917,6 +918,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
     A.train = p->d_train_records;
     A.train_cap = p->train_capacity;
     A.train_count = w.train_count;
+    A.train_weighting = p->train_weighting;
   }
   SplatArgs sa;
   std::memset(&sa, 0, sizeof sa);
@@ -961,7 +963,12 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       launch_zero_u32(w.W.npairs, 1, st);
       launch_zero_u32(w.item_counter, 1, st);
       const int blocks = std::min<int64_t>(wblocks, A.nitems);
-      rpi_status r = timed(t == 8 ? 11 : t, [&] { launch_walk(A, blocks, st); });
+      rpi_status r;
+      if (t == 8) {
+        r = timed(13, [&] { launch_t8_start(A, std::min<int64_t>(cblocks, A.nitems), st); });
+        if (r) return r;
+      }
+      r = timed(t == 8 ? 11 : t, [&] { launch_walk(A, blocks, st); });
       if (r) return r;
       if (t8) {
         r = timed(12, [&] { launch_proposal_pdf(A, cblocks, st); });

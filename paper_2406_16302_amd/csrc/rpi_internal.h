@@ -128,8 +128,8 @@ struct Workspace {
   float4* records;     // per queued path: pixel (int bits), rgb
   uint32_t* rec_keys;  // optional: dir | tech << 1 | pair << 8  (debug records)
   uint32_t* rec_sample;
-  float4* t8q;         // technique (8) on: per queued path, the proposal's solid-angle
-                       // density at interior vertices x_2 .. x_5 (0 where not dynamic)
+  float4* t8q;         // technique (8) on: per queued path (2 float4), the proposal's
+                       // solid-angle density at vertices x_1 .. x_5 (0 where not used)
   int32_t Q;           // samples per chunk
   int64_t pair_cap;
   int32_t nslot;       // vertex slots per side
@@ -201,6 +201,7 @@ struct WalkArgs {
   float* train;                // technique (3) paths -> proposal training records (or null)
   uint32_t* train_count;
   int64_t train_cap;
+  int32_t train_weighting;     // 0: |f| / p_gen, 1: |f|^2 / (p_gen * MIS sum)
 };
 
 // Tile-binned splat of one record queue.  ntiles * 4 bytes of LDS per
@@ -238,6 +239,7 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
 void launch_zero_f32(float* p, int64_t n, hipStream_t st);
 void launch_frame(const FrameArgs& A, hipStream_t st);
 void launch_proposal_pdf(const WalkArgs& A, int blocks, hipStream_t st);
+void launch_t8_start(const WalkArgs& A, int blocks, hipStream_t st);
 
 // learned proposal (rpi_train.hip)
 constexpr int kMlpNParam = 11368;

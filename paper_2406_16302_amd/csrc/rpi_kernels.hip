@@ -286,30 +286,18 @@ DEV void tech3(Lane& L) {
   eye_walk<CW>(L, e0, e0n, e0md, ce, xd, A.depth - 4);
 }
 
-// (8) learned proposal: technique (3) with the light-side direction drawn
-// from the MLP's vMF mixture at x_D (object space) instead of the cosine
-// lobe.  Called by every lane of the wave (the MLP runs on the matrix cores
-// for the whole wave); lanes without a sample pass active = false.
+// (8) learned proposal: x_D and its light-side direction come from the start
+// kernel (the MLP's vMF mixture at x_D, start records 0, 1, 3).  The sensor
+// side is the camera seeing x_D directly (technique (2)'s paths) and, as in
+// technique (3), a BSDF direction towards the sensor and an eye walk.
 template <bool CW>
-DEV void tech8(Lane& L, bool active, const MlpDev& M, void* lds) {
+DEV void tech8(Lane& L) {
   const Ctx& A = L.A;
   const DevScene& S = A.S;
-  float u[4];
-  vec3 p = v3(0.f, 0.f, 0.f), n = v3(0.f, 0.f, 1.f);
-  uint32_t md = 0u;
-  float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (active) {
-    draw(L.g, 0, 0, 0, u);
-    int tri;
-    object_point(S, A.F.pose, u, p, n, md, tri);
-    mlp_input(M, pose_inv_apply(A.F.pose, p), pose_inv_rot(A.F.pose, n), x);
-  }
-  if (A.depth < 4) return;  // uniform across the launch
-  const float* raw = mlp_forward_wave(M, x, lds);
-  if (!active) return;
-  draw(L.g, 0, 0, 2, u);
-  const vec3 wobj = vmf_mix_sample(raw, u[0], u[1], u[2]);
-  const vec3 wl = unit(pose_rot(A.F.pose, wobj));
+  if (A.depth < 3) return;
+  const float4 a = STA(A.W, 0, L.s), b = STA(A.W, 1, L.s), c = STA(A.W, 3, L.s);
+  const vec3 p = xyz(a), n = xyz(b), wl = xyz(c);
+  const uint32_t md = __float_as_uint(a.w);
   const vec3 ol = spawn_dir(S, p, n, wl);
   const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, ol, wl, L.stk, L.wc);
   if (!hl.ok) return;
@@ -317,6 +305,23 @@ DEV void tech8(Lane& L, bool active, const MlpDev& M, void* lds) {
   uint32_t l0md;
   hit_vertex(S, A.F.pose, hl, ol, wl, l0, l0n, l0md);
   if (is_emitter(S, l0md)) return;
+  const End xd = end_surf(p, n);
+  // the camera sees x_D, on the side of l0
+  Cross cam = no_cross();
+  if (raster(S.cam, p) >= 0 && same_side(n, p, S.cam.eye, l0)) {
+    const End e0 = end_eye(S);
+    if (edge_visible<CW>(S, A.F, e0, xd, L.stk, L.wc, RAY_CAMERA)) {
+      cam = edge_cross<CW>(S, A.F, e0, xd, L.stk, L.wc);
+      L.k2 = 1;
+    }
+  }
+  store_mid(L, p, n, md, cam, 1u);
+  const Cross cl = edge_cross<CW>(S, A.F, xd, end_surf(l0, l0n), L.stk, L.wc);
+  // one bounce further when the camera sees x_D (paths x_0 x_D l_0 .. l_j)
+  light_walk<CW>(L, l0, l0n, l0md, cl, xd, L.k2 ? A.depth - 3 : A.depth - 4, false);
+  // a BSDF direction towards the sensor; its incoming direction is x_{m+1}
+  if (A.depth < 4) return;
+  float u[4];
   draw(L.g, 0, 0, 3, u);
   const Material m = vmat(S, A.F, md);
   vec3 we;
@@ -328,11 +333,7 @@ DEV void tech8(Lane& L, bool active, const MlpDev& M, void* lds) {
   uint32_t e0md;
   hit_vertex(S, A.F.pose, he, oe, we, e0, e0n, e0md);
   if (is_emitter(S, e0md)) return;
-  const End xd = end_surf(p, n);
-  store_mid(L, p, n, md, no_cross(), 1u);
   const Cross ce = edge_cross<CW>(S, A.F, end_surf(e0, e0n), xd, L.stk, L.wc);
-  const Cross cl = edge_cross<CW>(S, A.F, xd, end_surf(l0, l0n), L.stk, L.wc);
-  light_walk<CW>(L, l0, l0n, l0md, cl, xd, A.depth - 4, false);
   eye_walk<CW>(L, e0, e0n, e0md, ce, xd, A.depth - 4);
 }
 
@@ -486,6 +487,7 @@ DEV int pair_count(const Lane& L, int depth) {
   } else if (TECH == 7) {
     c = __popc(L.neeok & L.dynpre) + L.k2;
   } else {
+    if (TECH == 8 && L.k2) c = __popc(L.neeok);  // the camera sees x_D: one path per light vertex
     const int extra = (TECH == 3 || TECH == 8) ? 4 : 3;
     for (int i = 0; i < L.nE; ++i)
       if (L.camok >> i & 1u)
@@ -508,6 +510,9 @@ DEV void write_pairs(const Lane& L, uint32_t* out, int depth) {
     for (int j = 0; j < L.nL; ++j)
       if (m >> j & 1u) out[w++] = pair_code(L.s, -1, j);
   } else {
+    if (TECH == 8 && L.k2)
+      for (int j = 0; j < L.nL; ++j)
+        if (L.neeok >> j & 1u) out[w++] = pair_code(L.s, -1, j);
     const int extra = (TECH == 3 || TECH == 8) ? 4 : 3;
     for (int i = 0; i < L.nE; ++i)
       if (L.camok >> i & 1u)
@@ -573,7 +578,6 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 template <int TECH, bool CW>
 __global__ __launch_bounds__(kTraceBlock) void walk_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
-  static_assert(sizeof(stk) >= kMlpLdsBytes, "one MLP pass fits the traversal stack");
   for (;;) {
     uint32_t it = 0;
     if (threadIdx.x == 0) it = atomicAdd(A.item_counter, 1u);
@@ -597,9 +601,9 @@ __global__ __launch_bounds__(kTraceBlock) void walk_kernel(WalkArgs A) {
       if (TECH == 5) tech5<CW>(L);
       if (TECH == 6) tech6<CW>(L);
       if (TECH == 7) tech7<CW>(L);
+      if (TECH == 8) tech8<CW>(L);
+      A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
     }
-    if (TECH == 8) tech8<CW>(L, active, A.mlp, stk);
-    if (active) A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
     const int c = active ? pair_count<TECH>(L, A.depth) : 0;
     int total;
     const uint32_t at = wave_reserve(A.W.npairs, c, total);
@@ -608,6 +612,45 @@ __global__ __launch_bounds__(kTraceBlock) void walk_kernel(WalkArgs A) {
       L.wc.bytes += 4u * (uint32_t)c + (active ? 4u : 0u);
       flush_work(A.stats, TECH == 8 ? 11 : TECH, L.wc);
     }
+  }
+}
+
+// Technique (8), first half: x_D by area, the proposal at x_D (one MLP pass
+// per wave on the matrix cores) and the light-side direction drawn from its
+// vMF mixture, into start records 0 (x_D, material), 1 (normal) and 3 (the
+// direction) of the sample's slot; walk_kernel<8> continues from there.
+// Items map to slots as in the walk kernel: item it, lane l -> it * 64 + l.
+__global__ __launch_bounds__(kTraceBlock) void t8_start_kernel(WalkArgs A) {
+  __shared__ __attribute__((aligned(16))) float lds[kMlpLdsBytes / 4];
+  for (uint32_t it = blockIdx.x; it < (uint32_t)A.nitems; it += gridDim.x) {
+    const int64_t g = A.item0 + it;
+    const int jd = __builtin_amdgcn_readfirstlane(find_jd(A.item_prefix, 2 * A.njobs, g));
+    const DevJob& J = A.jobs[jd >> 1];
+    const int dir = jd & 1;
+    const DevFrame& F = J.F[dir];
+    const int64_t smp = J.s0 + (g - A.item_prefix[jd]) * kItem + threadIdx.x;
+    const int s = (int)it * kItem + threadIdx.x;
+    const bool active = smp < J.s1;
+    const Rng rng{A.k0, A.k1, (uint32_t)smp, (8u << 24) | ((uint32_t)dir << 23), A.job_base + (uint32_t)(jd >> 1)};
+    float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    vec3 p = v3(0.f, 0.f, 0.f), n = v3(0.f, 0.f, 1.f);
+    uint32_t md = 0u;
+    float u[4];
+    if (active) {
+      draw(rng, 0, 0, 0, u);
+      int tri;
+      object_point(J.S, F.pose, u, p, n, md, tri);
+      mlp_input(A.mlp, pose_inv_apply(F.pose, p), pose_inv_rot(F.pose, n), x);
+    }
+    const float* raw = mlp_forward_wave(A.mlp, x, lds);
+    if (active) {
+      draw(rng, 0, 0, 2, u);
+      const vec3 wl = unit(pose_rot(F.pose, vmf_mix_sample(raw, u[0], u[1], u[2])));
+      STA(A.W, 0, s) = f4u(p, md);
+      STA(A.W, 1, s) = f4(n, 0.0f);
+      STA(A.W, 3, s) = f4(wl, 0.0f);
+    }
+    __syncthreads();  // the next item's pass overwrites the outputs
   }
 }
 
@@ -657,12 +700,13 @@ struct CCtx {
   float sigma, cweight, inv_n, alpha_min, d_min, jac_max;
   int job;
   const MlpDev* mlp;  // training-record input normalisation (collection on), else null
+  int train_weighting;
 };
 
-// q8: the proposal's densities at x_2..x_5 (technique (8) in the mask).
+// q8a, q8b: the proposal's densities at x_1..x_4 and x_5 (technique (8) in the mask).
 template <bool CW>
-DEV void connect_one(const CCtx& A, uint32_t code, float4 q8, int* stk, WorkCount& wc, float4& rec, int& reason,
-                     TrainRec& tr) {
+DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* stk, WorkCount& wc, float4& rec,
+                     int& reason, TrainRec& tr) {
   const DevScene& S = A.S;
   const Workspace& W = A.W;
   const int s = (int)(code >> 8);
@@ -850,7 +894,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8, int* stk, WorkCoun
   for (int q = kMaxK - 2; q >= 2; --q) Bsuf[q] = (q <= k - 2) ? Bsuf[q + 1] * gen(q - 1, q, q - 2) : 1.0f;
   auto on = [&](int t) { return (A.mask >> (t - 1)) & 1u; };
   float sum = 0.0f;
-  float pgen3 = 0.0f;  // technique (3): density of the generating strategy
+  float pgen = 0.0f;  // techniques (2), (3): density of the generating strategy
   if (on(7)) sum += k == 2 ? pcam : pcam * Bsuf[2] * pL;
 #pragma unroll
   for (int m = 1; m < kMaxK - 1; ++m) {
@@ -858,7 +902,12 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8, int* stk, WorkCoun
     if (m == k - 2) {
       if (on(1)) sum += pL * pD * Apre[m - 1];
     } else if (m == 1) {
-      if (on(2) && k >= 4) sum += pD * Bsuf[2] * pL;
+      if (on(2) && k >= 4) {
+        const float t2 = pD * Bsuf[2] * pL;
+        sum += t2;
+        if (T == 2) pgen = t2;
+      }
+      if (on(8)) sum += pD * q8a.x * to_area(1, 2, origin(1, 2)) * Bsuf[3] * pL;
     } else if (on(3) || on(8)) {
       const vec3 o = origin(m, m + 1);
       const vec3 w = unit(v[m + 1].p - o);
@@ -867,9 +916,9 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8, int* stk, WorkCoun
       if (on(3) && c > 0.0f) {
         const float t3 = pD * (c / kPi) * rest3;
         sum += t3;
-        if (T == 3 && m == i + 2) pgen3 = t3;
+        if (T == 3 && m == i + 2) pgen = t3;
       }
-      if (on(8)) sum += pD * (m == 2 ? q8.x : m == 3 ? q8.y : m == 4 ? q8.z : q8.w) * rest3;
+      if (on(8)) sum += pD * (m == 2 ? q8a.y : m == 3 ? q8a.z : m == 4 ? q8a.w : q8b.x) * rest3;
     }
   }
   if (motion && k >= 3) {
@@ -1030,7 +1079,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8, int* stk, WorkCoun
   }
   const float sc = A.sigma / sum * A.inv_n;
   rec = make_float4(__int_as_float(pixel | (A.job << 24)), val.x * sc, val.y * sc, val.z * sc);
-  if (A.mlp && T == 3 && pgen3 > 0.0f) {
+  if (A.mlp && (T == 2 || T == 3) && pgen > 0.0f) {
     const int m = i + 2;
     const vec3 o = origin(m, m + 1);
     const vec3 w = pose_inv_rot(A.F.pose, unit(v[m + 1].p - o));
@@ -1038,7 +1087,8 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8, int* stk, WorkCoun
     tr.w[0] = w.x;
     tr.w[1] = w.y;
     tr.w[2] = w.z;
-    tr.weight = (fabsf(val.x) + fabsf(val.y) + fabsf(val.z)) * (1.0f / 3.0f) / pgen3;
+    const float fa = (fabsf(val.x) + fabsf(val.y) + fabsf(val.z)) * (1.0f / 3.0f);
+    tr.weight = A.train_weighting == 1 ? fa / pgen * (fa / sum) : fa / pgen;
   }
 }
 
@@ -1065,11 +1115,13 @@ __global__ __launch_bounds__(kTraceBlock) void connect_kernel(WalkArgs A) {
       const DevJob& J = A.jobs[jd >> 1];
       const int dir = jd & 1;
       const CCtx C{J.S, J.F[dir], J.F[1 - dir], A.W, A.tech, A.material_mode, A.mask, dir ? -1.0f : 1.0f,
-                   A.cweight, J.inv_n, A.alpha_min, A.d_min, A.jac_max, jd >> 1, A.train ? &A.mlp : nullptr};
-      const float4 q8 = A.W.t8q ? A.W.t8q[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+                   A.cweight, J.inv_n, A.alpha_min, A.d_min, A.jac_max, jd >> 1, A.train ? &A.mlp : nullptr,
+                   A.train_weighting};
+      const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 q8a = A.W.t8q ? A.W.t8q[2 * (size_t)idx] : z4, q8b = A.W.t8q ? A.W.t8q[2 * (size_t)idx + 1] : z4;
       float4 rec;
       int reason;
-      connect_one<CW>(C, code, q8, stk, wc, rec, reason, tr);
+      connect_one<CW>(C, code, q8a, q8b, stk, wc, rec, reason, tr);
       A.W.records[idx] = rec;
       if (CW) wc.bytes += 16u;
       if (A.keep_records) {
@@ -1106,8 +1158,8 @@ __global__ __launch_bounds__(kTraceBlock) void connect_kernel(WalkArgs A) {
   if (CW) flush_work(A.stats, 8, wc);
 }
 
-// Technique (8)'s MIS term needs the proposal at every interior dynamic
-// vertex x_m (2 <= m <= k-3) of every queued path: one MLP pass per vertex
+// Technique (8)'s MIS term needs the proposal at every dynamic vertex x_m
+// with 1 <= m <= k-3 of every queued path: one MLP pass per vertex
 // position over the wave's 64 paths (matrix cores), then the mixture density
 // of the object-space direction x_m -> x_{m+1} (from the offset origin, as
 // the other MIS terms measure it).
@@ -1131,9 +1183,9 @@ __global__ __launch_bounds__(kTraceBlock) void proposal_pdf_kernel(WalkArgs A) {
       dir = jd & 1;
     }
     const Pose& pose = J->F[dir].pose;
-    float q[4] = {0.f, 0.f, 0.f, 0.f};
+    float q[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
-    for (int m = 2; m <= kMaxK - 3; ++m) {
+    for (int m = 1; m <= kMaxK - 3; ++m) {
       PV x = PV{v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 1.f), 0u}, y = x;
       bool need = act && m <= k - 3;
       if (need) {
@@ -1147,11 +1199,14 @@ __global__ __launch_bounds__(kTraceBlock) void proposal_pdf_kernel(WalkArgs A) {
       const float* raw = mlp_forward_wave(M, in, lds);
       if (need) {
         const vec3 o = spawn(J->S, x.p, x.n, y.p);
-        q[m - 2] = vmf_mix_pdf(raw, pose_inv_rot(pose, unit(y.p - o)));
+        q[m - 1] = vmf_mix_pdf(raw, pose_inv_rot(pose, unit(y.p - o)));
       }
       __syncthreads();  // the next pass overwrites the outputs
     }
-    if (act) A.W.t8q[idx] = make_float4(q[0], q[1], q[2], q[3]);
+    if (act) {
+      A.W.t8q[2 * (size_t)idx] = make_float4(q[0], q[1], q[2], q[3]);
+      A.W.t8q[2 * (size_t)idx + 1] = make_float4(q[4], 0.f, 0.f, 0.f);
+    }
   }
 }
 
@@ -1430,6 +1485,9 @@ void launch_walk(const WalkArgs& A, int blocks, hipStream_t st) {
 }
 void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st) {
   hipLaunchKernelGGL(zero_images, dim3(1024), dim3(256), 0, st, jobs, njobs);
+}
+void launch_t8_start(const WalkArgs& A, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(t8_start_kernel, dim3(blocks), dim3(kTraceBlock), 0, st, A);
 }
 void launch_proposal_pdf(const WalkArgs& A, int blocks, hipStream_t st) {
   hipLaunchKernelGGL(proposal_pdf_kernel, dim3(blocks), dim3(kTraceBlock), 0, st, A);

@@ -44,11 +44,12 @@ class Params(C.Structure):
                 ("d_min", C.c_float), ("jac_max", C.c_float), ("c_weight", C.c_float),
                 ("sample_begin", C.c_int64), ("sample_end", C.c_int64), ("queue_cap", C.c_int32),
                 ("job", C.c_uint32), ("proposal", C.c_void_p), ("d_train_records", C.c_void_p),
-                ("train_capacity", C.c_int64)]
+                ("train_capacity", C.c_int64), ("train_weighting", C.c_int32)]
 
     @staticmethod
     def make(spp, depth, seed, mask=0x7F, flags=FLAG_TWO_WAY, alpha_min=0.2, d_min=-1.0, jac_max=10.0,
-             c_weight=0.5, sample_begin=0, sample_end=-1, queue_cap=0, job=0, proposal=None, train_records=None):
+             c_weight=0.5, sample_begin=0, sample_end=-1, queue_cap=0, job=0, proposal=None, train_records=None,
+             train_weighting=0):
         """proposal: a Proposal (technique 8 with mask bit 7); train_records: a
         float32 device tensor [cap, 10] receiving technique-3 training records."""
         p = Params(spp, depth, seed, mask, flags, alpha_min, d_min, jac_max, c_weight, sample_begin,
@@ -60,6 +61,7 @@ class Params(C.Structure):
             cap = train_records.shape[0]
             p.d_train_records = _devptr(train_records, cap * TRAIN_RECORD_FLOATS).value
             p.train_capacity = cap
+        p.train_weighting = int(train_weighting)
         return p
 
 
