@@ -881,6 +881,20 @@ static V3 vmf_sample(const Lobes& L, float u0, float u1, float u2) {
   return normalize(t * (s * std::cos(ph)) + b * (s * std::sin(ph)) + mu * c);
 }
 
+// Technique (8)'s direction sampler is a defensive mixture (Hesterberg
+// 1995): with probability T8_UNIFORM a uniform direction on the sphere, else
+// the learned lobes.  The technique keeps full support where the lobes'
+// densities underflow, so it can stand in for techniques (2) and (3).
+static const float T8_UNIFORM = 0.25f;
+static V3 sphere_dir(float u0, float u1);
+static V3 t8_sample(const Lobes& L, float u0, float u1, float u2) {
+  if (u0 < T8_UNIFORM) return sphere_dir(u1, u2);
+  return vmf_sample(L, (u0 - T8_UNIFORM) / (1.0f - T8_UNIFORM), u1, u2);
+}
+static double t8_pdf(const Lobes& L, D3 w) {
+  return (double)T8_UNIFORM / (4.0 * PI) + (1.0 - (double)T8_UNIFORM) * vmf_pdf(L, w);
+}
+
 struct Proposal {
   const float* params;  // MLP_NPARAM floats, or null (technique 8 off)
   V3 center, inv_half;  // object-space bounding box normalisation
@@ -1047,7 +1061,7 @@ static double t8_dir_pdf(const Scene& S, const Path& P, const MisOpts& O, int m)
   Lobes Lb = proposal_lobes(*O.prop, pose_inv_apply(pose, P.v[m].p), pose_inv_rot(pose, P.v[m].n));
   V3 wg = normalize(P.v[m + 1].p - origin(S, P, m, m + 1));
   D3 wo = dnorm(dd(pose_inv_rot(pose, wg)));
-  return vmf_pdf(Lb, wo) * to_area(S, P, m, m + 1);
+  return t8_pdf(Lb, wo) * to_area(S, P, m, m + 1);
 }
 
 // Sum over every strategy able to produce the path: one per dynamic vertex
@@ -1528,7 +1542,8 @@ static void tech3(const Gen& g) {
 }
 
 // (8) Learned proposal: a start x_D on the object whose light-side direction
-// is drawn from the MLP's vMF mixture at x_D (object space).  On the sensor
+// is drawn from the MLP's vMF mixture at x_D (object space), made defensive
+// by a uniform-sphere component.  On the sensor
 // side x_D is either seen by the camera directly (the paths of technique
 // (2), whose BSDF direction the mixture replaces) or followed, as in
 // technique (3), by a BSDF direction towards the sensor and an eye walk.
@@ -1539,7 +1554,7 @@ static void tech8(const Gen& g, const Proposal& Pr) {
   if (g.depth < 3 || !Pr.params) return;
   Lobes Lb = proposal_lobes(Pr, pose_inv_apply(g.F.pose, xd.p), pose_inv_rot(g.F.pose, xd.n));
   g.rng.draw(0, 0, 2, u);
-  V3 wobj = vmf_sample(Lb, u[0], u[1], u[2]);
+  V3 wobj = t8_sample(Lb, u[0], u[1], u[2]);
   V3 wl = normalize(pose_rot(g.F.pose, wobj));
   V3 ol = spawn_dir(g.S, xd.p, xd.n, wl);
   Hit hl = closest(g.S, g.F.pose, ol, wl);
@@ -1547,7 +1562,7 @@ static void tech8(const Gen& g, const Proposal& Pr) {
   PV l0{hl.p, hl.n, hl.mat, hl.dyn};
   D3 dl = dd(l0.p) - dd(ol);
   D3 wq = dnorm(dd(pose_inv_rot(g.F.pose, normalize(l0.p - ol))));
-  double pl = vmf_pdf(Lb, wq) * std::fabs(ddot(dd(l0.n), dnorm(dl))) / dlen2(dl);
+  double pl = t8_pdf(Lb, wq) * std::fabs(ddot(dd(l0.n), dnorm(dl))) / dlen2(dl);
   // the sensor sees x_D (the support test of the assembled paths checks the sides)
   Path C;
   C.v[0] = PV{g.S.cam.eye, g.S.cam.fwd, -1, false};

@@ -115,3 +115,24 @@ def test_technique8_keeps_the_estimator_unbiased(oracle_lib):
     assert (np.abs(z) < 3).mean() > 0.97
     zm = (ma.mean() - mb.mean()) / (np.sqrt((sa ** 2).sum() + (sb ** 2).sum()) / ma.size)
     assert abs(zm) < 3.5
+
+
+def test_technique8_alone_stays_unbiased_with_sharp_lobes(oracle_lib):
+    # Technique 8 in place of techniques 2 and 3: its defensive uniform-sphere
+    # component must cover the directions that sharp lobes (kappa ~ 200) never
+    # reach in fp32 sampling.
+    w = scenes.cornell_material(width=8, height=8, depth=5)
+    o = oracle_lib.OracleScene(w.scene)
+    P = oracle_lib.mlp_init(7)
+    for lobe in range(8):
+        P[11328 + 5 * lobe + 3] = 200.0
+    kw = dict(material_mode=True, new_mat=w.edit.new_material, two_way=False, threads=8)
+    A = np.array([o.render_residual(48, 5, s, mask=0x07, **kw)["image"] for s in range(300, 316)])
+    B = np.array([o.render_residual(48, 5, s, mask=0x81, mlp=P, **kw)["image"] for s in range(400, 416)])
+    ma, mb = A.mean(0), B.mean(0)
+    sa, sb = A.std(0, ddof=1) / 4, B.std(0, ddof=1) / 4
+    zm = (ma.mean() - mb.mean()) / (np.sqrt((sa ** 2).sum() + (sb ** 2).sum()) / ma.size)
+    assert abs(zm) < 3.5, zm
+    sig = np.sqrt(sa ** 2 + sb ** 2)
+    m = sig > 0
+    assert (np.abs((ma - mb)[m] / sig[m]) < 3).mean() > 0.97
