@@ -39,7 +39,7 @@ class Params(C.Structure):
 RECORD_DTYPE = np.dtype([("dir", "<i4"), ("tech", "<i4"), ("sample", "<u4"), ("k", "<i4"),
                          ("pixel", "<i4"), ("reason", "<i4"), ("n_starts", "<i4"), ("pair", "<i4"),
                          ("val", "<f8", 3), ("mis_total", "<f8"), ("mis_tech", "<f8"),
-                         ("p_gen", "<f8"), ("train", "<f8", 10)])
+                         ("p_gen", "<f8"), ("train", "<f8", 10), ("mis_by_tech", "<f8", 9)])
 
 MLP_NPARAM = 11368
 

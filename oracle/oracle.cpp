@@ -649,7 +649,8 @@ static Seg edge_seg(const Scene& S, const Path& P, int a) {
   return s;
 }
 
-// Ghost crossings of an edge: count and sums of 1/|cos_g|, |g-A|^2/|cos_g|, |g-B|^2/|cos_g|.
+// Ghost crossings of an edge: count (canonical segment) and, over the
+// crossings of the generating line, sums of 1/|cos_g|, |g-A|^2/|cos_g|, |g-B|^2/|cos_g|.
 struct Cross {
   int n;
   double s0, sa, sb;
@@ -669,12 +670,17 @@ static Cross crossings(const Scene& S, const Frame& F, const Path& P, int a) {
   for (auto& h : hits) {
     // crossing point on the generating line where it meets that triangle
     V3 g = s.o + s.d * h.first;
+    c.n += 1;
     if (!envB) {
+      // a ghost technique generates this edge from a point of that triangle
+      // only if the generating line itself crosses it between the ends: other
+      // crossings of the canonical segment (near an end, where it leaves the
+      // line by the offsets) mark the edge dynamic but carry no density
       float tl = tri_t(pose_inv_apply(F.ghost, A), pose_inv_rot(F.ghost, B - A), S.obj[h.second]);
-      if (tl > 0.0f) g = A + (B - A) * tl;
+      if (!(tl > 0.0f && tl < 1.0f)) continue;
+      g = A + (B - A) * tl;
     }
     double cg = std::fabs(ddot(dd(pose_rot(F.ghost, S.obj[h.second].n)), u));
-    c.n += 1;
     c.s0 += 1.0 / cg;
     c.sa += dlen2(dd(g) - dd(A)) / cg;
     c.sb += envB ? 0.0 : dlen2(dd(g) - dd(B)) / cg;
@@ -1770,8 +1776,9 @@ struct Record {
   int32_t k, pixel, reason, n_starts, pad;
   double val[3];
   double mis_total, mis_tech, p_gen;
-  // technique (3) paths: proposal training record {x[6], w_obj[3], weight}
+  // techniques (2)/(3): proposal training record {x[6], w_obj[3], weight}
   double train[10];
+  double mis_by_tech[9];  // every strategy's term of mis_total
 };
 
 struct Stats {
@@ -1890,6 +1897,7 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
         r.val[2] = val.z;
         r.mis_total = mt.total;
         r.mis_tech = mt.by_tech[tech];
+        for (int t = 0; t < 9; ++t) r.mis_by_tech[t] = mt.by_tech[t];
         r.p_gen = X.p_gen;
         if (tech == 2 || tech == 3) train_record(S, F, *prop, X, unweighted, r.train);
         recs->push_back(r);

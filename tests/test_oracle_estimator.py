@@ -291,3 +291,30 @@ def test_depth2_residual_matches_quadrature(oracle_lib):
                       range(60, 68))
     ferr = np.abs(q2f - q2c)
     assert (np.abs(F2 - q2f) <= 3 * fse + ferr + 1e-7).mean() > 0.95
+
+
+# --- every strategy's MIS term integrates to what the strategy generates -------
+
+def test_strategy_terms_integrate_to_generated_paths(oracle_lib):
+    """Path tracing (7) reaches every dynamic path, so summing another
+    strategy's MIS term over technique-7 paths, each divided by its
+    technique-7 density, estimates how many paths that strategy generates per
+    sample; it must match the count the strategy actually produces.  A term
+    that counts configurations its sampler cannot reach (e.g. a ghost crossing
+    the generating line misses) shows up as a ratio above one.  The scene is
+    the clutter scene's moving sphere, whose ghost meets the object at an
+    angle."""
+    w = scenes.clutter_motion(width=16, height=16, depth=5, n_spheres=0)
+    o = oracle_lib.OracleScene(w.scene)
+    spp = 1024  # the estimate through technique 7 scatters by about 6% here
+    N = spp * 16 * 16
+    r = o.render_residual(spp, 5, 11, pose_new=w.edit.old_to_new, mask=0x7F, records=True, two_way=False,
+                          rec_cap=20_000_000, threads=1)
+    rec = r["records"]
+    r7 = rec[rec["tech"] == 7]
+    for t, tol in ((1, 0.2), (2, 0.2), (4, 0.2), (5, 0.2), (6, 0.2)):
+        direct = (rec["tech"] == t).sum() / N
+        est = (r7["mis_by_tech"][:, t] / r7["p_gen"]).sum() / N
+        print("technique %d: %.4f paths/sample, %.4f through technique 7" % (t, direct, est))
+        assert direct > 0.01
+        assert abs(est / direct - 1) < tol, (t, direct, est)
