@@ -25,7 +25,9 @@ METRIC = "residual paths/s & Mrays/s at 1 GPU; equal-time residual MSE vs plain 
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES = 64, 48
 KERNEL_NAMES = {1: "walk_kernel<1>", 2: "walk_kernel<2>", 3: "walk_kernel<3>", 4: "walk_kernel<4>",
-                5: "walk_kernel<5>", 6: "walk_kernel<6>", 7: "walk_kernel<7>", 8: "connect_kernel", 9: "splat"}
+                5: "walk_kernel<5>", 6: "walk_kernel<6>", 7: "walk_kernel<7>", 8: "connect_kernel", 9: "splat",
+                11: "walk_kernel<8>", 12: "proposal_pdf_kernel", 13: "t8_start_kernel"}
+KIDS = sorted(KERNEL_NAMES)
 
 
 def parse():
@@ -114,7 +116,7 @@ def main():
 
     # dominant kernel: largest share of device time; algorithmic bytes per launch =
     # (BVH nodes x 64 B + triangles x 48 B + record bytes written) of that kernel
-    kid = int(np.argmax(kms[1:10])) + 1
+    kid = max(KIDS, key=lambda k: kms[k])
     kbytes = (cw["kernel_nodes"][kid] * NODE_BYTES + cw["kernel_tris"][kid] * TRI_BYTES
               + cw["kernel_bytes_written"][kid])
     launches = max(klaunch[kid] / args.steps, 1)
@@ -124,7 +126,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": KERNEL_NAMES[kid], "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": int(kbytes / launches),
-                "device_time_share": round(float(kms[kid] / kms[1:10].sum()), 3)}
+                "device_time_share": round(float(kms[kid] / kms[KIDS].sum()), 3)}
     line = {"metric": METRIC, "value": round(value, 1), "unit": "residual paths/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -138,7 +140,7 @@ def main():
             "paths_per_step": int(paths_per_step), "rays_per_step": int(rays_per_step),
             "rays_by_type": {k: int(v) for k, v in zip(["closest", "shadow", "camera", "ghost", "map_retrace",
                                                          "map_visibility"], cw["rays"])},
-            "kernel_ms_per_step": {KERNEL_NAMES[k]: round(kms[k] / args.steps, 2) for k in range(1, 10)},
+            "kernel_ms_per_step": {KERNEL_NAMES[k]: round(kms[k] / args.steps, 2) for k in KIDS if kms[k] > 0},
             "roofline": roofline}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

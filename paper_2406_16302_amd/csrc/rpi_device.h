@@ -447,13 +447,16 @@ DEV Cross edge_cross(const DevScene& S, const DevFrame& F, const End& A, const E
       const float t = tri_t(go, gd, v0, e1, e2);
       if (!(t > 0.0f && t < tmax)) continue;
       vec3 g = s.o + s.d * t;
+      c.n += 1.0f;
       if (!env) {
+        // density only where the generating line itself crosses the triangle
+        // between the ends (the ghost techniques generate the edge along it)
         const float tl = tri_t(la, ld, v0, e1, e2);
-        if (tl > 0.0f) g = a + (b - a) * tl;
+        if (!(tl > 0.0f && tl < 1.0f)) continue;
+        g = a + (b - a) * tl;
       }
       const vec3 ng = pose_rot(F.ghost, unit(cross(e1, e2)));
       const float cg = fabsf(dot(ng, u));
-      c.n += 1.0f;
       c.s0 += 1.0f / cg;
       c.sa += len2(g - a) / cg;
       c.sb += env ? 0.0f : len2(g - b) / cg;

@@ -617,7 +617,7 @@ __global__ __launch_bounds__(kTraceBlock) void walk_kernel(WalkArgs A) {
 
 // Technique (8), first half: x_D by area, the proposal at x_D (one MLP pass
 // per wave on the matrix cores) and the light-side direction drawn from its
-// vMF mixture, into start records 0 (x_D, material), 1 (normal) and 3 (the
+// vMF mixture (made defensive by a uniform-sphere component), into start records 0 (x_D, material), 1 (normal) and 3 (the
 // direction) of the sample's slot; walk_kernel<8> continues from there.
 // Items map to slots as in the walk kernel: item it, lane l -> it * 64 + l.
 __global__ __launch_bounds__(kTraceBlock) void t8_start_kernel(WalkArgs A) {
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(kTraceBlock) void t8_start_kernel(WalkArgs A) {
     const float* raw = mlp_forward_wave(A.mlp, x, lds);
     if (active) {
       draw(rng, 0, 0, 2, u);
-      const vec3 wl = unit(pose_rot(F.pose, vmf_mix_sample(raw, u[0], u[1], u[2])));
+      const vec3 wl = unit(pose_rot(F.pose, t8_dir_sample(raw, u[0], u[1], u[2])));
       STA(A.W, 0, s) = f4u(p, md);
       STA(A.W, 1, s) = f4(n, 0.0f);
       STA(A.W, 3, s) = f4(wl, 0.0f);
@@ -1199,7 +1199,7 @@ __global__ __launch_bounds__(kTraceBlock) void proposal_pdf_kernel(WalkArgs A) {
       const float* raw = mlp_forward_wave(M, in, lds);
       if (need) {
         const vec3 o = spawn(J->S, x.p, x.n, y.p);
-        q[m - 1] = vmf_mix_pdf(raw, pose_inv_rot(pose, unit(y.p - o)));
+        q[m - 1] = t8_dir_pdf(raw, pose_inv_rot(pose, unit(y.p - o)));
       }
       __syncthreads();  // the next pass overwrites the outputs
     }
@@ -1441,6 +1441,7 @@ __global__ __launch_bounds__(kTraceBlock) void frame_kernel(FrameArgs A) {
       const float G = fabsf(dot(n, du)) * fabsf(dot(qn, du)) / len2(d);
       const vec3 dq = q - o;
       const float pa = bsdf_pdf(mt, n, wi, wo) * fabsf(dot(qn, unit(dq))) / len2(dq);
+      if (!(pa > 0.0f)) break;  // a direction of zero density (rounding at grazing angles) ends the walk
       beta = vmul(beta, rho) * (G / pa);
       prev = p;
       p = q;

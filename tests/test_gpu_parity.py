@@ -97,3 +97,33 @@ def test_chunked_queue_gives_same_image():
     a = gpu_residual(ws)["image"]
     b = gpu_residual(ws, queue_cap=999)["image"]
     assert np.allclose(a, b, rtol=1e-5, atol=1e-7 * np.abs(a).max())
+
+
+def test_motion_residual_matches_frame_difference_at_bench_scene():
+    """The residual of the clutter-motion edit (the benchmark's scene, at
+    128x128) against the difference of the two frames rendered independently
+    by path tracing, over the image sum: a strategy whose MIS term disagrees
+    with what it generates would move the residual away from it."""
+    from paper_2406_16302_amd import native
+    ws = scenes.clutter_motion(width=128, height=128, depth=5)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    frames = []
+    for c in range(8):
+        f1 = torch.zeros((128, 128, 3), dtype=torch.float32, device="cuda")
+        f2 = torch.zeros_like(f1)
+        p = native.Params.make(4096, 5, 80_000 + c)
+        native.render_frame(sc, ed, 1, p, f1)
+        native.render_frame(sc, ed, 2, p, f2)
+        frames.append((f2.double() - f1.double()).sum().item())
+    res = []
+    for k in range(16):
+        out = torch.zeros((128, 128, 3), dtype=torch.float32, device="cuda")
+        native.render_residual(sc, ed, native.Params.make(64, 5, 3000 + 71 * k, flags=native.FLAG_TWO_WAY), out)
+        res.append(out.double().sum().item())
+    fm, fs = np.mean(frames), np.std(frames, ddof=1) / np.sqrt(len(frames))
+    rm, rs = np.mean(res), np.std(res, ddof=1) / np.sqrt(len(res))
+    z = (rm - fm) / np.hypot(fs, rs)
+    print("frames %.4f +- %.3f  residual %.4f +- %.3f  z %.2f" % (fm, fs, rm, rs, z))
+    assert np.isfinite(frames).all()
+    assert abs(z) < 4
