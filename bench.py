@@ -14,8 +14,10 @@ of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,7 +40,48 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="a reduced workload (quick checks only)")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only a device-to-device copy of 1 GiB, three times (HBM counter calibration)")
     return ap.parse_args()
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "walk_kernel6_clutter_motion_512x512_d5_hbm_traffic.md")
+KERNEL_SOURCES = ["rpi_kernels.hip", "rpi_device.h", "rpi_internal.h", "rpi_mlp.h"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_2406_16302_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            m = re.search(r"```json\n(.*?)\n```", fh.read(), re.S)
+        rec = json.loads(m.group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def copy_only():
+    import torch
+    n = 1 << 28  # float32 elements: 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
 
 
 def workload(small):
@@ -74,6 +117,9 @@ def log(msg):
 
 def main():
     args = parse()
+    if args.copy_only:
+        copy_only()
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported (the estimator shards "
               "sample ranges across GPUs only by design, see DESIGN.md)" % args.gpus, file=sys.stderr)
@@ -122,8 +168,9 @@ def main():
     launches = max(klaunch[kid] / args.steps, 1)
     avg_ms = kms[kid] / max(klaunch[kid], 1)
     achieved = (kbytes / launches) / (avg_ms / 1e3) / 1e9
+    traffic = None if args.small else measured_traffic(KERNEL_NAMES[kid])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_NAMES[kid], "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": int(kbytes / launches),
                 "device_time_share": round(float(kms[kid] / kms[KIDS].sum()), 3)}

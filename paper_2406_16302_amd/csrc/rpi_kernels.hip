@@ -575,8 +575,22 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 // Persistent walk kernel: each wave pulls 64-sample work items (job,
 // direction, sample range) from a round counter until the round is drained,
 // which balances jobs of uneven image size and uneven per-sample cost.
+// Occupancy target of the trace-heavy kernels (waves per SIMD; 0 leaves the
+// register allocation to the compiler).  The 12 KB LDS stack per wave already
+// limits a compute unit to 13 waves, about 3 per SIMD; asking for 3 caps the
+// registers of the kernels that would otherwise run at 2 (technique 7: -20%
+// time).  Asking for 4 spills without gaining occupancy.
+#ifndef RPI_TRACE_WAVES_PER_EU
+#define RPI_TRACE_WAVES_PER_EU 3
+#endif
+#if RPI_TRACE_WAVES_PER_EU > 0
+#define RPI_TRACE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_TRACE_WAVES_PER_EU)))
+#else
+#define RPI_TRACE_OCCUPANCY
+#endif
+
 template <int TECH, bool CW>
-__global__ __launch_bounds__(kTraceBlock) void walk_kernel(WalkArgs A) {
+__global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   for (;;) {
     uint32_t it = 0;
@@ -1093,7 +1107,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
 }
 
 template <bool CW>
-__global__ __launch_bounds__(kTraceBlock) void connect_kernel(WalkArgs A) {
+__global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void connect_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   __shared__ unsigned long long cnt[16];
   if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
