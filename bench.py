@@ -26,9 +26,9 @@ import numpy as np
 METRIC = "residual paths/s & Mrays/s at 1 GPU; equal-time residual MSE vs plain GPU path"
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES = 64, 48
-KERNEL_NAMES = {1: "walk_kernel<1>", 2: "walk_kernel<2>", 3: "walk_kernel<3>", 4: "walk_kernel<4>",
-                5: "walk_kernel<5>", 6: "walk_kernel<6>", 7: "walk_kernel<7>", 8: "connect_kernel", 9: "splat",
-                11: "walk_kernel<8>", 12: "proposal_pdf_kernel", 13: "t8_start_kernel"}
+KERNEL_NAMES = {t: "walk_kernel<%d>" % t for t in range(1, 9)}          # start phase of technique t
+KERNEL_NAMES.update({16 + t: "walk_task_kernel<%d>" % t for t in range(1, 9)})  # its walk phase
+KERNEL_NAMES.update({9: "connect_kernel", 10: "splat", 12: "proposal_pdf_kernel", 13: "t8_start_kernel"})
 KIDS = sorted(KERNEL_NAMES)
 
 
@@ -143,8 +143,8 @@ def main():
         native.render_residual(sc, ed, params(0), out)
     torch.cuda.synchronize()
     log("warmup done")
-    kms = np.zeros(16)
-    klaunch = np.zeros(16)
+    kms = np.zeros(32)
+    klaunch = np.zeros(32)
     paths = []
     t0 = time.perf_counter()
     for _ in range(args.steps):

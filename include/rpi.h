@@ -125,16 +125,16 @@ typedef struct {
   int64_t nodes_visited;  /* with RPI_FLAG_COUNT_WORK */
   int64_t tris_tested;    /* with RPI_FLAG_COUNT_WORK */
   double milliseconds;    /* device time of the call (when stats are requested) */
-  /* Per kernel: index t = 1..7 walk kernel of technique t, 8 connect, 9 splat
-   * (all splat kernels of a chunk), 10 frame, 11 walk kernel of technique 8,
-   * 12 proposal densities for the MIS sums, 13 technique-8 starts (MLP).  ms/launches with
-   * RPI_FLAG_TIME_KERNELS; node/triangle fetches and record bytes written
-   * with RPI_FLAG_COUNT_WORK. */
-  double kernel_ms[16];
-  int64_t kernel_launches[16];
-  int64_t kernel_nodes[16];
-  int64_t kernel_tris[16];
-  int64_t kernel_bytes_written[16];
+  /* Per kernel: index t = 1..8 start phase of technique t, 16 + t its walk
+   * phase, 9 connect, 10 splat (all splat kernels of a chunk), 11 frame,
+   * 12 proposal densities for the MIS sums, 13 technique-8 starts (MLP).
+   * ms/launches with RPI_FLAG_TIME_KERNELS; node/triangle fetches and bytes
+   * written with RPI_FLAG_COUNT_WORK. */
+  double kernel_ms[32];
+  int64_t kernel_launches[32];
+  int64_t kernel_nodes[32];
+  int64_t kernel_tris[32];
+  int64_t kernel_bytes_written[32];
   int64_t train_records;  /* training records produced (may exceed train_capacity) */
 } rpi_stats;
 

@@ -724,6 +724,8 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   const size_t o_tj = take((size_t)ntiles * 4);
   const size_t o_ic = take(256);
   const size_t o_tc2 = take(256);
+  const size_t o_task = take((size_t)kTaskFields * Q * sizeof(float4));
+  const size_t o_nt = take(256);
   w.bytes = off;
   w.async = async;
   if (async) HIP_OK(hipMallocAsync(&w.mem, off, st));
@@ -739,6 +741,8 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   w.W.rec_keys = keep ? (uint32_t*)(b + o_keys) : nullptr;
   w.W.rec_sample = keep ? (uint32_t*)(b + o_ks) : nullptr;
   w.W.t8q = t8 ? (float4*)(b + o_t8) : nullptr;
+  w.W.task = (float4*)(b + o_task);
+  w.W.ntasks = (uint32_t*)(b + o_nt);
   w.W.Q = Q;
   w.W.pair_cap = pair_cap;
   w.W.nslot = nslot;
@@ -962,21 +966,26 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       A.nitems = (int)std::min<int64_t>(R, T - i0);
       launch_zero_u32(w.W.npairs, 1, st);
       launch_zero_u32(w.item_counter, 1, st);
+      launch_zero_u32(w.W.ntasks, 1, st);
       const int blocks = std::min<int64_t>(wblocks, A.nitems);
       rpi_status r;
       if (t == 8) {
-        r = timed(13, [&] { launch_t8_start(A, std::min<int64_t>(cblocks, A.nitems), st); });
+        r = timed(kKidT8Start, [&] { launch_t8_start(A, std::min<int64_t>(cblocks, A.nitems), st); });
         if (r) return r;
       }
-      r = timed(t == 8 ? 11 : t, [&] { launch_walk(A, blocks, st); });
+      r = timed(kid_start(t), [&] { launch_walk(A, blocks, st); });
       if (r) return r;
+      if (split_walks(t)) {
+        r = timed(kid_walk(t), [&] { launch_walk_tasks(A, blocks, st); });
+        if (r) return r;
+      }
       if (t8) {
-        r = timed(12, [&] { launch_proposal_pdf(A, cblocks, st); });
+        r = timed(kKidProposalPdf, [&] { launch_proposal_pdf(A, cblocks, st); });
         if (r) return r;
       }
-      r = timed(8, [&] { launch_connect(A, cblocks, st); });
+      r = timed(kKidConnect, [&] { launch_connect(A, cblocks, st); });
       if (r) return r;
-      r = timed(9, [&] { launch_splat(sa, st); });
+      r = timed(kKidSplat, [&] { launch_splat(sa, st); });
       if (r) return r;
       if (o.keep && rec_out) {
         uint32_t n = 0;
@@ -1030,7 +1039,7 @@ static void fill_stats(rpi_stats* stats, const DevStats& ds, const Plan& pl, con
   stats->nodes_visited = (int64_t)ds.nodes;
   stats->tris_tested = (int64_t)ds.tris;
   for (int q = 0; q < 6; ++q) stats->rays[q] = (int64_t)ds.rays[q];
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < kKernelSlots; ++q) {
     stats->kernel_nodes[q] = (int64_t)ds.knodes[q];
     stats->kernel_tris[q] = (int64_t)ds.ktris[q];
     stats->kernel_bytes_written[q] = (int64_t)ds.kbytes[q];

@@ -117,6 +117,7 @@ struct DevFrame {
 constexpr int kEyeFields = 4;    // pos+md, nrm+pred.n, pred sums+flags, camera-edge crossings
 constexpr int kLightFields = 6;  // pos+md, nrm+pred.n, pred sums+flags, light pos+md, light nrm+nee.n, nee sums+ok
 constexpr int kStartFields = 5;  // mid pos+md, mid nrm+cam.n, cam sums, x_L pos+md, x_L nrm
+constexpr int kTaskFields = 11;  // slot+flags, light walk start (5), eye walk start (5)
 
 struct Workspace {
   float4* eye;
@@ -128,6 +129,8 @@ struct Workspace {
   float4* records;     // per queued path: pixel (int bits), rgb
   uint32_t* rec_keys;  // optional: dir | tech << 1 | pair << 8  (debug records)
   uint32_t* rec_sample;
+  float4* task;        // walk tasks (start phase -> walk phase), SoA: task[field * Q + t]
+  uint32_t* ntasks;    // [1] task queue length
   float4* t8q;         // technique (8) on: per queued path (2 float4), the proposal's
                        // solid-angle density at vertices x_1 .. x_5 (0 where not used)
   int32_t Q;           // samples per chunk
@@ -151,6 +154,19 @@ struct DevJob {
 };
 
 constexpr int kItem = 64;  // samples per work item (one wave)
+
+// Kernel slots of the per-kernel statistics: 1..8 start phase of technique
+// t, 17..24 its walk phase, then connect, splat, frame, the proposal's
+// densities and technique 8's MLP starts.
+constexpr int kKernelSlots = 32;
+constexpr int kKidConnect = 9, kKidSplat = 10, kKidFrame = 11, kKidProposalPdf = 12, kKidT8Start = 13;
+RPI_HD constexpr int kid_start(int t) { return t; }
+RPI_HD constexpr int kid_walk(int t) { return 16 + t; }
+// Techniques whose walks run in a separate phase over the compacted task
+// queue: those whose starts fail often (ghost and two-ended starts, the
+// camera test of technique 2).  Techniques 1, 4 and 7 walk after most starts
+// and run faster in one kernel (measured).
+RPI_HD constexpr bool split_walks(int t) { return !(t == 1 || t == 4 || t == 7); }
 constexpr int kTechs = 8;  // techniques 1..6 of Sec. 4, 7 = path tracing, 8 = learned proposal
 
 // Device view of a learned proposal (technique 8): the MLP's BF16 weights in
@@ -173,7 +189,7 @@ struct MlpDev {
 
 struct DevStats {
   unsigned long long paths, accepted, rejected[7], by_tech[9], rays[6], nodes, tris, samples;
-  unsigned long long knodes[16], ktris[16], kbytes[16];
+  unsigned long long knodes[kKernelSlots], ktris[kKernelSlots], kbytes[kKernelSlots];
 };
 
 // One round of the estimator for one technique: work items g in
@@ -231,7 +247,8 @@ struct FrameArgs {
 };
 
 // launchers (rpi_kernels.hip)
-void launch_walk(const WalkArgs& A, int blocks, hipStream_t st);
+void launch_walk(const WalkArgs& A, int blocks, hipStream_t st);        // start phase (persistent over items)
+void launch_walk_tasks(const WalkArgs& A, int blocks, hipStream_t st);  // walk phase (over the task queue)
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st);
 void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st);
 void launch_splat(const SplatArgs& a, hipStream_t st);

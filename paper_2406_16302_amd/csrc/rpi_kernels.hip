@@ -53,6 +53,18 @@ struct Ctx {
   int depth;
 };
 
+// A random walk the start phase of a technique hands to its walk phase:
+// start vertex, crossings of the edge into it, the neighbour on the other
+// side (towards the camera for a light walk, towards the light for an eye
+// walk) and the last slot.
+struct WalkStart {
+  vec3 p, n;
+  uint32_t md;
+  Cross pred;
+  End end;
+  int lim;
+};
+
 struct Lane {
   const Ctx& A;
   Rng g;
@@ -61,9 +73,22 @@ struct Lane {
   WorkCount wc;
   int nE, nL;
   uint32_t camok, neeok, dynpre;
-  int k2;  // path tracing saw an emitter / the environment at x_1
+  int k2;  // path tracing saw an emitter / the environment at x_1; technique 8: the camera sees x_D
   int64_t sample;  // sample index within its (technique, direction) stream
+  uint32_t defer;  // walks left for the walk phase: bit 0 light, bit 1 eye
+  WalkStart lw, ew;
 };
+
+DEV void defer_light(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End prev0, int jmax) {
+  if (jmax < 0) return;
+  L.lw = WalkStart{p0, n0, md0, pred0, prev0, jmax};
+  L.defer |= 1u;
+}
+DEV void defer_eye(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End next0, int imax) {
+  if (imax < 0) return;
+  L.ew = WalkStart{p0, n0, md0, pred0, next0, imax};
+  L.defer |= 2u;
+}
 
 // Extend a walk from (p, n, md) whose other neighbour lies in direction wi.
 template <bool CW>
@@ -215,7 +240,7 @@ DEV void tech1(Lane& L) {
   if (!edge_visible<CW>(S, A.F, end_surf(p, n), eL, L.stk, L.wc, RAY_SHADOW)) return;
   const Cross c = edge_cross<CW>(S, A.F, end_surf(p, n), eL, L.stk, L.wc);
   store_xl(L, E);
-  eye_walk<CW>(L, p, n, md, c, eL, A.depth - 2);
+  defer_eye(L, p, n, md, c, eL, A.depth - 2);
 }
 
 // (2) dynamic from sensor
@@ -240,7 +265,7 @@ DEV void tech2(Lane& L) {
   if (!extend<CW>(L, p, n, md, unit(S.cam.eye - p), u, q, qn, qmd)) return;
   store_mid(L, p, n, md, cam, 1u);
   const Cross pred = edge_cross<CW>(S, A.F, xd, end_surf(q, qn), L.stk, L.wc);
-  light_walk<CW>(L, q, qn, qmd, pred, xd, A.depth - 3, false);
+  defer_light(L, q, qn, qmd, pred, xd, A.depth - 3);
 }
 
 // (3) dynamic two ends: cosine lobe about the outward normal towards the
@@ -282,8 +307,8 @@ DEV void tech3(Lane& L) {
   store_mid(L, p, n, md, no_cross(), 1u);
   const Cross ce = edge_cross<CW>(S, A.F, end_surf(e0, e0n), xd, L.stk, L.wc);
   const Cross cl = edge_cross<CW>(S, A.F, xd, end_surf(l0, l0n), L.stk, L.wc);
-  light_walk<CW>(L, l0, l0n, l0md, cl, xd, A.depth - 4, false);
-  eye_walk<CW>(L, e0, e0n, e0md, ce, xd, A.depth - 4);
+  defer_light(L, l0, l0n, l0md, cl, xd, A.depth - 4);
+  defer_eye(L, e0, e0n, e0md, ce, xd, A.depth - 4);
 }
 
 // (8) learned proposal: x_D and its light-side direction come from the start
@@ -318,7 +343,7 @@ DEV void tech8(Lane& L) {
   store_mid(L, p, n, md, cam, 1u);
   const Cross cl = edge_cross<CW>(S, A.F, xd, end_surf(l0, l0n), L.stk, L.wc);
   // one bounce further when the camera sees x_D (paths x_0 x_D l_0 .. l_j)
-  light_walk<CW>(L, l0, l0n, l0md, cl, xd, L.k2 ? A.depth - 3 : A.depth - 4, false);
+  defer_light(L, l0, l0n, l0md, cl, xd, L.k2 ? A.depth - 3 : A.depth - 4);
   // a BSDF direction towards the sensor; its incoming direction is x_{m+1}
   if (A.depth < 4) return;
   float u[4];
@@ -334,7 +359,7 @@ DEV void tech8(Lane& L) {
   hit_vertex(S, A.F.pose, he, oe, we, e0, e0n, e0md);
   if (is_emitter(S, e0md)) return;
   const Cross ce = edge_cross<CW>(S, A.F, end_surf(e0, e0n), xd, L.stk, L.wc);
-  eye_walk<CW>(L, e0, e0n, e0md, ce, xd, A.depth - 4);
+  defer_eye(L, e0, e0n, e0md, ce, xd, A.depth - 4);
 }
 
 // (4) ghost from emitter: the ray x_L -> x_G gives the first vertex.
@@ -365,7 +390,7 @@ DEV void tech4(Lane& L) {
   if (!ghost_on_edge(L, x1, eL, tri)) return;
   const Cross c = edge_cross<CW>(S, A.F, x1, eL, L.stk, L.wc);
   store_xl(L, E);
-  eye_walk<CW>(L, q, qn, qmd, c, eL, A.depth - 2);
+  defer_eye(L, q, qn, qmd, c, eL, A.depth - 2);
 }
 
 // (5) ghost from sensor: the camera ray through x_G gives x_1.
@@ -392,7 +417,7 @@ DEV void tech5(Lane& L) {
   const End e0 = end_eye(S), x1 = end_surf(q, qn);
   if (!ghost_on_edge(L, e0, x1, tri)) return;
   const Cross c = edge_cross<CW>(S, A.F, e0, x1, L.stk, L.wc);
-  light_walk<CW>(L, q, qn, qmd, c, e0, A.depth - 2, false);
+  defer_light(L, q, qn, qmd, c, e0, A.depth - 2);
 }
 
 // (6) ghost two ends: a uniform direction through x_G, rays both ways.
@@ -424,8 +449,8 @@ DEV void tech6(Lane& L) {
   const End ee = end_surf(e0, e0n), el = end_surf(l0, l0n);
   if (!ghost_on_edge(L, ee, el, tri)) return;
   const Cross c = edge_cross<CW>(S, A.F, ee, el, L.stk, L.wc);
-  light_walk<CW>(L, l0, l0n, l0md, c, ee, A.depth - 3, false);
-  eye_walk<CW>(L, e0, e0n, e0md, c, el, A.depth - 3);
+  defer_light(L, l0, l0n, l0md, c, ee, A.depth - 3);
+  defer_eye(L, e0, e0n, e0md, c, el, A.depth - 3);
 }
 
 // (7) path tracing with static paths rejected (and tech 0: plain frames).
@@ -473,7 +498,7 @@ DEV void tech7(Lane& L) {
   }
   if (raster(S.cam, q) < 0) return;
   const Cross c = edge_cross<CW>(S, A.F, e0, end_surf(q, qn), L.stk, L.wc);
-  light_walk<CW>(L, q, qn, qmd, c, e0, A.depth - 2, false);
+  defer_light(L, q, qn, qmd, c, e0, A.depth - 2);
 }
 
 // Number of connected paths of a sample and the i-th of them.
@@ -589,6 +614,30 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 #define RPI_TRACE_OCCUPANCY
 #endif
 
+// ------------------------------------------------------------------ walk tasks
+
+DEV float4& TSK(const Workspace& W, int field, uint32_t t) { return W.task[(size_t)field * W.Q + t]; }
+
+DEV void store_walk(const Workspace& W, int f0, uint32_t t, const WalkStart& w) {
+  TSK(W, f0, t) = f4u(w.p, w.md);
+  TSK(W, f0 + 1, t) = f4u(w.n, (uint32_t)w.lim);
+  TSK(W, f0 + 2, t) = make_float4(w.pred.n, w.pred.s0, w.pred.sa, w.pred.sb);
+  TSK(W, f0 + 3, t) = f4u(w.end.p, (uint32_t)w.end.kind);
+  TSK(W, f0 + 4, t) = f4(w.end.n, 0.0f);
+}
+DEV WalkStart load_walk(const Workspace& W, int f0, uint32_t t) {
+  const float4 a = TSK(W, f0, t), b = TSK(W, f0 + 1, t), c = TSK(W, f0 + 2, t), d = TSK(W, f0 + 3, t),
+               e = TSK(W, f0 + 4, t);
+  return WalkStart{xyz(a), xyz(b), __float_as_uint(a.w), Cross{c.x, c.y, c.z, c.w},
+                   End{xyz(d), xyz(e), (int)__float_as_uint(d.w)}, (int)__float_as_uint(b.w)};
+}
+
+// Start phase: persistent waves pull 64-sample work items (job, direction,
+// sample range) from a round counter until the round is drained, which
+// balances jobs of uneven image size and uneven per-sample cost.  Each lane
+// draws its technique's start; samples whose walks remain are compacted into
+// the task queue (one atomic per wave), so the walk phase runs full waves
+// instead of the few lanes whose starts succeeded.
 template <int TECH, bool CW>
 __global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
@@ -606,7 +655,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_kernel(W
     const bool active = smp < J.s1;
     const Ctx C{J.S, J.F[dir], A.W, A.depth};
     Lane L{C, Rng{A.k0, A.k1, (uint32_t)smp, ((uint32_t)TECH << 24) | ((uint32_t)dir << 23), A.job_base + (uint32_t)(jd >> 1)},
-           s, stk, WorkCount{}, 0, 0, 0u, 0u, 0u, 0, smp};
+           s, stk, WorkCount{}, 0, 0, 0u, 0u, 0u, 0, smp, 0u};
     if (active) {
       if (TECH == 1) tech1<CW>(L);
       if (TECH == 2) tech2<CW>(L);
@@ -616,16 +665,93 @@ __global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_kernel(W
       if (TECH == 6) tech6<CW>(L);
       if (TECH == 7) tech7<CW>(L);
       if (TECH == 8) tech8<CW>(L);
+    }
+    // samples with walks left go to the task queue (techniques whose starts
+    // fail often), or walk here (those whose walks follow most starts)
+    if (!split_walks(TECH) && active) {
+      if (L.defer & 1u) light_walk<CW>(L, L.lw.p, L.lw.n, L.lw.md, L.lw.pred, L.lw.end, L.lw.lim, false);
+      if (L.defer & 2u) eye_walk<CW>(L, L.ew.p, L.ew.n, L.ew.md, L.ew.pred, L.ew.end, L.ew.lim);
+      L.defer = 0u;
       A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
     }
-    const int c = active ? pair_count<TECH>(L, A.depth) : 0;
+    const int want = split_walks(TECH) && active && L.defer ? 1 : 0;
+    int ntask;
+    const uint32_t t = wave_reserve(A.W.ntasks, want, ntask);
+    if (want) {
+      TSK(A.W, 0, t) = make_float4(__uint_as_float((uint32_t)s), __uint_as_float(L.defer),
+                                   __uint_as_float((uint32_t)L.k2), 0.0f);
+      if (L.defer & 1u) store_walk(A.W, 1, t, L.lw);
+      if (L.defer & 2u) store_walk(A.W, 6, t, L.ew);
+    }
+    // the others are complete: their paths go out now
+    if (split_walks(TECH) && active && !want) A.W.counts[s] = 0u;
+    const int c = active && !want ? pair_count<TECH>(L, A.depth) : 0;
     int total;
     const uint32_t at = wave_reserve(A.W.npairs, c, total);
     if (c > 0 && at + (uint32_t)c <= (uint32_t)A.W.pair_cap) write_pairs<TECH>(L, A.W.pairs + at, A.depth);
     if (CW) {
-      L.wc.bytes += 4u * (uint32_t)c + (active ? 4u : 0u);
-      flush_work(A.stats, TECH == 8 ? 11 : TECH, L.wc);
+      L.wc.bytes += 4u * (uint32_t)c + (active && !want ? 4u : 0u) +
+                    (want ? 16u * (1u + 5u * (uint32_t)__popc(L.defer)) : 0u);
+      flush_work(A.stats, kid_start(TECH), L.wc);
     }
+  }
+}
+
+// The walks of one task and its connected paths.  jd: the lane's (job,
+// direction); wave-uniform in the common case, so that scene and frame data
+// come through scalar loads.
+template <int TECH, bool CW>
+DEV void run_task(const WalkArgs& A, int jd, uint32_t t, uint32_t s, bool act, int* stk) {
+  uint32_t defer = 0u, k2 = 0u;
+  if (act) {
+    const float4 h = TSK(A.W, 0, t);
+    defer = __float_as_uint(h.y);
+    k2 = __float_as_uint(h.z);
+  }
+  const int64_t g = A.item0 + s / kItem;
+  const DevJob& J = A.jobs[jd >> 1];
+  const int dir = jd & 1;
+  const int64_t smp = J.s0 + (g - A.item_prefix[jd]) * kItem + s % kItem;
+  const Ctx C{J.S, J.F[dir], A.W, A.depth};
+  Lane L{C, Rng{A.k0, A.k1, (uint32_t)smp, ((uint32_t)TECH << 24) | ((uint32_t)dir << 23), A.job_base + (uint32_t)(jd >> 1)},
+         (int)s, stk, WorkCount{}, 0, 0, 0u, 0u, 0u, (int)k2, smp, 0u};
+  if (act) {
+    if (defer & 1u) {
+      const WalkStart w = load_walk(A.W, 1, t);
+      light_walk<CW>(L, w.p, w.n, w.md, w.pred, w.end, w.lim, false);
+    }
+    if (defer & 2u) {
+      const WalkStart w = load_walk(A.W, 6, t);
+      eye_walk<CW>(L, w.p, w.n, w.md, w.pred, w.end, w.lim);
+    }
+    A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
+  }
+  const int c = act ? pair_count<TECH>(L, A.depth) : 0;
+  int total;
+  const uint32_t at = wave_reserve(A.W.npairs, c, total);
+  if (c > 0 && at + (uint32_t)c <= (uint32_t)A.W.pair_cap) write_pairs<TECH>(L, A.W.pairs + at, A.depth);
+  if (CW) {
+    L.wc.bytes += 4u * (uint32_t)c + (act ? 4u : 0u);
+    flush_work(A.stats, kid_walk(TECH), L.wc);
+  }
+}
+
+// Walk phase: one lane per queued task (full waves), the random walks with
+// their next-event and camera connections, then the sample's connected paths
+// into the path queue.
+template <int TECH, bool CW>
+__global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_task_kernel(WalkArgs A) {
+  __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
+  const uint32_t n = min(*A.W.ntasks, (uint32_t)A.W.Q);
+  for (uint32_t base = blockIdx.x * kTraceBlock; base < n; base += gridDim.x * kTraceBlock) {
+    const uint32_t t = base + threadIdx.x;
+    const bool act = t < n;
+    const uint32_t s = act ? __float_as_uint(TSK(A.W, 0, t).x) : 0u;
+    // the sample behind the slot: item -> (job, direction)
+    const int jd = act ? find_jd(A.item_prefix, 2 * A.njobs, A.item0 + s / kItem) : 0;
+    const int jd0 = __builtin_amdgcn_readfirstlane(jd);
+    if (__ballot(act && jd != jd0) == 0ull) run_task<TECH, CW>(A, jd0, t, s, act, stk);
+    else run_task<TECH, CW>(A, jd, t, s, act, stk);
   }
 }
 
@@ -1169,7 +1295,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void connect_kerne
       atomicAdd(&A.stats->by_tech[A.tech], c);
     }
   }
-  if (CW) flush_work(A.stats, 8, wc);
+  if (CW) flush_work(A.stats, kKidConnect, wc);
 }
 
 // Technique (8)'s MIS term needs the proposal at every dynamic vertex x_m
@@ -1497,6 +1623,27 @@ static void launch_walk_cw(const WalkArgs& A, int blocks, hipStream_t st) {
 void launch_walk(const WalkArgs& A, int blocks, hipStream_t st) {
   if (A.count_work) launch_walk_cw<true>(A, blocks, st);
   else launch_walk_cw<false>(A, blocks, st);
+}
+template <int T, bool CW>
+static void launch_walk_task_t(const WalkArgs& A, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((walk_task_kernel<T, CW>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
+}
+template <bool CW>
+static void launch_walk_task_cw(const WalkArgs& A, int blocks, hipStream_t st) {
+  switch (A.tech) {
+    case 1: launch_walk_task_t<1, CW>(A, blocks, st); break;
+    case 2: launch_walk_task_t<2, CW>(A, blocks, st); break;
+    case 3: launch_walk_task_t<3, CW>(A, blocks, st); break;
+    case 4: launch_walk_task_t<4, CW>(A, blocks, st); break;
+    case 5: launch_walk_task_t<5, CW>(A, blocks, st); break;
+    case 6: launch_walk_task_t<6, CW>(A, blocks, st); break;
+    case 8: launch_walk_task_t<8, CW>(A, blocks, st); break;
+    default: launch_walk_task_t<7, CW>(A, blocks, st); break;
+  }
+}
+void launch_walk_tasks(const WalkArgs& A, int blocks, hipStream_t st) {
+  if (A.count_work) launch_walk_task_cw<true>(A, blocks, st);
+  else launch_walk_task_cw<false>(A, blocks, st);
 }
 void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st) {
   hipLaunchKernelGGL(zero_images, dim3(1024), dim3(256), 0, st, jobs, njobs);

@@ -174,4 +174,17 @@ DEV vec3 vmf_mix_sample(const float* raw, float u0, float u1, float u2) {
   return unit(t * (s * cp) + b * (s * sp) + mu * c);
 }
 
+// Technique (8)'s direction sampler, a defensive mixture (Hesterberg 1995):
+// with probability kT8Uniform a uniform direction on the sphere, else the
+// learned lobes, so the technique keeps full support where the lobes'
+// densities underflow.
+constexpr float kT8Uniform = 0.25f;
+DEV vec3 t8_dir_sample(const float* raw, float u0, float u1, float u2) {
+  if (u0 < kT8Uniform) return sphere_dir(u1, u2);
+  return vmf_mix_sample(raw, (u0 - kT8Uniform) / (1.0f - kT8Uniform), u1, u2);
+}
+DEV float t8_dir_pdf(const float* raw, vec3 w) {
+  return kT8Uniform / (4.0f * kPi) + (1.0f - kT8Uniform) * vmf_mix_pdf(raw, w);
+}
+
 }  // namespace rpi

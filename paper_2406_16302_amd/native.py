@@ -69,9 +69,9 @@ class Stats(C.Structure):
     _fields_ = [("samples", C.c_int64), ("paths", C.c_int64), ("accepted", C.c_int64),
                 ("rejected", C.c_int64 * 7), ("by_tech", C.c_int64 * 9), ("rays", C.c_int64 * 6),
                 ("nodes_visited", C.c_int64), ("tris_tested", C.c_int64), ("milliseconds", C.c_double),
-                ("kernel_ms", C.c_double * 16), ("kernel_launches", C.c_int64 * 16),
-                ("kernel_nodes", C.c_int64 * 16), ("kernel_tris", C.c_int64 * 16),
-                ("kernel_bytes_written", C.c_int64 * 16), ("train_records", C.c_int64)]
+                ("kernel_ms", C.c_double * 32), ("kernel_launches", C.c_int64 * 32),
+                ("kernel_nodes", C.c_int64 * 32), ("kernel_tris", C.c_int64 * 32),
+                ("kernel_bytes_written", C.c_int64 * 32), ("train_records", C.c_int64)]
 
     def as_dict(self):
         return {"samples": self.samples, "paths": self.paths, "accepted": self.accepted,
