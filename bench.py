@@ -46,7 +46,9 @@ def parse():
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "walk_kernel6_clutter_motion_512x512_d5_hbm_traffic.md")
+def traffic_file(kernel):
+    name = kernel.replace("<", "").replace(">", "")
+    return os.path.join(HERE, "profiles", "%s_clutter_motion_512x512_d5_hbm_traffic.md" % name)
 KERNEL_SOURCES = ["rpi_kernels.hip", "rpi_device.h", "rpi_internal.h", "rpi_mlp.h"]
 
 
@@ -62,7 +64,7 @@ def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, if it was taken on the current kernel sources (else None)."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(kernel)) as fh:
             m = re.search(r"```json\n(.*?)\n```", fh.read(), re.S)
         rec = json.loads(m.group(1))
     except (OSError, AttributeError, ValueError):
