@@ -40,6 +40,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="a reduced workload (quick checks only)")
+    ap.add_argument("--workload", default="clutter_motion",
+                    choices=["clutter_motion", "material_edit", "batch", "proposal"],
+                    help="clutter_motion (default, the headline line); material_edit: 983k triangles, 1024^2, "
+                         "32 spp, depth 6; batch: 32 Bezier frames of the clutter scene, 256^2..1024^2, 16 spp, "
+                         "one captured graph; proposal: the material edit with a proposal trained on the GPU and "
+                         "technique 8 in place of 2 and 3")
     ap.add_argument("--copy-only", action="store_true",
                     help="only a device-to-device copy of 1 GiB, three times (HBM counter calibration)")
     return ap.parse_args()
@@ -86,11 +92,82 @@ def copy_only():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
 
 
-def workload(small):
+def workload(small, name="clutter_motion"):
     from paper_2406_16302_amd import scenes
+    if name in ("material_edit", "proposal"):
+        return scenes.material_edit(width=256, height=256, spp=4) if small else scenes.material_edit()
     if small:
         return scenes.clutter_motion(width=128, height=128, spp=8)
     return scenes.clutter_motion()
+
+
+def bench_batch(args):
+    """32 consecutive Bezier frames of the clutter scene, each a residual
+    against the previous frame, image sizes from {256, 512, 768, 1024}^2,
+    16 spp: one captured hipGraph per call."""
+    import torch
+    from paper_2406_16302_amd import native, scenes
+    ws = scenes.clutter_motion(spp=16)
+    sc = native.Scene(ws.scene)
+    jobs = scenes.bezier_jobs()
+    if args.small:
+        jobs = jobs[:4]
+    outs = [torch.zeros((j["height"], j["width"], 3), dtype=torch.float32, device="cuda") for j in jobs]
+    jl = [{"pose_old": j["pose_old"], "pose_new": j["pose_new"], "out": o} for j, o in zip(jobs, outs)]
+    p = native.Params.make(16, ws.depth, ws.seed, mask=ws.mask, flags=native.FLAG_TWO_WAY)
+    t0 = time.perf_counter()
+    st = native.render_residual_batch(sc, jl, p, stats=True)  # plan, autotune, capture
+    log("first call (autotune + capture): %.1f s, %d paths" % (time.perf_counter() - t0, st["paths"]))
+    for _ in range(args.warmup):
+        native.render_residual_batch(sc, jl, p)
+    torch.cuda.synchronize()
+    paths = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = native.render_residual_batch(sc, jl, p, stats=True)
+        paths.append(st["paths"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / args.steps * 1e3
+    pix = sum(j["width"] * j["height"] for j in jobs)
+    return {"metric": METRIC, "value": round(float(np.mean(paths)) / (ms / 1e3), 1), "unit": "residual paths/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 2),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "batch_bezier", "jobs": len(jobs), "pixels": pix, "spp": 16, "max_depth": ws.depth,
+                       "techniques": "1-7", "two_way": True, "graph": True},
+            "paths_per_step": int(np.mean(paths))}
+
+
+def train_proposal(sc, ed, ws, log_fn):
+    """Records from the plain estimator, then Adam on the GPU; returns the
+    proposal and a summary."""
+    import torch
+    from paper_2406_16302_amd import native
+    cap = 12_000_000
+    buf = torch.zeros((cap, 10), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    st = native.render_residual(sc, ed, native.Params.make(ws.spp, ws.depth, 777, mask=0x07, flags=0,
+                                                           train_records=buf), torch.zeros(
+        (sc.height, sc.width, 3), dtype=torch.float32, device="cuda"), stats=True)
+    n = min(st["train_records"], cap)
+    t1 = time.perf_counter()
+    prop = native.Proposal(sc, None, seed=3)
+    batch = 16384
+    steps = max(200, 20 * n // batch)  # 20 epochs
+    losses = torch.zeros(steps, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prop.train(buf, n, steps, batch=batch, lr=1e-3, seed=11, losses=losses)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    L = losses.cpu().numpy()
+    flop = 3 * 22272 * batch * steps
+    summary = {"records": int(n), "collect_s": round(t1 - t0, 3), "train_steps": steps, "batch": batch,
+               "train_s": round(t3 - t2, 3), "train_records_per_s": round(batch * steps / (t3 - t2), 1),
+               "train_tflops": round(flop / (t3 - t2) / 1e12, 3), "loss_first": round(float(L[:20].mean()), 4),
+               "loss_last": round(float(L[-20:].mean()), 4)}
+    log_fn("proposal: %s" % summary)
+    return prop, summary
 
 
 def cpu_baseline(ws, target_s):
@@ -122,20 +199,31 @@ def main():
     if args.copy_only:
         copy_only()
         return
+    if args.workload == "batch":
+        if args.gpus != 1:
+            print("bench.py: this build measures one GPU", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported (the estimator shards "
               "sample ranges across GPUs only by design, see DESIGN.md)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2406_16302_amd import native
-    ws = workload(args.small)
+    ws = workload(args.small, args.workload)
     sc = native.Scene(ws.scene)
     ed = native.Edit(sc, ws.edit)
     out = torch.zeros((sc.height, sc.width, 3), dtype=torch.float32, device="cuda")
-    base = native.FLAG_TWO_WAY
+    material = ws.edit.kind == native.EDIT_MATERIAL
+    base = 0 if material else native.FLAG_TWO_WAY
+    mask, prop, prop_summary = ws.mask, None, None
+    if args.workload == "proposal":
+        prop, prop_summary = train_proposal(sc, ed, ws, log)
+        mask = (ws.mask & ~0x6) | 0x80
 
     def params(flags):
-        return native.Params.make(ws.spp, ws.depth, ws.seed, mask=ws.mask, flags=base | flags)
+        return native.Params.make(ws.spp, ws.depth, ws.seed, mask=mask, flags=base | flags, proposal=prop)
 
     log("scene built: %d triangles, %dx%d" % (len(ws.scene.indices), sc.width, sc.height))
     # instrumented pass (untimed): rays by type and algorithmic work per kernel
@@ -180,18 +268,21 @@ def main():
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
-            "config": {"workload": "clutter_motion" + ("_small" if args.small else ""),
+            "config": {"workload": args.workload + ("_small" if args.small else ""),
                        "triangles": int(len(ws.scene.indices)),
                        "object_triangles": int((ws.scene.tri_object == 1).sum()),
                        "image": "%dx%d" % (sc.width, sc.height), "max_depth": ws.depth, "spp": ws.spp,
-                       "techniques": "1-7", "two_way": True},
+                       "techniques": {"clutter_motion": "1-7", "material_edit": "1-3",
+                                      "proposal": "1, 8"}[args.workload], "two_way": not material},
             "mrays_per_s": round(rays_per_step / (ms_per_step / 1e3) / 1e6, 1),
             "paths_per_step": int(paths_per_step), "rays_per_step": int(rays_per_step),
             "rays_by_type": {k: int(v) for k, v in zip(["closest", "shadow", "camera", "ghost", "map_retrace",
                                                          "map_visibility"], cw["rays"])},
             "kernel_ms_per_step": {KERNEL_NAMES[k]: round(kms[k] / args.steps, 2) for k in KIDS if kms[k] > 0},
             "roofline": roofline}
-    if not args.no_cpu_baseline:
+    if prop_summary is not None:
+        line["proposal"] = prop_summary
+    if not args.no_cpu_baseline and args.workload == "clutter_motion":
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(ws, args.cpu_seconds)
     print(json.dumps(line), flush=True)
