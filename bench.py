@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="default launch configuration instead of the tuned one")
+    ap.add_argument("--tuning", default=None,
+                    help="queue_cap,walk_blocks_per_cu,connect_blocks_per_cu: use this launch configuration "
+                         "instead of running the autotuner (profiling runs)")
     ap.add_argument("--small", action="store_true", help="a reduced workload (quick checks only)")
     ap.add_argument("--workload", default="clutter_motion",
                     choices=["clutter_motion", "material_edit", "batch", "proposal"],
@@ -66,16 +70,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, queue_cap):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources (else None)."""
+    summary, if it was taken on the current kernel sources with the same
+    round size (else None)."""
     try:
         with open(traffic_file(kernel)) as fh:
             m = re.search(r"```json\n(.*?)\n```", fh.read(), re.S)
         rec = json.loads(m.group(1))
     except (OSError, AttributeError, ValueError):
         return None
-    if rec.get("kernel") != kernel or rec.get("source_hash") != kernel_source_hash():
+    if rec.get("kernel") != kernel or rec.get("source_hash") != kernel_source_hash() or \
+            rec.get("queue_cap") != queue_cap:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -226,6 +232,15 @@ def main():
         return native.Params.make(ws.spp, ws.depth, ws.seed, mask=mask, flags=base | flags, proposal=prop)
 
     log("scene built: %d triangles, %dx%d" % (len(ws.scene.indices), sc.width, sc.height))
+    tuning = None
+    if args.tuning:
+        q, wb, cb = (int(x) for x in args.tuning.split(","))
+        native.set_tuning(sc, q, wb, cb)
+        tuning = {"queue_cap": q, "walk_blocks_per_cu": wb, "connect_blocks_per_cu": cb}
+    elif not args.no_autotune:
+        # the library's autotuner picks the round size and persistent grids (untimed setup)
+        tuning = native.autotune(sc, ed, params(0))
+        log("autotuned: %s" % tuning)
     # instrumented pass (untimed): rays by type and algorithmic work per kernel
     cw = native.render_residual(sc, ed, params(native.FLAG_COUNT_WORK), out, stats=True)
     log("instrumented pass: %d paths, %d rays" % (cw["paths"], sum(cw["rays"])))
@@ -258,7 +273,7 @@ def main():
     launches = max(klaunch[kid] / args.steps, 1)
     avg_ms = kms[kid] / max(klaunch[kid], 1)
     achieved = (kbytes / launches) / (avg_ms / 1e3) / 1e9
-    traffic = None if args.small else measured_traffic(KERNEL_NAMES[kid])
+    traffic = None if args.small else measured_traffic(KERNEL_NAMES[kid], tuning["queue_cap"] if tuning else 1 << 20)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_NAMES[kid], "avg_launch_ms": round(avg_ms, 4),
@@ -282,6 +297,9 @@ def main():
             "roofline": roofline}
     if prop_summary is not None:
         line["proposal"] = prop_summary
+    if tuning is not None:
+        line["config"]["launch"] = {"queue_cap": tuning["queue_cap"], "walk_blocks_per_cu": tuning["walk_blocks_per_cu"],
+                                    "connect_blocks_per_cu": tuning["connect_blocks_per_cu"]}
     if not args.no_cpu_baseline and args.workload == "clutter_motion":
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(ws, args.cpu_seconds)

@@ -197,11 +197,17 @@ typedef struct {
 } rpi_tuning;
 
 /* Time a small grid of launch configurations (round size, persistent grid,
- * connect grid) on the first 2^20 samples of every stream of this edit and
+ * connect grid) on the first 2^22 samples of every stream of this edit and
  * keep the fastest for later calls on this scene whose queue_cap is 0.
  * Synchronises hip_stream.  out may be NULL. */
 rpi_status rpi_autotune(rpi_scene* scene, const rpi_edit* edit, const rpi_render_params* params, rpi_tuning* out,
                         void* hip_stream);
+
+/* Use a launch configuration measured earlier (for example by rpi_autotune
+ * in another process) for later calls on this scene whose queue_cap is 0.
+ * Errors: INVALID_ARG (queue_cap not a positive multiple of 64, or blocks
+ * per CU outside [1, 64]). */
+rpi_status rpi_set_tuning(rpi_scene* scene, const rpi_tuning* tuning);
 
 /* Per-path records of the last rpi_render_residual call on this scene made
  * with RPI_FLAG_RECORDS (host copy): each record is 8 int32/float words

@@ -1208,7 +1208,7 @@ static rpi_status autotune_job(rpi_scene* s, const JobSpec& j, bool material_mod
   q.flags |= RPI_FLAG_ACCUMULATE;
   const int64_t N = (int64_t)p->spp * j.W * j.H;
   q.sample_begin = 0;
-  q.sample_end = std::min<int64_t>(N, 1 << 20);
+  q.sample_end = std::min<int64_t>(N, 1 << 22);  // enough samples per stream to need several rounds at the smaller sizes
   if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);
   const int Qs[3] = {1 << 20, 1 << 21, 1 << 22};
   const int walks[3] = {8, 16, 32};
@@ -1258,6 +1258,17 @@ extern "C" rpi_status rpi_autotune(rpi_scene* s, const rpi_edit* e, const rpi_re
   rc = autotune_job(s, j, e->kind == RPI_EDIT_MATERIAL, p, (hipStream_t)stream, out);
   (void)hipFree(tmp);
   return rc;
+}
+
+extern "C" rpi_status rpi_set_tuning(rpi_scene* s, const rpi_tuning* t) {
+  if (!s || !t) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  if (t->queue_cap <= 0 || t->queue_cap % kItem || t->queue_cap > (1 << 24) || t->walk_blocks_per_cu < 1 ||
+      t->walk_blocks_per_cu > 64 || t->connect_blocks_per_cu < 1 || t->connect_blocks_per_cu > 64)
+    return fail(RPI_ERR_INVALID_ARG, "bad tuning");
+  s->tuned_Q = t->queue_cap;
+  s->tuned_walk = t->walk_blocks_per_cu;
+  s->tuned_conn = t->connect_blocks_per_cu;
+  return RPI_OK;
 }
 
 // A captured batch: persistent workspace, job table staging, graph.

@@ -119,6 +119,7 @@ def load_library():
                                                 C.POINTER(Stats), vp]
         L.rpi_get_records.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.rpi_autotune.argtypes = [vp, vp, C.POINTER(Params), C.POINTER(Tuning), vp]
+        L.rpi_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.rpi_proposal_create.argtypes = [vp, vp, C.c_uint64, C.POINTER(vp)]
         L.rpi_proposal_destroy.argtypes = [vp]
         L.rpi_proposal_set_weights.argtypes = [vp, vp]
@@ -130,7 +131,7 @@ def load_library():
         L.rpi_version.restype = C.c_char_p
         for f in ("rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
                   "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records",
-                  "rpi_autotune", "rpi_proposal_create", "rpi_proposal_destroy", "rpi_proposal_set_weights",
+                  "rpi_autotune", "rpi_set_tuning", "rpi_proposal_create", "rpi_proposal_destroy", "rpi_proposal_set_weights",
                   "rpi_proposal_get_weights", "rpi_proposal_forward", "rpi_proposal_loss_grad",
                   "rpi_proposal_train"):
             getattr(L, f).restype = C.c_int32
@@ -243,6 +244,11 @@ def autotune(scene: Scene, edit: Edit, params: Params, stream=None):
     _check(L.rpi_autotune(scene.h, edit.h, C.byref(params), C.byref(t), _stream(stream)))
     return {"queue_cap": t.queue_cap, "walk_blocks_per_cu": t.walk_blocks_per_cu,
             "connect_blocks_per_cu": t.connect_blocks_per_cu, "ms_per_msample": t.ms_per_msample}
+
+
+def set_tuning(scene: Scene, queue_cap, walk_blocks_per_cu, connect_blocks_per_cu):
+    t = Tuning(int(queue_cap), int(walk_blocks_per_cu), int(connect_blocks_per_cu), 0.0)
+    _check(load_library().rpi_set_tuning(scene.h, C.byref(t)))
 
 
 def render_residual_batch(scene: Scene, jobs, params: Params, stats=False, stream=None):
