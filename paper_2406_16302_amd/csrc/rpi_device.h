@@ -194,8 +194,22 @@ DEV vec3 spawn_dir(const DevScene& S, vec3 p, vec3 n, vec3 dir) {
 }
 
 // ------------------------------------------------------------------ triangles
+
+// Scene arrays are reached through pointers read from the job table, which
+// the compiler would load with flat instructions; these go through the
+// global address space.
+typedef float gf4 __attribute__((ext_vector_type(4)));
+typedef int gi4 __attribute__((ext_vector_type(4)));
+DEV float4 gld(const float4* p, size_t i) {
+  const gf4 v = ((const __attribute__((address_space(1))) gf4*)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+DEV int4 gld(const int4* p, size_t i) {
+  const gi4 v = ((const __attribute__((address_space(1))) gi4*)p)[i];
+  return make_int4(v.x, v.y, v.z, v.w);
+}
 DEV void load_tri(const float4* __restrict__ T, int i, vec3& v0, vec3& e1, vec3& e2, int& id, int& mat) {
-  const float4 a = T[3 * i], b = T[3 * i + 1], c = T[3 * i + 2];
+  const float4 a = gld(T, 3 * (size_t)i), b = gld(T, 3 * (size_t)i + 1), c = gld(T, 3 * (size_t)i + 2);
   v0 = v3(a.x, a.y, a.z);
   e1 = v3(b.x, b.y, b.z);
   e2 = v3(c.x, c.y, c.z);
@@ -242,44 +256,35 @@ DEV bool slab(float lx, float ly, float lz, float hx, float hy, float hz, vec3 i
 
 // Visit every leaf whose box the ray (o, d) meets before tlim (read through
 // a reference, so closest-hit leaves tighten it).  leaf(code) returns true to
-// stop.  The stack lives in LDS: entry k of lane l at stk[k * kTraceBlock + l].
-// Visit every leaf whose box the ray (o, d) meets before tlim (read through
-// a reference, so closest-hit leaves tighten it).  leaf(code) returns true to
-// stop.  The stack lives in LDS: entry k of lane l at stk[k * kTraceBlock + l].
-// While-while traversal (Aila and Laine 2009): a lane visits inner nodes
-// until it has a leaf to test or its stack is empty, and the wave tests its
-// leaves together, so the triangle loop runs with the lanes of all leaves
-// instead of one branch per node visit (1.8x on the whole estimator).  Each
-// lane visits the same nodes in the same order as a one-node-per-step walk.
+// stop.  The stack lives in LDS: entry k of lane l at stk[k * kTraceBlock + l];
+// it holds inner nodes and leaves alike.
+// While-while traversal with speculative node visits (Aila and Laine 2009):
+// a lane that meets its first leaf postpones it and keeps visiting inner
+// nodes until every lane of the wave holds a leaf (or a lane meets a second
+// one); then the wave tests its leaves together.  The triangle loop runs
+// with the lanes of all leaves instead of one branch per node visit, and
+// lanes that found a leaf early do useful node work meanwhile.  A
+// closest-hit query may visit a few nodes that the postponed leaf's hit
+// would have culled; the hit found is the same.
 template <bool CW, class Leaf>
 DEV void bvh_walk(const float4* __restrict__ N, vec3 o, vec3 d, const float& tlim, int* __restrict__ stk,
                      WorkCount& wc, Leaf&& leaf) {
   const vec3 inv = v3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
   const vec3 oi = v3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
   const int lane = threadIdx.x;
+  constexpr int kDone = 0x7fffffff;  // no node left (inner node indices stay below it)
   int sp = 0;
-  int node = 0;  // next inner node, -1: none left
-  while (true) {
-    int pa = 0, pb = 0;  // pending leaves (negative codes), near one first
-    while (node >= 0 && pa == 0) {
-      const float4 a = N[4 * node], b = N[4 * node + 1], c = N[4 * node + 2];
-      const int4 e = reinterpret_cast<const int4*>(N)[4 * node + 3];
+  int node = 0;  // >= 0: inner node to visit next; < 0: a leaf code; kDone
+  int pl = 0;    // postponed leaf code, 0: none
+  while (node != kDone) {
+    while ((uint32_t)node < (uint32_t)kDone) {
+      const float4 a = gld(N, 4 * (size_t)node), b = gld(N, 4 * (size_t)node + 1), c = gld(N, 4 * (size_t)node + 2);
+      const int4 e = gld(reinterpret_cast<const int4*>(N), 4 * (size_t)node + 3);
       if (CW) wc.nodes++;
       float n0, n1;
-      bool h0 = slab(a.x, a.y, a.z, a.w, b.x, b.y, inv, oi, tlim, n0);
-      bool h1 = slab(b.z, b.w, c.x, c.y, c.z, c.w, inv, oi, tlim, n1);
+      const bool h0 = slab(a.x, a.y, a.z, a.w, b.x, b.y, inv, oi, tlim, n0);
+      const bool h1 = slab(b.z, b.w, c.x, c.y, c.z, c.w, inv, oi, tlim, n1);
       const bool first0 = n0 <= n1;
-      const bool l0 = h0 && e.x < 0, l1 = h1 && e.y < 0;
-      if (l0 && l1) {
-        pa = first0 ? e.x : e.y;
-        pb = first0 ? e.y : e.x;
-      } else if (l0) {
-        pa = e.x;
-      } else if (l1) {
-        pa = e.y;
-      }
-      h0 = h0 && !l0;
-      h1 = h1 && !l1;
       if (h0 && h1) {
         stk[sp * kTraceBlock + lane] = first0 ? e.y : e.x;
         ++sp;
@@ -288,16 +293,23 @@ DEV void bvh_walk(const float4* __restrict__ N, vec3 o, vec3 d, const float& tli
         node = e.x;
       } else if (h1) {
         node = e.y;
-      } else if (sp > 0) {
-        --sp;
-        node = stk[sp * kTraceBlock + lane];
       } else {
-        node = -1;
+        node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
+      }
+      if (node < 0 && pl == 0) {  // postpone the first leaf and go on with the stack
+        pl = node;
+        node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
+      }
+      if (__ballot(pl == 0) == 0ull) break;  // every lane still here holds a leaf
+    }
+    while (pl < 0) {
+      if (leaf(pl)) return;
+      pl = 0;
+      if (node < 0) {
+        pl = node;
+        node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
       }
     }
-    if (pa != 0 && leaf(pa)) return;
-    if (pb != 0 && leaf(pb)) return;
-    if (node < 0) return;
   }
 }
 
