@@ -687,7 +687,7 @@ struct Ws {
   bool async = true;
   Workspace W{};
   DevStats* stats = nullptr;
-  uint32_t *tcount, *toff, *hist, *item_counter, *train_count;
+  uint32_t *tcount, *toff, *cpre, *hist, *item_counter, *train_count;
   float4* binned;
   DevJob* jobs;
   int64_t* prefix;  // [kTechs][2 * njobs + 1]
@@ -717,6 +717,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   const size_t o_stats = take(sizeof(DevStats));
   const size_t o_tc = take((size_t)ntiles * 4);
   const size_t o_to = take((size_t)(ntiles + 1) * 4);
+  const size_t o_cp = take((size_t)(ntiles + 1) * 4);
   const size_t o_hist = take((size_t)ntiles * kSplatBlocks * 4);
   const size_t o_bin = take((size_t)pair_cap * sizeof(float4));
   const size_t o_jobs = take((size_t)njobs * sizeof(DevJob));
@@ -749,6 +750,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   w.stats = (DevStats*)(b + o_stats);
   w.tcount = (uint32_t*)(b + o_tc);
   w.toff = (uint32_t*)(b + o_to);
+  w.cpre = (uint32_t*)(b + o_cp);
   w.hist = (uint32_t*)(b + o_hist);
   w.binned = (float4*)(b + o_bin);
   w.jobs = (DevJob*)(b + o_jobs);
@@ -934,6 +936,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
   sa.hist = w.hist;
   sa.tcount = w.tcount;
   sa.toff = w.toff;
+  sa.cpre = w.cpre;
   sa.binned = w.binned;
   sa.ntiles = pl.ntiles;
   sa.nblk = kSplatBlocks;

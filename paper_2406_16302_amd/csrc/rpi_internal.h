@@ -222,6 +222,8 @@ struct WalkArgs {
 
 // Tile-binned splat of one record queue.  ntiles * 4 bytes of LDS per
 // workgroup hold a tile histogram (ntiles <= 16384).
+constexpr uint32_t kSplatChunk = 2048;  // binned records per splat workgroup pass
+
 struct SplatArgs {
   const float4* records;  // x: job << 24 | pixel (int bits), or -1; yzw: rgb
   const uint32_t* nrec;
@@ -231,6 +233,7 @@ struct SplatArgs {
   uint32_t* hist;     // [ntiles * nblk], then its per-tile exclusive scan
   uint32_t* tcount;   // [ntiles]
   uint32_t* toff;     // [ntiles + 1]
+  uint32_t* cpre;     // [ntiles + 1]: exclusive scan of the tiles' chunk counts
   float4* binned;     // [cap]
   int ntiles, nblk;
   int ts;             // tile edge in pixels: 16 or 32

@@ -1419,27 +1419,38 @@ __global__ __launch_bounds__(256) void splat_scan_blocks(SplatArgs a) {
   if (threadIdx.x == 255) a.tcount[t] = part[255];
 }
 
-// Exclusive scan of the tile totals by one workgroup.
+// Exclusive scans of the tile totals and of the tiles' chunk counts
+// (ceil(total / kSplatChunk)) by one workgroup.
 __global__ __launch_bounds__(1024) void splat_scan_tiles(SplatArgs a) {
-  __shared__ uint32_t part[1024];
+  __shared__ uint32_t part[1024], cpart[1024];
   const int t = threadIdx.x;
   const int per = (a.ntiles + 1023) / 1024;
-  uint32_t sum = 0;
-  for (int i = t * per; i < min(a.ntiles, (t + 1) * per); ++i) sum += a.tcount[i];
+  uint32_t sum = 0, csum = 0;
+  for (int i = t * per; i < min(a.ntiles, (t + 1) * per); ++i) {
+    sum += a.tcount[i];
+    csum += (a.tcount[i] + kSplatChunk - 1) / kSplatChunk;
+  }
   part[t] = sum;
+  cpart[t] = csum;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t x = t >= off ? part[t - off] : 0u;
+    const uint32_t x = t >= off ? part[t - off] : 0u, y = t >= off ? cpart[t - off] : 0u;
     __syncthreads();
     part[t] += x;
+    cpart[t] += y;
     __syncthreads();
   }
-  uint32_t run = part[t] - sum;
+  uint32_t run = part[t] - sum, crun = cpart[t] - csum;
   for (int i = t * per; i < min(a.ntiles, (t + 1) * per); ++i) {
     a.toff[i] = run;
+    a.cpre[i] = crun;
     run += a.tcount[i];
+    crun += (a.tcount[i] + kSplatChunk - 1) / kSplatChunk;
   }
-  if (t == 1023) a.toff[a.ntiles] = part[1023];
+  if (t == 1023) {
+    a.toff[a.ntiles] = part[1023];
+    a.cpre[a.ntiles] = cpart[1023];
+  }
 }
 
 __global__ __launch_bounds__(256) void splat_scatter(SplatArgs a) {
@@ -1460,34 +1471,55 @@ __global__ __launch_bounds__(256) void splat_scatter(SplatArgs a) {
   }
 }
 
-// One workgroup per tile: LDS accumulation, one read-modify-write of the tile.
+// Workgroups take chunks of at most kSplatChunk binned records of one tile
+// (a few tiles near the edit hold most records, so one workgroup per tile
+// would leave the chip idle behind them), accumulate them in LDS and add
+// the sums to the tile's pixels: a plain read-modify-write when the tile has
+// one chunk, float atomics when several chunks share it.
 __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
   __shared__ float acc[kTileMax * kTileMax * 3];
-  const int t = blockIdx.x;
-  const uint32_t b = a.toff[t], e = a.toff[t + 1];
-  if (e == b) return;
+  const uint32_t nch = a.cpre[a.ntiles];
   const int tp = a.ts * a.ts;
-  for (int i = threadIdx.x; i < tp * 3; i += 256) acc[i] = 0.0f;
-  __syncthreads();
-  for (uint32_t i = b + threadIdx.x; i < e; i += 256) {
-    const float4 r = a.binned[i];
-    const int l = __float_as_int(r.x);
-    atomicAdd(&acc[3 * l + 0], r.y);
-    atomicAdd(&acc[3 * l + 1], r.z);
-    atomicAdd(&acc[3 * l + 2], r.w);
-  }
-  __syncthreads();
-  const DevJob& J = a.jobs[a.tile_job[t]];
-  const int lt = t - J.tile0;
-  const int tx = lt % J.tilesx, ty = lt / J.tilesx;
-  for (int l = threadIdx.x; l < tp; l += 256) {
-    const int px = tx * a.ts + (l % a.ts), py = ty * a.ts + (l / a.ts);
-    if (px < J.W && py < J.H) {
-      float* o = J.image + 3 * ((size_t)py * J.W + px);
-      o[0] += acc[3 * l];
-      o[1] += acc[3 * l + 1];
-      o[2] += acc[3 * l + 2];
+  for (uint32_t g = blockIdx.x; g < nch; g += gridDim.x) {
+    int lo = 0, hi = a.ntiles;  // cpre[lo] <= g < cpre[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.cpre[mid] <= g) lo = mid;
+      else hi = mid;
     }
+    const int t = lo;
+    const uint32_t b = a.toff[t] + (g - a.cpre[t]) * kSplatChunk;
+    const uint32_t e = min(b + kSplatChunk, a.toff[t + 1]);
+    const bool shared = a.cpre[t + 1] - a.cpre[t] > 1;
+    for (int i = threadIdx.x; i < tp * 3; i += 256) acc[i] = 0.0f;
+    __syncthreads();
+    for (uint32_t i = b + threadIdx.x; i < e; i += 256) {
+      const float4 r = a.binned[i];
+      const int l = __float_as_int(r.x);
+      atomicAdd(&acc[3 * l + 0], r.y);
+      atomicAdd(&acc[3 * l + 1], r.z);
+      atomicAdd(&acc[3 * l + 2], r.w);
+    }
+    __syncthreads();
+    const DevJob& J = a.jobs[a.tile_job[t]];
+    const int lt = t - J.tile0;
+    const int tx = lt % J.tilesx, ty = lt / J.tilesx;
+    for (int l = threadIdx.x; l < tp; l += 256) {
+      const int px = tx * a.ts + (l % a.ts), py = ty * a.ts + (l / a.ts);
+      if (px < J.W && py < J.H) {
+        float* o = J.image + 3 * ((size_t)py * J.W + px);
+        if (shared) {
+          unsafeAtomicAdd(o + 0, acc[3 * l]);  // the hardware float add (device memory)
+          unsafeAtomicAdd(o + 1, acc[3 * l + 1]);
+          unsafeAtomicAdd(o + 2, acc[3 * l + 2]);
+        } else {
+          o[0] += acc[3 * l];
+          o[1] += acc[3 * l + 1];
+          o[2] += acc[3 * l + 2];
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1667,7 +1699,9 @@ void launch_splat(const SplatArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(splat_scan_blocks, dim3(a.ntiles), dim3(256), 0, st, a);
   hipLaunchKernelGGL(splat_scan_tiles, dim3(1), dim3(1024), 0, st, a);
   hipLaunchKernelGGL(splat_scatter, dim3(a.nblk), dim3(256), lds, st, a);
-  hipLaunchKernelGGL(splat_tiles, dim3(a.ntiles), dim3(256), 0, st, a);
+  // chunks: at most one per tile plus one per kSplatChunk records
+  const int64_t chunks = (int64_t)a.ntiles + a.cap / kSplatChunk + 1;
+  hipLaunchKernelGGL(splat_tiles, dim3((unsigned)std::min<int64_t>(chunks, 8192)), dim3(256), 0, st, a);
 }
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(zero_u32, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256 + 1)), dim3(256), 0, st, p, n);
