@@ -512,11 +512,13 @@ struct LightEnd {
   int env;
 };
 DEV bool sample_light(const DevScene& S, const float u[4], LightEnd& L) {
+  // every branch writes the fields in the same order, which lets the
+  // compiler keep a LightEnd in registers
   if (u[0] < S.p_env) {
-    L.env = 1;
-    L.n = sphere_dir(u[2], u[3]);
     L.p = v3(0, 0, 0);
+    L.n = sphere_dir(u[2], u[3]);
     L.mat = 0;
+    L.env = 1;
     return true;
   }
   if (S.nlights == 0) return false;

@@ -744,6 +744,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   w.W.t8q = t8 ? (float4*)(b + o_t8) : nullptr;
   w.W.task = (float4*)(b + o_task);
   w.W.ntasks = (uint32_t*)(b + o_nt);
+  w.W.fetch = w.W.ntasks + 16;
   w.W.Q = Q;
   w.W.pair_cap = pair_cap;
   w.W.nslot = nslot;
@@ -969,7 +970,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       A.nitems = (int)std::min<int64_t>(R, T - i0);
       launch_zero_u32(w.W.npairs, 1, st);
       launch_zero_u32(w.item_counter, 1, st);
-      launch_zero_u32(w.W.ntasks, 1, st);
+      launch_zero_u32(w.W.ntasks, 64, st);  // the task count and the fetch counters
       const int blocks = std::min<int64_t>(wblocks, A.nitems);
       rpi_status r;
       if (t == 8) {

@@ -131,6 +131,7 @@ struct Workspace {
   uint32_t* rec_sample;
   float4* task;        // walk tasks (start phase -> walk phase), SoA: task[field * Q + t]
   uint32_t* ntasks;    // [1] task queue length
+  uint32_t* fetch;     // [2] work counters of the walk phase (tasks) and the connect kernel (paths)
   float4* t8q;         // technique (8) on: per queued path (2 float4), the proposal's
                        // solid-angle density at vertices x_1 .. x_5 (0 where not used)
   int32_t Q;           // samples per chunk
@@ -163,10 +164,9 @@ constexpr int kKidConnect = 9, kKidSplat = 10, kKidFrame = 11, kKidProposalPdf =
 RPI_HD constexpr int kid_start(int t) { return t; }
 RPI_HD constexpr int kid_walk(int t) { return 16 + t; }
 // Techniques whose walks run in a separate phase over the compacted task
-// queue: those whose starts fail often (ghost and two-ended starts, the
-// camera test of technique 2).  Techniques 1, 4 and 7 walk after most starts
-// and run faster in one kernel (measured).
-RPI_HD constexpr bool split_walks(int t) { return !(t == 1 || t == 4 || t == 7); }
+// queue: all but path tracing (7), whose camera rays start a walk in most
+// lanes and which runs faster in one kernel (measured).
+RPI_HD constexpr bool split_walks(int t) { return t != 7; }
 constexpr int kTechs = 8;  // techniques 1..6 of Sec. 4, 7 = path tracing, 8 = learned proposal
 
 // Device view of a learned proposal (technique 8): the MLP's BF16 weights in

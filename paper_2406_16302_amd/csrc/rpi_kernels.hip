@@ -586,6 +586,14 @@ DEV void flush_work(DevStats* st, int kid, const WorkCount& wc) {
   }
 }
 
+// The next 64 entries of a queue for this wave (one wave per workgroup):
+// waves take work as they finish, which balances uneven per-entry cost.
+DEV uint32_t next_batch(uint32_t* counter) {
+  uint32_t b = 0;
+  if (threadIdx.x == 0) b = atomicAdd(counter, (uint32_t)kTraceBlock);
+  return __builtin_amdgcn_readfirstlane(__shfl(b, 0, kWave));
+}
+
 // Work item g -> (job, direction) by binary search of the item prefix table.
 DEV int find_jd(const int64_t* pre, int n, int64_t g) {
   int lo = 0, hi = n;  // pre[lo] <= g < pre[hi]
@@ -743,7 +751,9 @@ template <int TECH, bool CW>
 __global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_task_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   const uint32_t n = min(*A.W.ntasks, (uint32_t)A.W.Q);
-  for (uint32_t base = blockIdx.x * kTraceBlock; base < n; base += gridDim.x * kTraceBlock) {
+  for (;;) {
+    const uint32_t base = next_batch(&A.W.fetch[0]);
+    if (base >= n) break;
     const uint32_t t = base + threadIdx.x;
     const bool act = t < n;
     const uint32_t s = act ? __float_as_uint(TSK(A.W, 0, t).x) : 0u;
@@ -1242,7 +1252,9 @@ __global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void connect_kerne
   WorkCount wc{};
   // wave-uniform trip count (one wave per workgroup): the training-record
   // queue reservation below is a wave-wide prefix sum
-  for (uint32_t base = blockIdx.x * kTraceBlock; base < n; base += gridDim.x * kTraceBlock) {
+  for (;;) {
+    const uint32_t base = next_batch(&A.W.fetch[1]);
+    if (base >= n) break;
     const uint32_t idx = base + threadIdx.x;
     const bool act = idx < n;
     TrainRec tr;
