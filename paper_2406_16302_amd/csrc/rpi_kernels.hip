@@ -502,8 +502,8 @@ DEV void tech7(Lane& L) {
 }
 
 // Number of connected paths of a sample and the i-th of them.
-template <int TECH>
-DEV int pair_count(const Lane& L, int depth) {
+template <int TECH, class LaneT>
+DEV int pair_count(const LaneT& L, int depth) {
   int c = 0;
   if (TECH == 1 || TECH == 4) {
     c = __popc(L.camok);
@@ -523,8 +523,8 @@ DEV int pair_count(const Lane& L, int depth) {
 }
 DEV uint32_t pair_code(int s, int i, int j) { return ((uint32_t)s << 8) | ((uint32_t)(i + 1) << 4) | (uint32_t)(j + 1); }
 
-template <int TECH>
-DEV void write_pairs(const Lane& L, uint32_t* out, int depth) {
+template <int TECH, class LaneT>
+DEV void write_pairs(const LaneT& L, uint32_t* out, int depth) {
   int w = 0;
   if (TECH == 1 || TECH == 4) {
     for (int i = 0; i < L.nE; ++i)
@@ -705,64 +705,482 @@ __global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_kernel(W
   }
 }
 
-// The walks of one task and its connected paths.  jd: the lane's (job,
-// direction); wave-uniform in the common case, so that scene and frame data
-// come through scalar loads.
-template <int TECH, bool CW>
-DEV void run_task(const WalkArgs& A, int jd, uint32_t t, uint32_t s, bool act, int* stk) {
-  uint32_t defer = 0u, k2 = 0u;
-  if (act) {
-    const float4 h = TSK(A.W, 0, t);
-    defer = __float_as_uint(h.y);
-    k2 = __float_as_uint(h.z);
+// ------------------------------------------------------------------ walk phase
+// Every lane of a wave runs its own task through a small state machine
+// (next-event or camera connection, extension, vertex records) that issues
+// one compound ray query at a time:
+//   visibility: any hit in the static scene, then in the object at its pose
+//     (when the segment meets its box), then, if nothing blocks, the ghost
+//     crossings of the same segment;
+//   extension: closest hit in the static scene and the object, then the
+//     ghost crossings of the new edge.
+// One traversal loop serves the queries of all lanes together whatever their
+// kind and stage, so lanes whose walk has no query of a given kind do not sit
+// out that query, and a lane whose task is done takes the next one from the
+// queue.  The arithmetic of each query is that of edge_visible, closest and
+// edge_cross.
+enum : int { QS_NONE = 0, QS_STAT = 1, QS_OBJ = 2, QS_GHOST = 3 };
+enum : int { QK_VIS = 0, QK_EXT = 1 };
+enum : int {
+  PH_IDLE = 0, PH_LNEE, PH_LNEE_RES, PH_LREC, PH_LEXT_RES,
+  PH_ESTART, PH_ECAM, PH_ECAM_RES, PH_EREC, PH_EEXT_RES, PH_FIN
+};
+
+struct SmQuery {
+  int stage, kind;
+  int node, sp, pl;
+  const float4* nodes;  // BVH of the stage
+  const float4* tris;
+  vec3 o, d;      // world ray; in the ghost stage the canonical segment
+  float tmax;     // segment end, or the closest t so far (extension)
+  vec3 ro, rd, inv, oi;  // ray in the frame of the stage's BVH
+  int hit;        // visibility: occluded; extension: a closest hit exists
+  Cross c;        // ghost crossings; before them, an extension's closest hit
+                  // (bits of its id, triangle index and object flag in s0, sa, sb)
+};
+
+struct SmLane {
+  uint32_t s, defer;
+  int jd, ph, j, lim;
+  uint32_t smp;      // sample index in its (technique, direction) stream
+  vec3 p, n;
+  uint32_t md;
+  Cross pred;        // crossings into the vertex
+  vec3 other;        // light walk: the neighbour towards the camera; eye walk: the point towards the light
+  int dyn, ok;
+  LightEnd E;        // the light end of the connection; from an extension on, its hit
+                     // (p, n and material word in p, n, mat)
+  int nE, nL, k2;
+  uint32_t camok, neeok, dynpre;
+};
+
+DEV void sm_stage(SmQuery& q, int stage, const DevBvh& B, vec3 ro, vec3 rd) {
+  q.stage = stage;
+  q.node = 0;
+  q.sp = 0;
+  q.pl = 0;
+  q.nodes = B.nodes;
+  q.tris = B.tris;
+  q.ro = ro;
+  q.rd = rd;
+  q.inv = v3(1.0f / rd.x, 1.0f / rd.y, 1.0f / rd.z);
+  q.oi = v3(ro.x * q.inv.x, ro.y * q.inv.y, ro.z * q.inv.z);
+}
+
+template <bool CW>
+DEV void sm_visibility(SmQuery& q, const DevScene& S, const End& A, const End& B, int ray_type, WorkCount& wc) {
+  if (CW) wc.rays[ray_type]++;
+  const Seg sg = canon(S, A, B);
+  q.kind = QK_VIS;
+  q.o = sg.o;
+  q.d = sg.d;
+  q.tmax = sg.tmax;
+  q.hit = 0;
+  q.c = no_cross();
+  sm_stage(q, QS_STAT, S.stat, sg.o, sg.d);
+}
+
+template <bool CW>
+DEV void sm_extension(SmQuery& q, const DevScene& S, vec3 o, vec3 d, WorkCount& wc) {
+  if (CW) wc.rays[RAY_CLOSEST]++;
+  q.kind = QK_EXT;
+  q.o = o;
+  q.d = d;
+  q.tmax = INFINITY;
+  q.hit = 0;
+  q.c = Cross{0.0f, __int_as_float(0x7fffffff), __int_as_float(-1), __int_as_float(0)};
+  sm_stage(q, QS_STAT, S.stat, o, d);
+}
+
+// The next stage of a lane's query once the traversal of its current stage
+// has ended (QS_NONE: the query is answered).
+template <bool CW>
+DEV void sm_next(SmQuery& q, SmLane& L, const DevScene& S, const DevFrame& F, WorkCount& wc) {
+  if (q.stage == QS_GHOST) {
+    q.stage = QS_NONE;
+    return;
   }
-  const int64_t g = A.item0 + s / kItem;
-  const DevJob& J = A.jobs[jd >> 1];
-  const int dir = jd & 1;
-  const int64_t smp = J.s0 + (g - A.item_prefix[jd]) * kItem + s % kItem;
-  const Ctx C{J.S, J.F[dir], A.W, A.depth};
-  Lane L{C, Rng{A.k0, A.k1, (uint32_t)smp, ((uint32_t)TECH << 24) | ((uint32_t)dir << 23), A.job_base + (uint32_t)(jd >> 1)},
-         (int)s, stk, WorkCount{}, 0, 0, 0u, 0u, 0u, (int)k2, smp, 0u};
-  if (act) {
-    if (defer & 1u) {
-      const WalkStart w = load_walk(A.W, 1, t);
-      light_walk<CW>(L, w.p, w.n, w.md, w.pred, w.end, w.lim, false);
-    }
-    if (defer & 2u) {
-      const WalkStart w = load_walk(A.W, 6, t);
-      eye_walk<CW>(L, w.p, w.n, w.md, w.pred, w.end, w.lim);
-    }
-    A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
+  if (q.kind == QK_VIS && q.hit) {  // blocked
+    q.stage = QS_NONE;
+    return;
   }
-  const int c = act ? pair_count<TECH>(L, A.depth) : 0;
-  int total;
-  const uint32_t at = wave_reserve(A.W.npairs, c, total);
-  if (c > 0 && at + (uint32_t)c <= (uint32_t)A.W.pair_cap) write_pairs<TECH>(L, A.W.pairs + at, A.depth);
-  if (CW) {
-    L.wc.bytes += 4u * (uint32_t)c + (act ? 4u : 0u);
-    flush_work(A.stats, kid_walk(TECH), L.wc);
+  if (q.stage == QS_STAT && box_hit(F.olo, F.ohi, q.o, q.d, q.tmax)) {
+    sm_stage(q, QS_OBJ, S.obj, pose_inv_apply(F.pose, q.o), pose_inv_rot(F.pose, q.d));
+    return;
+  }
+  if (q.kind == QK_VIS) {  // visible: the ghost crossings of the same segment
+    if (F.ghosts) {
+      if (CW) wc.rays[RAY_GHOST]++;
+      if (box_hit(F.glo, F.ghi, q.o, q.d, q.tmax)) {
+        sm_stage(q, QS_GHOST, S.obj, pose_inv_apply(F.ghost, q.o), pose_inv_rot(F.ghost, q.d));
+        return;
+      }
+    }
+    q.stage = QS_NONE;
+    return;
+  }
+  // extension: the new vertex, then the ghost crossings of the new edge (its
+  // end nearer the camera first)
+  q.stage = QS_NONE;
+  if (!q.hit) return;
+  const Hit h{q.tmax, __float_as_int(q.c.s0), __float_as_int(q.c.sa), __float_as_int(q.c.sb), 1};
+  q.c = no_cross();
+  hit_vertex(S, F.pose, h, q.o, q.d, L.E.p, L.E.n, L.E.mat);
+  if (is_emitter(S, L.E.mat) || !F.ghosts) return;
+  if (CW) wc.rays[RAY_GHOST]++;
+  const bool light = L.ph == PH_LEXT_RES;
+  const End A = light ? end_surf(L.p, L.n) : end_surf(L.E.p, L.E.n);
+  const End B = light ? end_surf(L.E.p, L.E.n) : end_surf(L.p, L.n);
+  const Seg sg = canon(S, A, B);
+  if (!box_hit(F.glo, F.ghi, sg.o, sg.d, sg.tmax)) return;
+  q.o = sg.o;
+  q.d = sg.d;
+  q.tmax = sg.tmax;
+  sm_stage(q, QS_GHOST, S.obj, pose_inv_apply(F.ghost, sg.o), pose_inv_rot(F.ghost, sg.d));
+}
+
+// Ends a, b of the line along which a ghost-started technique generates the
+// edge of the lane's query (as edge_cross takes them from the edge's ends).
+DEV void sm_line(const SmLane& L, const DevScene& S, vec3& a, vec3& b, int& env) {
+  env = 0;
+  if (L.ph == PH_LNEE_RES) {  // x_j -> light point (offset) or environment
+    a = L.p;
+    env = L.E.env;
+    b = env ? L.p : spawn(S, L.E.p, L.E.n, L.p);
+  } else if (L.ph == PH_ECAM_RES) {  // pinhole -> x_i
+    a = S.cam.eye;
+    b = L.p;
+  } else if (L.ph == PH_LEXT_RES) {  // x_j -> new vertex
+    a = L.p;
+    b = L.E.p;
+  } else {  // new vertex -> x_i
+    a = L.E.p;
+    b = L.p;
   }
 }
 
-// Walk phase: one lane per queued task (full waves), the random walks with
-// their next-event and camera connections, then the sample's connected paths
-// into the path queue.
+// Triangle i of a leaf for the lane's query; true ends the stage (any hit).
+template <bool CW>
+DEV bool sm_triangle(SmQuery& q, const SmLane& L, const DevScene& S, const DevFrame& F, int i, WorkCount& wc) {
+  vec3 v0, e1, e2;
+  int id, mat;
+  load_tri(q.tris, i, v0, e1, e2, id, mat);
+  if (CW) wc.tris++;
+  const float t = tri_t(q.ro, q.rd, v0, e1, e2);
+  if (q.stage == QS_GHOST) {
+    if (!(t > 0.0f && t < q.tmax)) return false;
+    vec3 g = q.o + q.d * t;
+    q.c.n += 1.0f;
+    vec3 a, b;
+    int env;
+    sm_line(L, S, a, b, env);
+    if (!env) {
+      // density only where the generating line itself crosses the triangle
+      const vec3 la = pose_inv_apply(F.ghost, a), ld = pose_inv_rot(F.ghost, b - a);
+      const float tl = tri_t(la, ld, v0, e1, e2);
+      if (!(tl > 0.0f && tl < 1.0f)) return false;
+      g = a + (b - a) * tl;
+    }
+    const vec3 u = env ? unit(q.d) : unit(b - a);
+    const vec3 ng = pose_rot(F.ghost, unit(cross(e1, e2)));
+    const float cg = fabsf(dot(ng, u));
+    q.c.s0 += 1.0f / cg;
+    q.c.sa += len2(g - a) / cg;
+    q.c.sb += env ? 0.0f : len2(g - b) / cg;
+    return false;
+  }
+  if (q.kind == QK_VIS) {
+    if (t > 0.0f && t < q.tmax) {
+      q.hit = 1;
+      return true;
+    }
+    return false;
+  }
+  if (t > 0.0f && (t < q.tmax || (t == q.tmax && id < __float_as_int(q.c.s0)))) {
+    q.tmax = t;
+    q.c.s0 = __int_as_float(id);
+    q.c.sa = __int_as_float(i);
+    q.c.sb = __int_as_float(q.stage == QS_OBJ ? 1 : 0);
+    q.hit = 1;
+  }
+  return false;
+}
+
+DEV Rng sm_rng(const WalkArgs& A, const SmLane& L, int tech) {
+  return Rng{A.k0, A.k1, L.smp, ((uint32_t)tech << 24) | ((uint32_t)(L.jd & 1) << 23),
+             A.job_base + (uint32_t)(L.jd >> 1)};
+}
+
+DEV void sm_begin(const WalkArgs& A, SmLane& L, uint32_t t) {
+  const float4 h = TSK(A.W, 0, t);
+  L.s = __float_as_uint(h.x);
+  L.defer = __float_as_uint(h.y);
+  L.k2 = (int)__float_as_uint(h.z);
+  const int64_t g = A.item0 + L.s / kItem;
+  L.jd = find_jd(A.item_prefix, 2 * A.njobs, g);
+  L.smp = (uint32_t)(A.jobs[L.jd >> 1].s0 + (g - A.item_prefix[L.jd]) * kItem + L.s % kItem);
+  L.nE = L.nL = 0;
+  L.camok = L.neeok = L.dynpre = 0u;
+  L.ph = PH_ESTART;
+  if (L.defer & 1u) {
+    const WalkStart w = load_walk(A.W, 1, t);
+    L.p = w.p;
+    L.n = w.n;
+    L.md = w.md;
+    L.pred = w.pred;
+    L.other = w.end.p;
+    L.lim = w.lim;
+    L.j = 0;
+    L.dyn = 0;
+    L.ph = PH_LNEE;
+  }
+}
+
+// One pass of a lane's walk: it takes its query's answer, moves to the next
+// vertex or walk, and issues its next query, or finishes.  Each block below
+// runs once per pass for all lanes that need it (one random draw, one light
+// sample, one BSDF sample per pass), so lanes in different parts of their
+// walks share the code instead of taking one branch each.
+template <int TECH, bool CW>
+DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount& wc) {
+  const DevJob& J = A.jobs[L.jd >> 1];
+  const DevScene& S = J.S;
+  const DevFrame& F = J.F[L.jd & 1];
+  const Workspace& W = A.W;
+  const int s = (int)L.s;
+  // answers: visibility of a connection, or the next vertex of a walk
+  if (L.ph == PH_LNEE_RES || L.ph == PH_ECAM_RES) {
+    L.ok = q.hit ? 0 : 1;
+    if (q.hit) q.c = no_cross();
+    L.ph = L.ph == PH_LNEE_RES ? PH_LREC : PH_EREC;
+  } else if (L.ph == PH_LEXT_RES || L.ph == PH_EEXT_RES) {
+    const bool light = L.ph == PH_LEXT_RES;
+    if (!q.hit || is_emitter(S, L.E.mat)) {
+      L.ph = light ? PH_ESTART : PH_FIN;
+    } else {
+      L.pred = q.c;
+      // component copies: a struct copy inside the lane state keeps the
+      // compiler from holding it in registers
+      L.other.x = L.p.x;
+      L.other.y = L.p.y;
+      L.other.z = L.p.z;
+      L.p.x = L.E.p.x;
+      L.p.y = L.E.p.y;
+      L.p.z = L.E.p.z;
+      L.n.x = L.E.n.x;
+      L.n.y = L.E.n.y;
+      L.n.z = L.E.n.z;
+      L.md = L.E.mat;
+      L.j += 1;
+      L.ph = light ? PH_LNEE : PH_ECAM;
+    }
+  }
+  if (L.ph == PH_ESTART) {
+    L.ph = PH_FIN;
+    if (L.defer & 2u) {
+      const WalkStart w = load_walk(W, 6, t);
+      L.p = w.p;
+      L.n = w.n;
+      L.md = w.md;
+      L.pred = w.pred;
+      // the point towards the light: the neighbour, or a point along the
+      // environment direction
+      L.other = w.end.kind == END_ENV ? L.p + w.end.n : w.end.p;
+      L.lim = w.lim;
+      L.j = 0;
+      L.ph = PH_ECAM;
+    }
+  }
+  // connections: next-event estimation (light walk), camera (eye walk)
+  if (L.ph == PH_LNEE || L.ph == PH_ECAM) {
+    q.c = no_cross();  // the connection's crossings (none unless it is traced)
+    L.ok = 0;
+    bool go;
+    End ea, eb;
+    int rt;
+    if (L.ph == PH_LNEE) {
+      L.dyn = L.dyn || (L.md & kDynBit) || L.pred.n > 0.0f;
+      float u[4];
+      draw(sm_rng(A, L, TECH), 0, L.j + 1, 1, u);
+      L.E = LightEnd{v3(0, 0, 0), v3(0, 0, 0), 0u, 0};
+      go = sample_light(S, u, L.E);
+      if (go)
+        go = L.E.env ? same_side_dir(L.n, L.p, L.other, L.E.n)
+                     : (dot(L.E.n, L.p - L.E.p) > 0.0f && same_side(L.n, L.p, L.other, L.E.p));
+      ea = end_surf(L.p, L.n);
+      eb = end_light(L.E);
+      rt = RAY_SHADOW;
+      L.ph = go ? PH_LNEE_RES : PH_LREC;
+    } else {
+      go = raster(S.cam, L.p) >= 0 && same_side(L.n, L.p, S.cam.eye, L.other);
+      ea = end_eye(S);
+      eb = end_surf(L.p, L.n);
+      rt = RAY_CAMERA;
+      L.ph = go ? PH_ECAM_RES : PH_EREC;
+    }
+    if (go) {
+      sm_visibility<CW>(q, S, ea, eb, rt, wc);
+      return;
+    }
+  }
+  // vertex records, then the extension
+  if (L.ph == PH_LREC || L.ph == PH_EREC) {
+    const bool light = L.ph == PH_LREC;
+    const int j = L.j;
+    if (light) {
+      LIT(W, j, 0, s) = f4u(L.p, L.md);
+      LIT(W, j, 1, s) = f4(L.n, L.pred.n);
+      LIT(W, j, 2, s) = make_float4(L.pred.s0, L.pred.sa, L.pred.sb, 0.0f);
+      LIT(W, j, 3, s) = f4u(L.E.p, light_word(L.E));
+      LIT(W, j, 4, s) = f4(L.E.n, q.c.n);
+      LIT(W, j, 5, s) = make_float4(q.c.s0, q.c.sa, q.c.sb, 0.0f);
+      if (CW) wc.bytes += kLightFields * 16;
+      if (L.dyn || q.c.n > 0.0f) L.dynpre |= 1u << j;
+    } else {
+      EYE(W, j, 0, s) = f4u(L.p, L.md);
+      EYE(W, j, 1, s) = f4(L.n, L.pred.n);
+      EYE(W, j, 2, s) = make_float4(L.pred.s0, L.pred.sa, L.pred.sb, 0.0f);
+      EYE(W, j, 3, s) = make_float4(q.c.n, q.c.s0, q.c.sa, q.c.sb);
+      if (CW) wc.bytes += kEyeFields * 16;
+    }
+    // (selects rather than branches: a store through a chosen field keeps
+    // the lane state out of registers)
+    const uint32_t bit = L.ok ? 1u << j : 0u;
+    L.nL = light ? j + 1 : L.nL;
+    L.nE = light ? L.nE : j + 1;
+    L.neeok |= light ? bit : 0u;
+    L.camok |= light ? 0u : bit;
+    const int end = light ? PH_ESTART : PH_FIN;
+    L.ph = end;
+    if (j < L.lim) {
+      float u[4];
+      draw(sm_rng(A, L, TECH), light ? 0u : 1u, j + 1, 0, u);
+      vec3 wo;
+      if (bsdf_sample(vmat(S, F, L.md), L.n, unit(L.other - L.p), u[0], u[1], wo)) {
+        sm_extension<CW>(q, S, spawn_dir(S, L.p, L.n, wo), wo, wc);
+        L.ph = light ? PH_LEXT_RES : PH_EEXT_RES;
+      }
+    }
+  }
+}
+
+#ifndef RPI_SM_REFILL
+#define RPI_SM_REFILL 32
+#endif
+
+// Walk phase: persistent waves; see the state machine above.  Lanes hand the
+// wave their finished tasks' connected paths with one queue reservation per
+// wave and take new tasks with one counter update per wave.
 template <int TECH, bool CW>
 __global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_task_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
+  constexpr int kDone = 0x7fffffff;  // no node left in the stage
+  const int lane = threadIdx.x;
   const uint32_t n = min(*A.W.ntasks, (uint32_t)A.W.Q);
+  WorkCount wc{};
+  SmLane L;
+  L.ph = PH_IDLE;
+  SmQuery q;
+  q.stage = QS_NONE;
+  q.node = kDone;
+  q.pl = 0;
+  uint32_t t = 0;
+  bool drained = false;
   for (;;) {
-    const uint32_t base = next_batch(&A.W.fetch[0]);
-    if (base >= n) break;
-    const uint32_t t = base + threadIdx.x;
-    const bool act = t < n;
-    const uint32_t s = act ? __float_as_uint(TSK(A.W, 0, t).x) : 0u;
-    // the sample behind the slot: item -> (job, direction)
-    const int jd = act ? find_jd(A.item_prefix, 2 * A.njobs, A.item0 + s / kItem) : 0;
-    const int jd0 = __builtin_amdgcn_readfirstlane(jd);
-    if (__ballot(act && jd != jd0) == 0ull) run_task<TECH, CW>(A, jd0, t, s, act, stk);
-    else run_task<TECH, CW>(A, jd, t, s, act, stk);
+    // connected paths of the finished tasks
+    const unsigned long long fin = __ballot(L.ph == PH_FIN);
+    if (fin) {
+      const bool f = L.ph == PH_FIN;
+      const int c = f ? pair_count<TECH>(L, A.depth) : 0;
+      int total;
+      const uint32_t at = wave_reserve(A.W.npairs, c, total);
+      if (c > 0 && at + (uint32_t)c <= (uint32_t)A.W.pair_cap) write_pairs<TECH>(L, A.W.pairs + at, A.depth);
+      if (f) {
+        A.W.counts[L.s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
+        if (CW) wc.bytes += 4u * (uint32_t)c + 4u;
+        L.ph = PH_IDLE;
+      }
+    }
+    // idle lanes take the next tasks
+    if (!drained) {
+      const unsigned long long idle = __ballot(L.ph == PH_IDLE);
+      if (idle) {
+        const uint32_t k = (uint32_t)__popcll(idle);
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&A.W.fetch[0], k);
+        base = __builtin_amdgcn_readfirstlane(__shfl(base, 0, kWave));
+        if (base + k >= n) drained = true;
+        if (L.ph == PH_IDLE) {
+          t = base + (uint32_t)__popcll(idle & ((1ull << lane) - 1ull));
+          if (t < n) sm_begin(A, L, t);
+        }
+      }
+    }
+    // every lane steps its walk until it has a query pending or its task is done
+    while (L.ph != PH_IDLE && L.ph != PH_FIN && q.stage == QS_NONE) sm_step<TECH, CW>(A, L, q, t, wc);
+    if (__ballot(q.stage != QS_NONE) == 0ull) {
+      if (drained && __ballot(L.ph != PH_IDLE) == 0ull) break;
+      continue;
+    }
+    // the queries of all lanes, stage by stage, until every one is answered
+    for (;;) {
+      if (q.stage != QS_NONE && q.node == kDone && q.pl == 0) {
+        const DevJob& J = A.jobs[L.jd >> 1];
+        sm_next<CW>(q, L, J.S, J.F[L.jd & 1], wc);
+      }
+      // back to the walks when few lanes still trace, so that the others
+      // can take their next queries (all of them once the queue is drained)
+      if (__popcll(__ballot(q.stage != QS_NONE)) <= (drained ? 0 : RPI_SM_REFILL)) break;
+      while (q.stage != QS_NONE && (uint32_t)q.node < (uint32_t)kDone) {
+        const float4 a = gld(q.nodes, 4 * (size_t)q.node), b = gld(q.nodes, 4 * (size_t)q.node + 1),
+                     c = gld(q.nodes, 4 * (size_t)q.node + 2);
+        const int4 e = gld(reinterpret_cast<const int4*>(q.nodes), 4 * (size_t)q.node + 3);
+        if (CW) wc.nodes++;
+        float n0, n1;
+        const bool h0 = slab(a.x, a.y, a.z, a.w, b.x, b.y, q.inv, q.oi, q.tmax, n0);
+        const bool h1 = slab(b.z, b.w, c.x, c.y, c.z, c.w, q.inv, q.oi, q.tmax, n1);
+        const bool first0 = n0 <= n1;
+        if (h0 && h1) {
+          stk[q.sp * kTraceBlock + lane] = first0 ? e.y : e.x;
+          ++q.sp;
+          q.node = first0 ? e.x : e.y;
+        } else if (h0) {
+          q.node = e.x;
+        } else if (h1) {
+          q.node = e.y;
+        } else {
+          q.node = q.sp > 0 ? stk[--q.sp * kTraceBlock + lane] : kDone;
+        }
+        if (q.node < 0 && q.pl == 0) {  // postpone the first leaf and go on with the stack
+          q.pl = q.node;
+          q.node = q.sp > 0 ? stk[--q.sp * kTraceBlock + lane] : kDone;
+        }
+        if (__ballot(q.pl == 0) == 0ull) break;  // every lane still here holds a leaf
+      }
+      while (q.pl < 0) {
+        const DevJob& J = A.jobs[L.jd >> 1];
+        const DevScene& S = J.S;
+        const DevFrame& F = J.F[L.jd & 1];
+        const int f0 = leaf_first(q.pl), cnt = leaf_count(q.pl);
+        bool stop = false;
+        for (int i = f0; i < f0 + cnt; ++i)
+          if (sm_triangle<CW>(q, L, S, F, i, wc)) {
+            stop = true;
+            break;
+          }
+        q.pl = 0;
+        if (stop) {
+          q.node = kDone;
+          break;
+        }
+        if (q.node < 0) {
+          q.pl = q.node;
+          q.node = q.sp > 0 ? stk[--q.sp * kTraceBlock + lane] : kDone;
+        }
+      }
+    }
   }
+  if (CW) flush_work(A.stats, kid_walk(TECH), wc);
 }
 
 // Technique (8), first half: x_D by area, the proposal at x_D (one MLP pass
