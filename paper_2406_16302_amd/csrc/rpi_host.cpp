@@ -76,7 +76,7 @@ struct BuiltBvh {
 
 constexpr int kLeafMax = 4;
 constexpr int kBins = 16;
-constexpr int kMedianDepth = 24;  // below this depth splits are object medians (bounded stack use)
+constexpr int kMedianDepth = 24;  // from this depth on splits are object medians (bounded stack use)
 
 // Binned SAH (16 bins per axis) with object-median splits from depth 24 on;
 // children's boxes are stored in their parent (64-byte nodes).
@@ -105,6 +105,12 @@ class Builder {
       err = "empty triangle set";
       return false;
     }
+    // Object medians halve a node's triangles per level, so starting them at
+    // depth D leaves every leaf within D + ceil(log2(n / kLeafMax)) levels:
+    // D is chosen to keep that under the traversal stack depth.
+    int halvings = 0;
+    while (((int64_t)kLeafMax << halvings) < (int64_t)n) ++halvings;
+    median_depth_ = std::max(1, std::min(kMedianDepth, kStackDepth - 2 - halvings));
     // root node holds the two children of the full range
     out.nodes.resize(4);
     struct Job {
@@ -170,7 +176,7 @@ class Builder {
     for (int i = first; i < first + count; ++i) cb.grow(cen_[order_[i]].data());
     int best_axis = -1, best_bin = -1;
     float best_cost = INFINITY;
-    if (depth < kMedianDepth) {
+    if (depth < median_depth_) {
       for (int a = 0; a < 3; ++a) {
         const float ext = cb.hi[a] - cb.lo[a];
         if (!(ext > 0)) continue;
@@ -287,6 +293,7 @@ class Builder {
   std::vector<std::array<float, 3>> cen_;
   std::vector<Box> box_;
   std::vector<int> order_;
+  int median_depth_ = kMedianDepth;
 };
 
 template <class T>

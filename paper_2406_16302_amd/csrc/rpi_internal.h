@@ -66,7 +66,13 @@ struct DevBvh {
   int32_t ntris;
 };
 
-constexpr int kStackDepth = 48;  // the builder keeps every leaf at depth < kStackDepth
+// Traversal stack entries per lane (LDS: kStackDepth * 256 B per wave).  At
+// 40 a compute unit holds 16 waves of the trace kernels, four per SIMD; the
+// builder keeps every leaf at depth < kStackDepth.
+#ifndef RPI_STACK_DEPTH
+#define RPI_STACK_DEPTH 40
+#endif
+constexpr int kStackDepth = RPI_STACK_DEPTH;
 
 struct DevCamera {
   vec3 eye, fwd, right, up;

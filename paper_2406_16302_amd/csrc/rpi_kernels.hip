@@ -609,10 +609,10 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 // direction, sample range) from a round counter until the round is drained,
 // which balances jobs of uneven image size and uneven per-sample cost.
 // Occupancy target of the trace-heavy kernels (waves per SIMD; 0 leaves the
-// register allocation to the compiler).  The 12 KB LDS stack per wave already
-// limits a compute unit to 13 waves, about 3 per SIMD; asking for 3 caps the
-// registers of the kernels that would otherwise run at 2 (technique 7: -20%
-// time).  Asking for 4 spills without gaining occupancy.
+// register allocation to the compiler).  Asking for 3 caps the registers of
+// the walk-phase and connect kernels, which would otherwise run at 2; asking
+// them for 4 spills.  The start kernels need fewer registers and run at 4,
+// which the 10 KB LDS stack per wave allows (-7% time per step).
 #ifndef RPI_TRACE_WAVES_PER_EU
 #define RPI_TRACE_WAVES_PER_EU 3
 #endif
@@ -620,6 +620,14 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 #define RPI_TRACE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_TRACE_WAVES_PER_EU)))
 #else
 #define RPI_TRACE_OCCUPANCY
+#endif
+#ifndef RPI_START_WAVES_PER_EU
+#define RPI_START_WAVES_PER_EU 4
+#endif
+#if RPI_START_WAVES_PER_EU > 0
+#define RPI_START_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_START_WAVES_PER_EU)))
+#else
+#define RPI_START_OCCUPANCY
 #endif
 
 // ------------------------------------------------------------------ walk tasks
@@ -647,7 +655,7 @@ DEV WalkStart load_walk(const Workspace& W, int f0, uint32_t t) {
 // the task queue (one atomic per wave), so the walk phase runs full waves
 // instead of the few lanes whose starts succeeded.
 template <int TECH, bool CW>
-__global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_kernel(WalkArgs A) {
+__global__ __launch_bounds__(kTraceBlock) RPI_START_OCCUPANCY void walk_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   for (;;) {
     uint32_t it = 0;
@@ -1423,8 +1431,14 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
   // ---- MIS (Sec. 4.3): forward/backward pdf tables
   const float pL = light_pdf(S, E.env);
   const float pD = S.inv_obj_area;
+  // the last scattering vertex x_{k-2}, picked with constant indices (an index
+  // that depends on k would keep the vertex array in scratch memory)
+  PV vl = v[0];
+#pragma unroll
+  for (int q = 1; q < kMaxK - 1; ++q)
+    if (q == k - 2) vl = v[q];
   auto origin = [&](int r, int q) -> vec3 {  // ray origin generating q from r
-    const vec3 to = q == k - 1 ? lpos(E, v[k - 2].p) : v[q].p;
+    const vec3 to = q == k - 1 ? lpos(E, vl.p) : v[q].p;
     if (r == 0) return C.eye;
     if (r == k - 1) return spawn(S, E.p, E.n, to);
     return spawn(S, v[r].p, v[r].n, to);
@@ -1497,9 +1511,13 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
       if (a > k - 2 || !(ex[a].n > 0.0f)) continue;
       if (a == k - 2) {
         if (on(4) && !E.env) {
-          const vec3 o = origin(k - 1, k - 2);
-          const vec3 d = v[k - 2].p - o;
-          sum += pL * pG * ex[a].sb * fabsf(dot(v[k - 2].n, unit(d))) / len2(d) * Apre[k - 3];
+          const vec3 o = spawn(S, E.p, E.n, vl.p);  // the offset light point generating x_{k-2}
+          const vec3 d = vl.p - o;
+          float ak = Apre[0];
+#pragma unroll
+          for (int q = 1; q < kMaxK; ++q)
+            if (q == k - 3) ak = Apre[q];
+          sum += pL * pG * ex[a].sb * fabsf(dot(vl.n, unit(d))) / len2(d) * ak;
         }
       } else if (a == 0) {
         if (on(5)) {
@@ -1610,7 +1628,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
           if (!same_side(cur.n, cur.p, a, b)) rej = 6;
         }
         if (!rej && !E.env) {
-          const vec3 prv = k - 2 == istar ? y.p : v[k - 2].p;
+          const vec3 prv = k - 2 == istar ? y.p : vl.p;
           if (!(dot(E.n, prv - E.p) > 0.0f)) rej = 6;
         }
       }
