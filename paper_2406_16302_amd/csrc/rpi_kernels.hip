@@ -609,12 +609,12 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 // direction, sample range) from a round counter until the round is drained,
 // which balances jobs of uneven image size and uneven per-sample cost.
 // Occupancy target of the trace-heavy kernels (waves per SIMD; 0 leaves the
-// register allocation to the compiler).  Asking for 3 caps the registers of
-// the walk-phase and connect kernels, which would otherwise run at 2; asking
-// them for 4 spills.  The start kernels need fewer registers and run at 4,
-// which the 10 KB LDS stack per wave allows (-7% time per step).
+// register allocation to the compiler).  The 10 KB LDS stack per wave lets a
+// compute unit hold 16 waves, four per SIMD; at four the walk-phase and
+// connect kernels spill a few registers, and still run faster than at three
+// (measured: -8% time per step for the start kernels, -4% for the others).
 #ifndef RPI_TRACE_WAVES_PER_EU
-#define RPI_TRACE_WAVES_PER_EU 3
+#define RPI_TRACE_WAVES_PER_EU 4
 #endif
 #if RPI_TRACE_WAVES_PER_EU > 0
 #define RPI_TRACE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_TRACE_WAVES_PER_EU)))
@@ -622,8 +622,17 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 #define RPI_TRACE_OCCUPANCY
 #endif
 #ifndef RPI_START_WAVES_PER_EU
-#define RPI_START_WAVES_PER_EU 4
+#define RPI_START_WAVES_PER_EU RPI_TRACE_WAVES_PER_EU
 #endif
+#if RPI_START_WAVES_PER_EU > 0
+#define RPI_START_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_START_WAVES_PER_EU)))
+#else
+#define RPI_START_OCCUPANCY
+#endif
+#ifndef RPI_WALK_WAVES_PER_EU
+#define RPI_WALK_WAVES_PER_EU RPI_TRACE_WAVES_PER_EU
+#endif
+#define RPI_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_WALK_WAVES_PER_EU)))
 #if RPI_START_WAVES_PER_EU > 0
 #define RPI_START_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_START_WAVES_PER_EU)))
 #else
@@ -1080,7 +1089,7 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
 // wave their finished tasks' connected paths with one queue reservation per
 // wave and take new tasks with one counter update per wave.
 template <int TECH, bool CW>
-__global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void walk_task_kernel(WalkArgs A) {
+__global__ __launch_bounds__(kTraceBlock) RPI_WALK_OCCUPANCY void walk_task_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   constexpr int kDone = 0x7fffffff;  // no node left in the stage
   const int lane = threadIdx.x;
@@ -1666,10 +1675,18 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
   const float sc = A.sigma / sum * A.inv_n;
   rec = make_float4(__int_as_float(pixel | (A.job << 24)), val.x * sc, val.y * sc, val.z * sc);
   if (A.mlp && (T == 2 || T == 3) && pgen > 0.0f) {
+    // x_m = x_D (m = i + 2) and its light-side neighbour, by constant indices
     const int m = i + 2;
-    const vec3 o = origin(m, m + 1);
-    const vec3 w = pose_inv_rot(A.F.pose, unit(v[m + 1].p - o));
-    mlp_input(*A.mlp, pose_inv_apply(A.F.pose, v[m].p), pose_inv_rot(A.F.pose, v[m].n), tr.x);
+    PV xm = v[0], xn = v[0];
+#pragma unroll
+    for (int q = 1; q < kMaxK - 1; ++q) {
+      if (q == m) xm = v[q];
+      if (q == m + 1) xn = v[q];
+    }
+    const vec3 to = m + 1 == k - 1 ? lpos(E, vl.p) : xn.p;
+    const vec3 o = spawn(S, xm.p, xm.n, to);  // the ray origin generating x_{m+1} from x_m
+    const vec3 w = pose_inv_rot(A.F.pose, unit(xn.p - o));
+    mlp_input(*A.mlp, pose_inv_apply(A.F.pose, xm.p), pose_inv_rot(A.F.pose, xm.n), tr.x);
     tr.w[0] = w.x;
     tr.w[1] = w.y;
     tr.w[2] = w.z;
