@@ -193,6 +193,16 @@ DEV vec3 spawn_dir(const DevScene& S, vec3 p, vec3 n, vec3 dir) {
   return p + n * (s * S.eps);
 }
 
+// A ray from point p on the object (geometric normal n) in direction dir
+// leaves the object for good when the object is convex and dir points to the
+// outer side of the face, the side away from a point inside (its centre at
+// this pose): the object's BVH can be skipped for it.
+DEV bool leaves_convex(const DevScene& S, const Pose& pose, vec3 p, vec3 n, vec3 dir) {
+  if (!S.obj_convex) return false;
+  const vec3 c = pose_apply(pose, S.obj_center);
+  return dot(n, p - c) * dot(n, dir) > 0.0f;
+}
+
 // ------------------------------------------------------------------ triangles
 
 // Scene arrays are reached through pointers read from the job table, which

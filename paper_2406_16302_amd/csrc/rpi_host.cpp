@@ -10,6 +10,8 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <atomic>
+#include <thread>
 #include <random>
 #include <string>
 #include <vector>
@@ -362,6 +364,62 @@ struct rpi_proposal {
 
 static bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
+// Whether the object's triangles bound a convex solid: every vertex lies on
+// the inner side (the side of the vertex mean c) of every face plane, within
+// tol.  A face whose plane passes through c (within tol) makes it non-convex.
+// Rays leaving a convex object through its surface cannot meet it again,
+// which lets the kernels skip its BVH for them.  O(faces x vertices), on
+// host threads.
+static bool object_convex(const std::vector<HostTri>& obj, double tol, vec3& center) {
+  std::vector<std::array<float, 3>> v;
+  v.reserve(3 * obj.size());
+  for (const auto& t : obj)
+    for (const float* p : {t.v0, t.v1, t.v2}) v.push_back({p[0], p[1], p[2]});
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  double c[3] = {0, 0, 0};
+  for (const auto& p : v)
+    for (int a = 0; a < 3; ++a) c[a] += p[a];
+  for (int a = 0; a < 3; ++a) c[a] /= (double)v.size();
+  center = v3((float)c[0], (float)c[1], (float)c[2]);
+  const int nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::atomic<bool> ok{true};
+  std::vector<std::thread> th;
+  for (int w = 0; w < nt; ++w)
+    th.emplace_back([&, w] {
+      for (size_t f = w; f < obj.size() && ok.load(std::memory_order_relaxed); f += nt) {
+        const HostTri& t = obj[f];
+        double e1[3], e2[3], n[3];
+        for (int a = 0; a < 3; ++a) {
+          e1[a] = (double)t.v1[a] - t.v0[a];
+          e2[a] = (double)t.v2[a] - t.v0[a];
+        }
+        n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (!(len > 0)) {
+          ok = false;
+          return;
+        }
+        const double d = (n[0] * t.v0[0] + n[1] * t.v0[1] + n[2] * t.v0[2]) / len;
+        const double sc = (n[0] * c[0] + n[1] * c[1] + n[2] * c[2]) / len - d;
+        if (!(std::fabs(sc) > tol)) {
+          ok = false;
+          return;
+        }
+        const double s = sc > 0 ? 1.0 : -1.0;
+        for (const auto& p : v)
+          if (s * ((n[0] * p[0] + n[1] * p[1] + n[2] * p[2]) / len - d) < -tol) {
+            ok = false;
+            return;
+          }
+      }
+    });
+  for (auto& x : th) x.join();
+  return ok.load();
+}
+
 extern "C" const char* rpi_last_error(void) { return g_err.c_str(); }
 extern "C" const char* rpi_version(void) { return "rpi 0.1 (gfx950)"; }
 
@@ -534,6 +592,7 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, rpi_scene** out) 
   C.a_film = (float)(4.0 * (double)C.aspect * (double)C.tan_half * (double)C.tan_half);
   if (!(std::fabs(dot(C.right, C.right) - 1.0f) < 1e-3f)) return fail(RPI_ERR_INVALID_ARG, "camera up parallel to view");
   D.eps = (float)(1e-4 * diag);
+  D.obj_convex = object_convex(obj, 1e-6 * diag, D.obj_center) ? 1 : 0;
   S->W = C.W;
   S->H = C.H;
   *out = S.release();

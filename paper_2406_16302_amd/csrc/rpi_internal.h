@@ -97,6 +97,8 @@ struct DevScene {
   vec3 env;
   DevCamera cam;
   float eps;            // ray offset: 1e-4 of the scene diagonal
+  int32_t obj_convex;   // the object bounds a convex solid (every vertex on the inner side of every face)
+  vec3 obj_center;      // a point inside it (object space): the mean of its vertices
 };
 
 struct Material {

@@ -752,6 +752,7 @@ struct SmQuery {
   float tmax;     // segment end, or the closest t so far (extension)
   vec3 ro, rd, inv, oi;  // ray in the frame of the stage's BVH
   int hit;        // visibility: occluded; extension: a closest hit exists
+  int noobj;      // the ray leaves the (convex) object it starts on: no object stage
   Cross c;        // ghost crossings; before them, an extension's closest hit
                   // (bits of its id, triangle index and object flag in s0, sa, sb)
 };
@@ -785,10 +786,12 @@ DEV void sm_stage(SmQuery& q, int stage, const DevBvh& B, vec3 ro, vec3 rd) {
 }
 
 template <bool CW>
-DEV void sm_visibility(SmQuery& q, const DevScene& S, const End& A, const End& B, int ray_type, WorkCount& wc) {
+DEV void sm_visibility(SmQuery& q, const DevScene& S, const End& A, const End& B, int ray_type, bool noobj,
+                       WorkCount& wc) {
   if (CW) wc.rays[ray_type]++;
   const Seg sg = canon(S, A, B);
   q.kind = QK_VIS;
+  q.noobj = noobj ? 1 : 0;
   q.o = sg.o;
   q.d = sg.d;
   q.tmax = sg.tmax;
@@ -798,9 +801,10 @@ DEV void sm_visibility(SmQuery& q, const DevScene& S, const End& A, const End& B
 }
 
 template <bool CW>
-DEV void sm_extension(SmQuery& q, const DevScene& S, vec3 o, vec3 d, WorkCount& wc) {
+DEV void sm_extension(SmQuery& q, const DevScene& S, vec3 o, vec3 d, bool noobj, WorkCount& wc) {
   if (CW) wc.rays[RAY_CLOSEST]++;
   q.kind = QK_EXT;
+  q.noobj = noobj ? 1 : 0;
   q.o = o;
   q.d = d;
   q.tmax = INFINITY;
@@ -821,7 +825,7 @@ DEV void sm_next(SmQuery& q, SmLane& L, const DevScene& S, const DevFrame& F, Wo
     q.stage = QS_NONE;
     return;
   }
-  if (q.stage == QS_STAT && box_hit(F.olo, F.ohi, q.o, q.d, q.tmax)) {
+  if (q.stage == QS_STAT && !q.noobj && box_hit(F.olo, F.ohi, q.o, q.d, q.tmax)) {
     sm_stage(q, QS_OBJ, S.obj, pose_inv_apply(F.pose, q.o), pose_inv_rot(F.pose, q.d));
     return;
   }
@@ -839,6 +843,7 @@ DEV void sm_next(SmQuery& q, SmLane& L, const DevScene& S, const DevFrame& F, Wo
   // extension: the new vertex, then the ghost crossings of the new edge (its
   // end nearer the camera first)
   q.stage = QS_NONE;
+  q.noobj = 0;
   if (!q.hit) return;
   const Hit h{q.tmax, __float_as_int(q.c.s0), __float_as_int(q.c.sa), __float_as_int(q.c.sb), 1};
   q.c = no_cross();
@@ -1012,7 +1017,7 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
   if (L.ph == PH_LNEE || L.ph == PH_ECAM) {
     q.c = no_cross();  // the connection's crossings (none unless it is traced)
     L.ok = 0;
-    bool go;
+    bool go, noobj = false;
     End ea, eb;
     int rt;
     if (L.ph == PH_LNEE) {
@@ -1027,16 +1032,19 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
       ea = end_surf(L.p, L.n);
       eb = end_light(L.E);
       rt = RAY_SHADOW;
+      if (go && (L.md & kDynBit))
+        noobj = leaves_convex(S, F.pose, L.p, L.n, L.E.env ? L.E.n : L.E.p - L.p);
       L.ph = go ? PH_LNEE_RES : PH_LREC;
     } else {
       go = raster(S.cam, L.p) >= 0 && same_side(L.n, L.p, S.cam.eye, L.other);
       ea = end_eye(S);
       eb = end_surf(L.p, L.n);
       rt = RAY_CAMERA;
+      if (go && (L.md & kDynBit)) noobj = leaves_convex(S, F.pose, L.p, L.n, S.cam.eye - L.p);
       L.ph = go ? PH_ECAM_RES : PH_EREC;
     }
     if (go) {
-      sm_visibility<CW>(q, S, ea, eb, rt, wc);
+      sm_visibility<CW>(q, S, ea, eb, rt, noobj, wc);
       return;
     }
   }
@@ -1074,7 +1082,8 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
       draw(sm_rng(A, L, TECH), light ? 0u : 1u, j + 1, 0, u);
       vec3 wo;
       if (bsdf_sample(vmat(S, F, L.md), L.n, unit(L.other - L.p), u[0], u[1], wo)) {
-        sm_extension<CW>(q, S, spawn_dir(S, L.p, L.n, wo), wo, wc);
+        sm_extension<CW>(q, S, spawn_dir(S, L.p, L.n, wo), wo,
+                         (L.md & kDynBit) && leaves_convex(S, F.pose, L.p, L.n, wo), wc);
         L.ph = light ? PH_LEXT_RES : PH_EEXT_RES;
       }
     }
