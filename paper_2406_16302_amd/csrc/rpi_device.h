@@ -364,9 +364,10 @@ DEV void closest_in(const DevBvh& B, vec3 o, vec3 d, Hit& h, int dyn, int* stk, 
 }
 
 // Closest hit in scene_f: static geometry plus the object at `pose`.
+// noobj: the ray leaves the convex object it starts on (leaves_convex).
 template <bool CW>
 DEV Hit closest(const DevScene& S, const Pose& pose, vec3 olo, vec3 ohi, vec3 o, vec3 d, int* stk,
-                WorkCount& wc, int ray_type = RAY_CLOSEST) {
+                WorkCount& wc, int ray_type = RAY_CLOSEST, bool noobj = false) {
   if (CW) wc.rays[ray_type]++;
   Hit h;
   h.t = INFINITY;
@@ -375,7 +376,8 @@ DEV Hit closest(const DevScene& S, const Pose& pose, vec3 olo, vec3 ohi, vec3 o,
   h.dyn = 0;
   h.ok = 0;
   closest_in<CW>(S.stat, o, d, h, 0, stk, wc);
-  if (box_hit(olo, ohi, o, d, h.t)) closest_in<CW>(S.obj, pose_inv_apply(pose, o), pose_inv_rot(pose, d), h, 1, stk, wc);
+  if (!noobj && box_hit(olo, ohi, o, d, h.t))
+    closest_in<CW>(S.obj, pose_inv_apply(pose, o), pose_inv_rot(pose, d), h, 1, stk, wc);
   return h;
 }
 
@@ -403,9 +405,9 @@ DEV bool any_in(const DevBvh& B, vec3 o, vec3 d, float tmax, int* stk, WorkCount
 // Any hit of scene_f on o + t d, 0 < t < tmax.
 template <bool CW>
 DEV bool occluded(const DevScene& S, const Pose& pose, vec3 olo, vec3 ohi, vec3 o, vec3 d, float tmax, int* stk,
-                  WorkCount& wc) {
+                  WorkCount& wc, bool noobj = false) {
   if (any_in<CW>(S.stat, o, d, tmax, stk, wc)) return true;
-  if (!box_hit(olo, ohi, o, d, tmax)) return false;
+  if (noobj || !box_hit(olo, ohi, o, d, tmax)) return false;
   return any_in<CW>(S.obj, pose_inv_apply(pose, o), pose_inv_rot(pose, d), tmax, stk, wc);
 }
 
@@ -509,10 +511,10 @@ DEV Cross edge_cross(const DevScene& S, const DevFrame& F, const End& A, const E
 
 template <bool CW>
 DEV bool edge_visible(const DevScene& S, const DevFrame& F, const End& A, const End& B, int* stk, WorkCount& wc,
-                      int ray_type) {
+                      int ray_type, bool noobj = false) {
   if (CW) wc.rays[ray_type]++;
   const Seg s = canon(S, A, B);
-  return !occluded<CW>(S, F.pose, F.olo, F.ohi, s.o, s.d, s.tmax, stk, wc);
+  return !occluded<CW>(S, F.pose, F.olo, F.ohi, s.o, s.d, s.tmax, stk, wc, noobj);
 }
 
 // ------------------------------------------------------------------ light sampling

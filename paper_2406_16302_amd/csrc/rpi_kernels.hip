@@ -98,7 +98,8 @@ DEV bool extend(Lane& L, vec3 p, vec3 n, uint32_t md, vec3 wi, const float u[4],
   vec3 wo;
   if (!bsdf_sample(m, n, wi, u[0], u[1], wo)) return false;
   const vec3 o = spawn_dir(L.A.S, p, n, wo);
-  const Hit h = closest<CW>(L.A.S, L.A.F.pose, L.A.F.olo, L.A.F.ohi, o, wo, L.stk, L.wc);
+  const bool noobj = (md & kDynBit) && leaves_convex(L.A.S, L.A.F.pose, p, n, wo);
+  const Hit h = closest<CW>(L.A.S, L.A.F.pose, L.A.F.olo, L.A.F.ohi, o, wo, L.stk, L.wc, RAY_CLOSEST, noobj);
   if (!h.ok) return false;
   hit_vertex(L.A.S, L.A.F.pose, h, o, wo, q, qn, qmd);
   return !is_emitter(L.A.S, qmd);
@@ -132,7 +133,8 @@ DEV void light_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End pr
                  : (dot(E.n, p - E.p) > 0.0f && same_side(n, p, prev.p, E.p));
       if (ok) {
         const End cur = end_surf(p, n);
-        ok = edge_visible<CW>(S, A.F, cur, eL, L.stk, L.wc, RAY_SHADOW);
+        const bool noobj = (md & kDynBit) && leaves_convex(S, A.F.pose, p, n, E.env ? E.n : E.p - p);
+        ok = edge_visible<CW>(S, A.F, cur, eL, L.stk, L.wc, RAY_SHADOW, noobj);
         if (ok) nee = edge_cross<CW>(S, A.F, cur, eL, L.stk, L.wc);
       }
     }
@@ -175,7 +177,8 @@ DEV void eye_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End next
     Cross cam = no_cross();
     if (ok) {
       const End e0 = end_eye(S), cur = end_surf(p, n);
-      ok = edge_visible<CW>(S, A.F, e0, cur, L.stk, L.wc, RAY_CAMERA);
+      const bool noobj = (md & kDynBit) && leaves_convex(S, A.F.pose, p, n, S.cam.eye - p);
+      ok = edge_visible<CW>(S, A.F, e0, cur, L.stk, L.wc, RAY_CAMERA, noobj);
       if (ok) cam = edge_cross<CW>(S, A.F, e0, cur, L.stk, L.wc);
     }
     EYE(A.W, i, 0, L.s) = f4u(p, md);
@@ -237,7 +240,9 @@ DEV void tech1(Lane& L) {
   if (!sample_light(S, u, E)) return;
   const End eL = end_light(E);
   if (!E.env && !(dot(E.n, p - E.p) > 0.0f)) return;
-  if (!edge_visible<CW>(S, A.F, end_surf(p, n), eL, L.stk, L.wc, RAY_SHADOW)) return;
+  if (!edge_visible<CW>(S, A.F, end_surf(p, n), eL, L.stk, L.wc, RAY_SHADOW,
+                        leaves_convex(S, A.F.pose, p, n, E.env ? E.n : E.p - p)))
+    return;
   const Cross c = edge_cross<CW>(S, A.F, end_surf(p, n), eL, L.stk, L.wc);
   store_xl(L, E);
   defer_eye(L, p, n, md, c, eL, A.depth - 2);
@@ -257,7 +262,8 @@ DEV void tech2(Lane& L) {
   object_point(S, A.F.pose, u, p, n, md, tri);
   if (raster(S.cam, p) < 0) return;
   const End e0 = end_eye(S), xd = end_surf(p, n);
-  if (!edge_visible<CW>(S, A.F, e0, xd, L.stk, L.wc, RAY_CAMERA)) return;
+  if (!edge_visible<CW>(S, A.F, e0, xd, L.stk, L.wc, RAY_CAMERA, leaves_convex(S, A.F.pose, p, n, S.cam.eye - p)))
+    return;
   const Cross cam = edge_cross<CW>(S, A.F, e0, xd, L.stk, L.wc);
   draw(L.g, 0, 0, 2, u);
   vec3 q, qn;
@@ -285,7 +291,8 @@ DEV void tech3(Lane& L) {
   const vec3 wl = cosine_dir(n, u[0], u[1]);
   if (!(dot(wl, n) > 0.0f)) return;
   const vec3 ol = spawn_dir(S, p, n, wl);
-  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, ol, wl, L.stk, L.wc);
+  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, ol, wl, L.stk, L.wc, RAY_CLOSEST,
+                             leaves_convex(S, A.F.pose, p, n, wl));
   if (!hl.ok) return;
   vec3 l0, l0n;
   uint32_t l0md;
@@ -297,7 +304,8 @@ DEV void tech3(Lane& L) {
   vec3 we;
   if (!bsdf_sample(m, n, unit(l0 - p), u[0], u[1], we)) return;
   const vec3 oe = spawn_dir(S, p, n, we);
-  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, oe, we, L.stk, L.wc);
+  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, oe, we, L.stk, L.wc, RAY_CLOSEST,
+                             leaves_convex(S, A.F.pose, p, n, we));
   if (!he.ok) return;
   vec3 e0, e0n;
   uint32_t e0md;
@@ -324,7 +332,8 @@ DEV void tech8(Lane& L) {
   const vec3 p = xyz(a), n = xyz(b), wl = xyz(c);
   const uint32_t md = __float_as_uint(a.w);
   const vec3 ol = spawn_dir(S, p, n, wl);
-  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, ol, wl, L.stk, L.wc);
+  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, ol, wl, L.stk, L.wc, RAY_CLOSEST,
+                             leaves_convex(S, A.F.pose, p, n, wl));
   if (!hl.ok) return;
   vec3 l0, l0n;
   uint32_t l0md;
@@ -335,7 +344,7 @@ DEV void tech8(Lane& L) {
   Cross cam = no_cross();
   if (raster(S.cam, p) >= 0 && same_side(n, p, S.cam.eye, l0)) {
     const End e0 = end_eye(S);
-    if (edge_visible<CW>(S, A.F, e0, xd, L.stk, L.wc, RAY_CAMERA)) {
+    if (edge_visible<CW>(S, A.F, e0, xd, L.stk, L.wc, RAY_CAMERA, leaves_convex(S, A.F.pose, p, n, S.cam.eye - p))) {
       cam = edge_cross<CW>(S, A.F, e0, xd, L.stk, L.wc);
       L.k2 = 1;
     }
@@ -352,7 +361,8 @@ DEV void tech8(Lane& L) {
   vec3 we;
   if (!bsdf_sample(m, n, unit(l0 - p), u[0], u[1], we)) return;
   const vec3 oe = spawn_dir(S, p, n, we);
-  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, oe, we, L.stk, L.wc);
+  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, oe, we, L.stk, L.wc, RAY_CLOSEST,
+                             leaves_convex(S, A.F.pose, p, n, we));
   if (!he.ok) return;
   vec3 e0, e0n;
   uint32_t e0md;

@@ -197,8 +197,10 @@ def box_mesh(center, half):
 # --- workloads --------------------------------------------------------------
 
 def cornell_motion(width=64, height=64, spp=16, depth=3, seed=1001,
-                   offset=(0.1, 0.0, 0.05)) -> Workload:
-    """Tiny Cornell box with a moving 12-triangle cube (24 triangles)."""
+                   offset=(0.1, 0.0, 0.05), two_cubes=False) -> Workload:
+    """Tiny Cornell box with a moving 12-triangle cube (24 triangles), or with
+    a moving object made of two cubes with a gap between them (a non-convex
+    object that shadows and reflects onto itself)."""
     mats = [mat(DIFFUSE, (0.7, 0.7, 0.7)), mat(DIFFUSE, (0.7, 0.1, 0.1)),
             mat(DIFFUSE, (0.1, 0.7, 0.1)), mat(EMITTER, emission=(15, 15, 15)),
             mat(DIFFUSE, (0.7, 0.7, 0.7))]
@@ -211,9 +213,15 @@ def cornell_motion(width=64, height=64, spp=16, depth=3, seed=1001,
     m.add_quad((s, -s, -s), (s, -s, s), (s, s, s), (s, s, -s), 2)       # right, -x
     ly, lh = 0.499, 0.1
     m.add_quad((-lh, ly, -lh), (lh, ly, -lh), (lh, ly, lh), (-lh, ly, lh), 3)  # light, -y
-    # cube of side 0.3 lifted 1e-3 above the floor (no coplanar contact)
-    v, f = box_mesh((-0.05, -0.349, -0.05), (0.15, 0.15, 0.15))
-    m.add(v, f, 4, obj=1)
+    if two_cubes:
+        # two cubes of side 0.16, 0.06 apart, lifted 1e-3 above the floor
+        for cx in (-0.16, 0.06):
+            v, f = box_mesh((cx, -0.419, -0.05), (0.08, 0.08, 0.08))
+            m.add(v, f, 4, obj=1)
+    else:
+        # cube of side 0.3 lifted 1e-3 above the floor (no coplanar contact)
+        v, f = box_mesh((-0.05, -0.349, -0.05), (0.15, 0.15, 0.15))
+        m.add(v, f, 4, obj=1)
     cam = [0, 0, 1.7, 0, 0, 0, 0, 1, 0, 40.0, width, height]
     scene = m.build(mats, (0, 0, 0), cam)
     return Workload("cornell_motion", scene, Edit(EDIT_RIGID, translation(offset)),

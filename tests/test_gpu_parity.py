@@ -91,6 +91,13 @@ def test_ghost_plane_open_object():
     _parity(scenes.ghost_plane(width=24, height=24, open_object=True))
 
 
+def test_nonconvex_object_motion():
+    """A moving object of two cubes: rays leaving one cube can meet the other,
+    so the object's BVH must not be skipped for them (it is for convex
+    objects)."""
+    _parity(scenes.cornell_motion(width=32, height=32, spp=8, depth=4, two_cubes=True))
+
+
 def test_chunked_queue_gives_same_image():
     from gpu_parity import gpu_residual
     ws = scenes.cornell_motion(width=32, height=32, spp=4, depth=5)
