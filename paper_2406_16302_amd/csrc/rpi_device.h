@@ -333,6 +333,17 @@ DEV bool box_hit(vec3 lo, vec3 hi, vec3 o, vec3 d, float tlim) {
   return slab(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, inv, oi, tlim, tn);
 }
 
+// Whether the segment o + t d, 0 < t < tlim, comes within radius r of c
+// (a cheap cull before an object's BVH; the sphere is padded).
+DEV bool sphere_near(vec3 c, float r, vec3 o, vec3 d, float tlim) {
+  const vec3 oc = c - o;
+  const float dd = dot(d, d);
+  float t = dot(oc, d) / dd;
+  t = fminf(fmaxf(t, 0.0f), tlim);
+  const vec3 x = o + d * t - c;
+  return dot(x, x) <= r * r;
+}
+
 struct Hit {
   float t;
   int id;    // input triangle index
@@ -363,11 +374,21 @@ DEV void closest_in(const DevBvh& B, vec3 o, vec3 d, Hit& h, int dyn, int* stk, 
   });
 }
 
-// Closest hit in scene_f: static geometry plus the object at `pose`.
+// Whether a ray may meet the object of frame F: its padded box and
+// bounding sphere, both tested against o + t d, 0 < t < tlim.
+DEV bool near_object(const DevFrame& F, vec3 o, vec3 d, float tlim) {
+  return box_hit(F.olo, F.ohi, o, d, tlim) && sphere_near(F.oc, F.orad, o, d, tlim);
+}
+DEV bool near_ghost(const DevFrame& F, vec3 o, vec3 d, float tlim) {
+  return box_hit(F.glo, F.ghi, o, d, tlim) && sphere_near(F.gc, F.orad, o, d, tlim);
+}
+
+// Closest hit in scene_f: static geometry plus the object at F's pose.
 // noobj: the ray leaves the convex object it starts on (leaves_convex).
 template <bool CW>
-DEV Hit closest(const DevScene& S, const Pose& pose, vec3 olo, vec3 ohi, vec3 o, vec3 d, int* stk,
-                WorkCount& wc, int ray_type = RAY_CLOSEST, bool noobj = false) {
+DEV Hit closest(const DevScene& S, const DevFrame& F, vec3 o, vec3 d, int* stk, WorkCount& wc,
+                int ray_type = RAY_CLOSEST, bool noobj = false) {
+  const Pose& pose = F.pose;
   if (CW) wc.rays[ray_type]++;
   Hit h;
   h.t = INFINITY;
@@ -376,7 +397,7 @@ DEV Hit closest(const DevScene& S, const Pose& pose, vec3 olo, vec3 ohi, vec3 o,
   h.dyn = 0;
   h.ok = 0;
   closest_in<CW>(S.stat, o, d, h, 0, stk, wc);
-  if (!noobj && box_hit(olo, ohi, o, d, h.t))
+  if (!noobj && near_object(F, o, d, h.t))
     closest_in<CW>(S.obj, pose_inv_apply(pose, o), pose_inv_rot(pose, d), h, 1, stk, wc);
   return h;
 }
@@ -404,10 +425,11 @@ DEV bool any_in(const DevBvh& B, vec3 o, vec3 d, float tmax, int* stk, WorkCount
 
 // Any hit of scene_f on o + t d, 0 < t < tmax.
 template <bool CW>
-DEV bool occluded(const DevScene& S, const Pose& pose, vec3 olo, vec3 ohi, vec3 o, vec3 d, float tmax, int* stk,
-                  WorkCount& wc, bool noobj = false) {
+DEV bool occluded(const DevScene& S, const DevFrame& F, vec3 o, vec3 d, float tmax, int* stk, WorkCount& wc,
+                  bool noobj = false) {
+  const Pose& pose = F.pose;
   if (any_in<CW>(S.stat, o, d, tmax, stk, wc)) return true;
-  if (noobj || !box_hit(olo, ohi, o, d, tmax)) return false;
+  if (noobj || !near_object(F, o, d, tmax)) return false;
   return any_in<CW>(S.obj, pose_inv_apply(pose, o), pose_inv_rot(pose, d), tmax, stk, wc);
 }
 
@@ -472,7 +494,7 @@ DEV Cross edge_cross(const DevScene& S, const DevFrame& F, const End& A, const E
   if (!F.ghosts) return c;
   if (CW) wc.rays[RAY_GHOST]++;
   const Seg s = canon(S, A, B);
-  if (!box_hit(F.glo, F.ghi, s.o, s.d, s.tmax)) return c;
+  if (!near_ghost(F, s.o, s.d, s.tmax)) return c;
   const bool env = B.kind == END_ENV;
   const vec3 a = A.p;
   const vec3 b = env ? A.p : (B.kind == END_LIGHT ? spawn(S, B.p, B.n, A.p) : B.p);
@@ -514,7 +536,7 @@ DEV bool edge_visible(const DevScene& S, const DevFrame& F, const End& A, const 
                       int ray_type, bool noobj = false) {
   if (CW) wc.rays[ray_type]++;
   const Seg s = canon(S, A, B);
-  return !occluded<CW>(S, F.pose, F.olo, F.ohi, s.o, s.d, s.tmax, stk, wc, noobj);
+  return !occluded<CW>(S, F, s.o, s.d, s.tmax, stk, wc, noobj);
 }
 
 // ------------------------------------------------------------------ light sampling

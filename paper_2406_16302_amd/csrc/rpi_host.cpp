@@ -339,6 +339,7 @@ struct rpi_scene {
   BatchCache* batch = nullptr;
   std::vector<void*> allocs;
   float obj_lo[3], obj_hi[3];  // object bounds in object space (= old pose)
+  float obj_sc[3], obj_sr;     // bounding sphere in object space: centre, radius
   Material obj_mat;
   float diag;
   int W, H;
@@ -545,6 +546,18 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, rpi_scene** out) 
         S->obj_lo[a] = std::min(S->obj_lo[a], p[a]);
         S->obj_hi[a] = std::max(S->obj_hi[a], p[a]);
       }
+  // bounding sphere: centre of the bounds, radius to the farthest vertex (double)
+  {
+    double r2 = 0;
+    for (int a = 0; a < 3; ++a) S->obj_sc[a] = 0.5f * (S->obj_lo[a] + S->obj_hi[a]);
+    for (const auto& t : obj)
+      for (const float* p : {t.v0, t.v1, t.v2}) {
+        double q = 0;
+        for (int a = 0; a < 3; ++a) q += ((double)p[a] - S->obj_sc[a]) * ((double)p[a] - S->obj_sc[a]);
+        r2 = std::max(r2, q);
+      }
+    S->obj_sr = (float)(std::sqrt(r2) * (1.0 + 1e-6));
+  }
   S->obj_mat = mat_of(d->materials + 8 * obj[0].mat);
   for (const auto& t : obj)
     if (t.mat != obj[0].mat) return fail(RPI_ERR_UNSUPPORTED, "the dynamic object must use a single material");
@@ -680,6 +693,10 @@ static DevFrame make_frame(const rpi_scene* s, const float* pose, const float* g
   const float pad = 1e-3f * s->diag;
   world_box(s, F.pose, F.olo, F.ohi, pad);
   world_box(s, F.ghost, F.glo, F.ghi, pad);
+  const vec3 sc = v3(s->obj_sc[0], s->obj_sc[1], s->obj_sc[2]);
+  F.oc = pose_apply(F.pose, sc);
+  F.gc = pose_apply(F.ghost, sc);
+  F.orad = s->obj_sr + pad;
   F.ghosts = ghosts ? 1 : 0;
   F.same_pose = std::memcmp(pose, ghost, 12 * sizeof(float)) == 0 ? 1 : 0;
   return F;

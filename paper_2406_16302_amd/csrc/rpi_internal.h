@@ -114,6 +114,8 @@ struct DevFrame {
   Material objmat; // object material in this frame
   vec3 olo, ohi;   // padded world bounds of the object at pose
   vec3 glo, ghi;   // padded world bounds of the ghost
+  vec3 oc, gc;     // padded bounding spheres of the object at pose and of the ghost:
+  float orad;      //   centres and radius (the same for both)
   int32_t ghosts;  // 1 for motion edits
   int32_t same_pose;  // the two frames place the object identically
 };

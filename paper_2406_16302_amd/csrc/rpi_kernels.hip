@@ -99,7 +99,7 @@ DEV bool extend(Lane& L, vec3 p, vec3 n, uint32_t md, vec3 wi, const float u[4],
   if (!bsdf_sample(m, n, wi, u[0], u[1], wo)) return false;
   const vec3 o = spawn_dir(L.A.S, p, n, wo);
   const bool noobj = (md & kDynBit) && leaves_convex(L.A.S, L.A.F.pose, p, n, wo);
-  const Hit h = closest<CW>(L.A.S, L.A.F.pose, L.A.F.olo, L.A.F.ohi, o, wo, L.stk, L.wc, RAY_CLOSEST, noobj);
+  const Hit h = closest<CW>(L.A.S, L.A.F, o, wo, L.stk, L.wc, RAY_CLOSEST, noobj);
   if (!h.ok) return false;
   hit_vertex(L.A.S, L.A.F.pose, h, o, wo, q, qn, qmd);
   return !is_emitter(L.A.S, qmd);
@@ -291,7 +291,7 @@ DEV void tech3(Lane& L) {
   const vec3 wl = cosine_dir(n, u[0], u[1]);
   if (!(dot(wl, n) > 0.0f)) return;
   const vec3 ol = spawn_dir(S, p, n, wl);
-  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, ol, wl, L.stk, L.wc, RAY_CLOSEST,
+  const Hit hl = closest<CW>(S, A.F, ol, wl, L.stk, L.wc, RAY_CLOSEST,
                              leaves_convex(S, A.F.pose, p, n, wl));
   if (!hl.ok) return;
   vec3 l0, l0n;
@@ -304,7 +304,7 @@ DEV void tech3(Lane& L) {
   vec3 we;
   if (!bsdf_sample(m, n, unit(l0 - p), u[0], u[1], we)) return;
   const vec3 oe = spawn_dir(S, p, n, we);
-  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, oe, we, L.stk, L.wc, RAY_CLOSEST,
+  const Hit he = closest<CW>(S, A.F, oe, we, L.stk, L.wc, RAY_CLOSEST,
                              leaves_convex(S, A.F.pose, p, n, we));
   if (!he.ok) return;
   vec3 e0, e0n;
@@ -332,7 +332,7 @@ DEV void tech8(Lane& L) {
   const vec3 p = xyz(a), n = xyz(b), wl = xyz(c);
   const uint32_t md = __float_as_uint(a.w);
   const vec3 ol = spawn_dir(S, p, n, wl);
-  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, ol, wl, L.stk, L.wc, RAY_CLOSEST,
+  const Hit hl = closest<CW>(S, A.F, ol, wl, L.stk, L.wc, RAY_CLOSEST,
                              leaves_convex(S, A.F.pose, p, n, wl));
   if (!hl.ok) return;
   vec3 l0, l0n;
@@ -361,7 +361,7 @@ DEV void tech8(Lane& L) {
   vec3 we;
   if (!bsdf_sample(m, n, unit(l0 - p), u[0], u[1], we)) return;
   const vec3 oe = spawn_dir(S, p, n, we);
-  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, oe, we, L.stk, L.wc, RAY_CLOSEST,
+  const Hit he = closest<CW>(S, A.F, oe, we, L.stk, L.wc, RAY_CLOSEST,
                              leaves_convex(S, A.F.pose, p, n, we));
   if (!he.ok) return;
   vec3 e0, e0n;
@@ -390,7 +390,7 @@ DEV void tech4(Lane& L) {
   const vec3 o = spawn(S, E.p, E.n, xg);
   const vec3 w = unit(xg - o);
   const float tg = sqrtf(len2(xg - o));
-  const Hit h = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, o, w, L.stk, L.wc);
+  const Hit h = closest<CW>(S, A.F, o, w, L.stk, L.wc);
   if (!h.ok || !(h.t > tg)) return;
   vec3 q, qn;
   uint32_t qmd;
@@ -417,7 +417,7 @@ DEV void tech5(Lane& L) {
   object_point(S, A.F.ghost, u, xg, ng, gmd, tri);
   const vec3 w = unit(xg - S.cam.eye);
   const float tg = sqrtf(len2(xg - S.cam.eye));
-  const Hit h = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, S.cam.eye, w, L.stk, L.wc);
+  const Hit h = closest<CW>(S, A.F, S.cam.eye, w, L.stk, L.wc);
   if (!h.ok || !(h.t > tg)) return;
   vec3 q, qn;
   uint32_t qmd;
@@ -444,13 +444,13 @@ DEV void tech6(Lane& L) {
   object_point(S, A.F.ghost, u, xg, ng, gmd, tri);
   draw(L.g, 0, 0, 2, u);
   const vec3 w = sphere_dir(u[0], u[1]);
-  const Hit hl = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, xg, w, L.stk, L.wc);
+  const Hit hl = closest<CW>(S, A.F, xg, w, L.stk, L.wc);
   if (!hl.ok) return;
   vec3 l0, l0n;
   uint32_t l0md;
   hit_vertex(S, A.F.pose, hl, xg, w, l0, l0n, l0md);
   if (is_emitter(S, l0md)) return;
-  const Hit he = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, xg, -w, L.stk, L.wc);
+  const Hit he = closest<CW>(S, A.F, xg, -w, L.stk, L.wc);
   if (!he.ok) return;
   vec3 e0, e0n;
   uint32_t e0md;
@@ -473,7 +473,7 @@ DEV void tech7(Lane& L) {
   float u[4];
   draw(L.g, 0, 0, 0, u);
   const vec3 w = camera_dir(S.cam, pixel, u[0], u[1]);
-  const Hit h = closest<CW>(S, A.F.pose, A.F.olo, A.F.ohi, S.cam.eye, w, L.stk, L.wc);
+  const Hit h = closest<CW>(S, A.F, S.cam.eye, w, L.stk, L.wc);
   const End e0 = end_eye(S);
   if (!h.ok) {
     if (S.p_env > 0.0f) {
@@ -835,14 +835,14 @@ DEV void sm_next(SmQuery& q, SmLane& L, const DevScene& S, const DevFrame& F, Wo
     q.stage = QS_NONE;
     return;
   }
-  if (q.stage == QS_STAT && !q.noobj && box_hit(F.olo, F.ohi, q.o, q.d, q.tmax)) {
+  if (q.stage == QS_STAT && !q.noobj && near_object(F, q.o, q.d, q.tmax)) {
     sm_stage(q, QS_OBJ, S.obj, pose_inv_apply(F.pose, q.o), pose_inv_rot(F.pose, q.d));
     return;
   }
   if (q.kind == QK_VIS) {  // visible: the ghost crossings of the same segment
     if (F.ghosts) {
       if (CW) wc.rays[RAY_GHOST]++;
-      if (box_hit(F.glo, F.ghi, q.o, q.d, q.tmax)) {
+      if (near_ghost(F, q.o, q.d, q.tmax)) {
         sm_stage(q, QS_GHOST, S.obj, pose_inv_apply(F.ghost, q.o), pose_inv_rot(F.ghost, q.d));
         return;
       }
@@ -864,7 +864,7 @@ DEV void sm_next(SmQuery& q, SmLane& L, const DevScene& S, const DevFrame& F, Wo
   const End A = light ? end_surf(L.p, L.n) : end_surf(L.E.p, L.E.n);
   const End B = light ? end_surf(L.E.p, L.E.n) : end_surf(L.p, L.n);
   const Seg sg = canon(S, A, B);
-  if (!box_hit(F.glo, F.ghi, sg.o, sg.d, sg.tmax)) return;
+  if (!near_ghost(F, sg.o, sg.d, sg.tmax)) return;
   q.o = sg.o;
   q.d = sg.d;
   q.tmax = sg.tmax;
@@ -1594,7 +1594,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
       if (!rej && moved == 1) {
         if (istar == 1) {
           const vec3 w = unit(v[1].p - C.eye);
-          const Hit h = closest<CW>(S, Fp.pose, Fp.olo, Fp.ohi, C.eye, w, stk, wc, RAY_RETRACE);
+          const Hit h = closest<CW>(S, Fp, C.eye, w, stk, wc, RAY_RETRACE);
           if (!h.ok) {
             rej = 1;
           } else {
@@ -2036,7 +2036,7 @@ __global__ __launch_bounds__(kTraceBlock) void frame_kernel(FrameArgs A) {
     float u[4];
     draw(g, 0, 0, 0, u);
     const vec3 w = camera_dir(C, pixel, u[0], u[1]);
-    const Hit h = closest<false>(S, A.F.pose, A.F.olo, A.F.ohi, C.eye, w, stk, wc);
+    const Hit h = closest<false>(S, A.F, C.eye, w, stk, wc);
     if (!h.ok) {
       if (S.p_env > 0.0f && raster(C, C.eye + w) >= 0) sum = sum + S.env * (Pf * invN);
       continue;
@@ -2083,7 +2083,7 @@ __global__ __launch_bounds__(kTraceBlock) void frame_kernel(FrameArgs A) {
       vec3 wo;
       if (!bsdf_sample(mt, n, unit(prev - p), u[0], u[1], wo)) break;
       const vec3 o = spawn_dir(S, p, n, wo);
-      const Hit h2 = closest<false>(S, A.F.pose, A.F.olo, A.F.ohi, o, wo, stk, wc);
+      const Hit h2 = closest<false>(S, A.F, o, wo, stk, wc);
       if (!h2.ok) break;
       vec3 q, qn;
       uint32_t qmd;
