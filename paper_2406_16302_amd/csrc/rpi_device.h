@@ -203,6 +203,16 @@ DEV bool leaves_convex(const DevScene& S, const Pose& pose, vec3 p, vec3 n, vec3
   return dot(n, p - c) * dot(n, dir) > 0.0f;
 }
 
+// A hit q on a sealed object (closed, convex, camera and emitters outside)
+// whose ray came from the inner side of q's face (from: the ray's start)
+// is inside the object for good: every later vertex of its walk is too, and
+// no path through them can reach the camera or an emitter.  Walks stop there.
+DEV bool interior_hit(const DevScene& S, const DevFrame& F, vec3 q, vec3 qn, uint32_t qmd, vec3 from) {
+  if (!F.sealed || !(qmd & kDynBit)) return false;
+  const vec3 c = pose_apply(F.pose, S.obj_center);
+  return dot(qn, from - q) * dot(qn, c - q) > 0.0f;
+}
+
 // ------------------------------------------------------------------ triangles
 
 // Scene arrays are reached through pointers read from the job table, which

@@ -340,6 +340,11 @@ struct rpi_scene {
   std::vector<void*> allocs;
   float obj_lo[3], obj_hi[3];  // object bounds in object space (= old pose)
   float obj_sc[3], obj_sr;     // bounding sphere in object space: centre, radius
+  // A closed convex object: its outward face planes in object space (n, d:
+  // n.x - d > 0 outside), the emitter triangles (world) and whether it is sealed
+  bool obj_sealed = false;
+  std::vector<std::array<double, 4>> obj_planes;
+  std::vector<std::array<float, 9>> light_host;
   Material obj_mat;
   float diag;
   int W, H;
@@ -371,13 +376,37 @@ static bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinit
 // Rays leaving a convex object through its surface cannot meet it again,
 // which lets the kernels skip its BVH for them.  O(faces x vertices), on
 // host threads.
-static bool object_convex(const std::vector<HostTri>& obj, double tol, vec3& center) {
+static bool object_convex(const std::vector<HostTri>& obj, double tol, vec3& center,
+                          std::vector<std::array<double, 4>>* planes, bool* closed) {
   std::vector<std::array<float, 3>> v;
   v.reserve(3 * obj.size());
   for (const auto& t : obj)
     for (const float* p : {t.v0, t.v1, t.v2}) v.push_back({p[0], p[1], p[2]});
   std::sort(v.begin(), v.end());
   v.erase(std::unique(v.begin(), v.end()), v.end());
+  // closed: with vertices welded by position, every edge borders exactly two triangles
+  {
+    auto id = [&](const float* p) {
+      const std::array<float, 3> k{p[0], p[1], p[2]};
+      return (int64_t)(std::lower_bound(v.begin(), v.end(), k) - v.begin());
+    };
+    std::vector<int64_t> edges;
+    edges.reserve(3 * obj.size());
+    for (const auto& t : obj) {
+      const int64_t a = id(t.v0), b = id(t.v1), c = id(t.v2);
+      for (auto e : {std::make_pair(a, b), std::make_pair(b, c), std::make_pair(c, a)})
+        edges.push_back(std::min(e.first, e.second) * (int64_t)v.size() + std::max(e.first, e.second));
+    }
+    std::sort(edges.begin(), edges.end());
+    bool ok = true;
+    for (size_t i = 0; i < edges.size() && ok;) {
+      size_t j = i;
+      while (j < edges.size() && edges[j] == edges[i]) ++j;
+      ok = j - i == 2;
+      i = j;
+    }
+    *closed = ok;
+  }
   double c[3] = {0, 0, 0};
   for (const auto& p : v)
     for (int a = 0; a < 3; ++a) c[a] += p[a];
@@ -385,6 +414,7 @@ static bool object_convex(const std::vector<HostTri>& obj, double tol, vec3& cen
   center = v3((float)c[0], (float)c[1], (float)c[2]);
   const int nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::atomic<bool> ok{true};
+  planes->assign(obj.size(), {0, 0, 0, 0});
   std::vector<std::thread> th;
   for (int w = 0; w < nt; ++w)
     th.emplace_back([&, w] {
@@ -410,6 +440,8 @@ static bool object_convex(const std::vector<HostTri>& obj, double tol, vec3& cen
           return;
         }
         const double s = sc > 0 ? 1.0 : -1.0;
+        // outward plane: n.x - d > 0 on the side away from the centre
+        (*planes)[f] = {-s * n[0] / len, -s * n[1] / len, -s * n[2] / len, -s * d};
         for (const auto& p : v)
           if (s * ((n[0] * p[0] + n[1] * p[1] + n[2] * p[2]) / len - d) < -tol) {
             ok = false;
@@ -605,7 +637,15 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, rpi_scene** out) 
   C.a_film = (float)(4.0 * (double)C.aspect * (double)C.tan_half * (double)C.tan_half);
   if (!(std::fabs(dot(C.right, C.right) - 1.0f) < 1e-3f)) return fail(RPI_ERR_INVALID_ARG, "camera up parallel to view");
   D.eps = (float)(1e-4 * diag);
-  D.obj_convex = object_convex(obj, 1e-6 * diag, D.obj_center) ? 1 : 0;
+  bool closed = false;
+  D.obj_convex = object_convex(obj, 1e-6 * diag, D.obj_center, &S->obj_planes, &closed) ? 1 : 0;
+  S->obj_sealed = D.obj_convex && closed;
+  if (!S->obj_sealed) S->obj_planes.clear();
+  S->light_host.clear();
+  for (size_t i = 0; i < light_flat.size(); i += 3) {
+    const float4 a = light_flat[i], e1 = light_flat[i + 1], e2 = light_flat[i + 2];
+    S->light_host.push_back({a.x, a.y, a.z, a.x + e1.x, a.y + e1.y, a.z + e1.z, a.x + e2.x, a.y + e2.y, a.z + e2.z});
+  }
   S->W = C.W;
   S->H = C.H;
   *out = S.release();
@@ -699,6 +739,26 @@ static DevFrame make_frame(const rpi_scene* s, const float* pose, const float* g
   F.orad = s->obj_sr + pad;
   F.ghosts = ghosts ? 1 : 0;
   F.same_pose = std::memcmp(pose, ghost, 12 * sizeof(float)) == 0 ? 1 : 0;
+  // Sealed: the object is closed and convex and, at this pose, the camera and
+  // every emitter lie outside it (a face plane separates each of them).  Then
+  // no path that reaches the object's inside can leave it again to connect.
+  if (s->obj_sealed) {
+    const double tol = 1e-5 * s->diag;
+    auto separated = [&](const float* pts, int n) {
+      vec3 q[3];
+      for (int i = 0; i < n; ++i) q[i] = pose_inv_apply(F.pose, v3(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]));
+      for (const auto& pl : s->obj_planes) {
+        bool all = true;
+        for (int i = 0; i < n && all; ++i) all = pl[0] * q[i].x + pl[1] * q[i].y + pl[2] * q[i].z - pl[3] > tol;
+        if (all) return true;
+      }
+      return false;
+    };
+    const float eye[3] = {s->dev.cam.eye.x, s->dev.cam.eye.y, s->dev.cam.eye.z};
+    bool ok = separated(eye, 1);
+    for (size_t i = 0; ok && i < s->light_host.size(); ++i) ok = separated(s->light_host[i].data(), 3);
+    F.sealed = ok ? 1 : 0;
+  }
   return F;
 }
 

@@ -118,6 +118,7 @@ struct DevFrame {
   float orad;      //   centres and radius (the same for both)
   int32_t ghosts;  // 1 for motion edits
   int32_t same_pose;  // the two frames place the object identically
+  int32_t sealed;  // closed convex object with the camera and the emitters outside it
 };
 
 // ------------------------------------------------------------------ workspace

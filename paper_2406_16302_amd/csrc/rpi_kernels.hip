@@ -102,7 +102,7 @@ DEV bool extend(Lane& L, vec3 p, vec3 n, uint32_t md, vec3 wi, const float u[4],
   const Hit h = closest<CW>(L.A.S, L.A.F, o, wo, L.stk, L.wc, RAY_CLOSEST, noobj);
   if (!h.ok) return false;
   hit_vertex(L.A.S, L.A.F.pose, h, o, wo, q, qn, qmd);
-  return !is_emitter(L.A.S, qmd);
+  return !is_emitter(L.A.S, qmd) && !interior_hit(L.A.S, L.A.F, q, qn, qmd, p);
 }
 
 DEV uint32_t light_word(const LightEnd& E) { return E.mat | (E.env ? 0x40000000u : 0u); }
@@ -298,6 +298,7 @@ DEV void tech3(Lane& L) {
   uint32_t l0md;
   hit_vertex(S, A.F.pose, hl, ol, wl, l0, l0n, l0md);
   if (is_emitter(S, l0md)) return;
+  if (interior_hit(S, A.F, l0, l0n, l0md, p)) return;  // the light side starts inside the object
   draw(L.g, 0, 0, 3, u);
   const Material m = vmat(S, A.F, md);
   // the sensor-side BSDF sample sees x_{m+1} as its incoming direction
@@ -311,6 +312,7 @@ DEV void tech3(Lane& L) {
   uint32_t e0md;
   hit_vertex(S, A.F.pose, he, oe, we, e0, e0n, e0md);
   if (is_emitter(S, e0md)) return;
+  if (interior_hit(S, A.F, e0, e0n, e0md, p)) return;  // the sensor side starts inside the object
   const End xd = end_surf(p, n);
   store_mid(L, p, n, md, no_cross(), 1u);
   const Cross ce = edge_cross<CW>(S, A.F, end_surf(e0, e0n), xd, L.stk, L.wc);
@@ -339,6 +341,7 @@ DEV void tech8(Lane& L) {
   uint32_t l0md;
   hit_vertex(S, A.F.pose, hl, ol, wl, l0, l0n, l0md);
   if (is_emitter(S, l0md)) return;
+  if (interior_hit(S, A.F, l0, l0n, l0md, p)) return;  // the light side starts inside the object
   const End xd = end_surf(p, n);
   // the camera sees x_D, on the side of l0
   Cross cam = no_cross();
@@ -368,6 +371,7 @@ DEV void tech8(Lane& L) {
   uint32_t e0md;
   hit_vertex(S, A.F.pose, he, oe, we, e0, e0n, e0md);
   if (is_emitter(S, e0md)) return;
+  if (interior_hit(S, A.F, e0, e0n, e0md, p)) return;  // the sensor side starts inside the object
   const Cross ce = edge_cross<CW>(S, A.F, end_surf(e0, e0n), xd, L.stk, L.wc);
   defer_eye(L, e0, e0n, e0md, ce, xd, A.depth - 4);
 }
@@ -450,12 +454,14 @@ DEV void tech6(Lane& L) {
   uint32_t l0md;
   hit_vertex(S, A.F.pose, hl, xg, w, l0, l0n, l0md);
   if (is_emitter(S, l0md)) return;
+  if (interior_hit(S, A.F, l0, l0n, l0md, xg)) return;  // x_G inside the object: no path leaves it
   const Hit he = closest<CW>(S, A.F, xg, -w, L.stk, L.wc);
   if (!he.ok) return;
   vec3 e0, e0n;
   uint32_t e0md;
   hit_vertex(S, A.F.pose, he, xg, -w, e0, e0n, e0md);
   if (is_emitter(S, e0md)) return;
+  if (interior_hit(S, A.F, e0, e0n, e0md, xg)) return;
   const End ee = end_surf(e0, e0n), el = end_surf(l0, l0n);
   if (!ghost_on_edge(L, ee, el, tri)) return;
   const Cross c = edge_cross<CW>(S, A.F, ee, el, L.stk, L.wc);
@@ -858,6 +864,10 @@ DEV void sm_next(SmQuery& q, SmLane& L, const DevScene& S, const DevFrame& F, Wo
   const Hit h{q.tmax, __float_as_int(q.c.s0), __float_as_int(q.c.sa), __float_as_int(q.c.sb), 1};
   q.c = no_cross();
   hit_vertex(S, F.pose, h, q.o, q.d, L.E.p, L.E.n, L.E.mat);
+  if (interior_hit(S, F, L.E.p, L.E.n, L.E.mat, L.p)) {  // the walk ends inside the object
+    q.hit = 0;
+    return;
+  }
   if (is_emitter(S, L.E.mat) || !F.ghosts) return;
   if (CW) wc.rays[RAY_GHOST]++;
   const bool light = L.ph == PH_LEXT_RES;
