@@ -363,7 +363,7 @@ struct Hit {
 };
 
 template <bool CW>
-DEV void closest_in(const DevBvh& B, vec3 o, vec3 d, Hit& h, int dyn, int* stk, WorkCount& wc) {
+DEV void closest_in(const DevBvh& B, vec3 o, vec3 d, Hit& h, int dyn, int* stk, WorkCount& wc, float tstop) {
   bvh_walk<CW>(B.nodes, o, d, h.t, stk, wc, [&](int code) {
     const int f = leaf_first(code), n = leaf_count(code);
     for (int i = f; i < f + n; ++i) {
@@ -380,7 +380,7 @@ DEV void closest_in(const DevBvh& B, vec3 o, vec3 d, Hit& h, int dyn, int* stk, 
         h.ok = 1;
       }
     }
-    return false;
+    return h.t <= tstop;
   });
 }
 
@@ -395,9 +395,11 @@ DEV bool near_ghost(const DevFrame& F, vec3 o, vec3 d, float tlim) {
 
 // Closest hit in scene_f: static geometry plus the object at F's pose.
 // noobj: the ray leaves the convex object it starts on (leaves_convex).
+// tstop: the caller rejects any hit at t <= tstop, so the search may end
+// as soon as it has one (the hit returned is then not the closest).
 template <bool CW>
 DEV Hit closest(const DevScene& S, const DevFrame& F, vec3 o, vec3 d, int* stk, WorkCount& wc,
-                int ray_type = RAY_CLOSEST, bool noobj = false) {
+                int ray_type = RAY_CLOSEST, bool noobj = false, float tstop = -1.0f) {
   const Pose& pose = F.pose;
   if (CW) wc.rays[ray_type]++;
   Hit h;
@@ -406,9 +408,9 @@ DEV Hit closest(const DevScene& S, const DevFrame& F, vec3 o, vec3 d, int* stk, 
   h.idx = -1;
   h.dyn = 0;
   h.ok = 0;
-  closest_in<CW>(S.stat, o, d, h, 0, stk, wc);
-  if (!noobj && near_object(F, o, d, h.t))
-    closest_in<CW>(S.obj, pose_inv_apply(pose, o), pose_inv_rot(pose, d), h, 1, stk, wc);
+  closest_in<CW>(S.stat, o, d, h, 0, stk, wc, tstop);
+  if (!noobj && h.t > tstop && near_object(F, o, d, h.t))
+    closest_in<CW>(S.obj, pose_inv_apply(pose, o), pose_inv_rot(pose, d), h, 1, stk, wc, tstop);
   return h;
 }
 

@@ -852,6 +852,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   const size_t o_start = take((size_t)kStartFields * Q * sizeof(float4));
   const size_t o_counts = take((size_t)Q * 4);
   const size_t o_pairs = take((size_t)pair_cap * 4);
+  const size_t o_pairs2 = take((size_t)pair_cap * 4);
   const size_t o_np = take(256);
   const size_t o_rec = take((size_t)pair_cap * sizeof(float4));
   const size_t o_keys = keep ? take((size_t)pair_cap * 4) : 0;
@@ -880,6 +881,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   w.W.start = (float4*)(b + o_start);
   w.W.counts = (uint32_t*)(b + o_counts);
   w.W.pairs = (uint32_t*)(b + o_pairs);
+  w.W.pairs2 = (uint32_t*)(b + o_pairs2);
   w.W.npairs = (uint32_t*)(b + o_np);
   w.W.records = (float4*)(b + o_rec);
   w.W.rec_keys = keep ? (uint32_t*)(b + o_keys) : nullptr;
@@ -888,6 +890,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   w.W.task = (float4*)(b + o_task);
   w.W.ntasks = (uint32_t*)(b + o_nt);
   w.W.fetch = w.W.ntasks + 16;
+  w.W.kbins = w.W.ntasks + 32;
   w.W.Q = Q;
   w.W.pair_cap = pair_cap;
   w.W.nslot = nslot;
@@ -1113,7 +1116,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       A.nitems = (int)std::min<int64_t>(R, T - i0);
       launch_zero_u32(w.W.npairs, 1, st);
       launch_zero_u32(w.item_counter, 1, st);
-      launch_zero_u32(w.W.ntasks, 64, st);  // the task count and the fetch counters
+      launch_zero_u32(w.W.ntasks, 64, st);  // the task count, the fetch counters, the length bins
       const int blocks = std::min<int64_t>(wblocks, A.nitems);
       rpi_status r;
       if (t == 8) {
@@ -1126,11 +1129,16 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
         r = timed(kid_walk(t), [&] { launch_walk_tasks(A, blocks, st); });
         if (r) return r;
       }
+      // the path queue sorted by path length, so that a wave's paths loop over
+      // the same number of vertices
+      launch_sort_pairs(A, st);
+      WalkArgs As = A;
+      As.W.pairs = w.W.pairs2;
       if (t8) {
-        r = timed(kKidProposalPdf, [&] { launch_proposal_pdf(A, cblocks, st); });
+        r = timed(kKidProposalPdf, [&] { launch_proposal_pdf(As, cblocks, st); });
         if (r) return r;
       }
-      r = timed(kKidConnect, [&] { launch_connect(A, cblocks, st); });
+      r = timed(kKidConnect, [&] { launch_connect(As, cblocks, st); });
       if (r) return r;
       r = timed(kKidSplat, [&] { launch_splat(sa, st); });
       if (r) return r;

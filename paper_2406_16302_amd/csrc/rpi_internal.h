@@ -143,6 +143,8 @@ struct Workspace {
   float4* task;        // walk tasks (start phase -> walk phase), SoA: task[field * Q + t]
   uint32_t* ntasks;    // [1] task queue length
   uint32_t* fetch;     // [2] work counters of the walk phase (tasks) and the connect kernel (paths)
+  uint32_t* kbins;     // [32] paths per length k, then the sort's cursors per k
+  uint32_t* pairs2;    // [pair_cap] the path queue sorted by path length
   float4* t8q;         // technique (8) on: per queued path (2 float4), the proposal's
                        // solid-angle density at vertices x_1 .. x_5 (0 where not used)
   int32_t Q;           // samples per chunk
@@ -264,6 +266,7 @@ struct FrameArgs {
 void launch_walk(const WalkArgs& A, int blocks, hipStream_t st);        // start phase (persistent over items)
 void launch_walk_tasks(const WalkArgs& A, int blocks, hipStream_t st);  // walk phase (over the task queue)
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st);
+void launch_sort_pairs(const WalkArgs& A, hipStream_t st);
 void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st);
 void launch_splat(const SplatArgs& a, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);

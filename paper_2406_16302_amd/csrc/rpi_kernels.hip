@@ -394,7 +394,7 @@ DEV void tech4(Lane& L) {
   const vec3 o = spawn(S, E.p, E.n, xg);
   const vec3 w = unit(xg - o);
   const float tg = sqrtf(len2(xg - o));
-  const Hit h = closest<CW>(S, A.F, o, w, L.stk, L.wc);
+  const Hit h = closest<CW>(S, A.F, o, w, L.stk, L.wc, RAY_CLOSEST, false, tg);
   if (!h.ok || !(h.t > tg)) return;
   vec3 q, qn;
   uint32_t qmd;
@@ -421,7 +421,7 @@ DEV void tech5(Lane& L) {
   object_point(S, A.F.ghost, u, xg, ng, gmd, tri);
   const vec3 w = unit(xg - S.cam.eye);
   const float tg = sqrtf(len2(xg - S.cam.eye));
-  const Hit h = closest<CW>(S, A.F, S.cam.eye, w, L.stk, L.wc);
+  const Hit h = closest<CW>(S, A.F, S.cam.eye, w, L.stk, L.wc, RAY_CLOSEST, false, tg);
   if (!h.ok || !(h.t > tg)) return;
   vec3 q, qn;
   uint32_t qmd;
@@ -2179,6 +2179,50 @@ void launch_t8_start(const WalkArgs& A, int blocks, hipStream_t st) {
 }
 void launch_proposal_pdf(const WalkArgs& A, int blocks, hipStream_t st) {
   hipLaunchKernelGGL(proposal_pdf_kernel, dim3(blocks), dim3(kTraceBlock), 0, st, A);
+}
+
+// Counting sort of the path queue by path length k (vertices), in two
+// passes: histogram, then each block reserves its slice's places per k and
+// scatters.  The order within one k is not kept.
+DEV int path_len(uint32_t code, int tech) {
+  const int i = (int)((code >> 4) & 15u) - 1, j = (int)(code & 15u) - 1;
+  return min((i + 1) + (has_mid(tech) ? 1 : 0) + (j + 1) + 2, 15);
+}
+__global__ __launch_bounds__(256) void pair_hist_kernel(WalkArgs A) {
+  __shared__ uint32_t h[16];
+  if (threadIdx.x < 16) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t n = min((uint32_t)A.W.pair_cap, *A.W.npairs);
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    atomicAdd(&h[path_len(A.W.pairs[i], A.tech)], 1u);
+  __syncthreads();
+  if (threadIdx.x < 16 && h[threadIdx.x]) atomicAdd(&A.W.kbins[threadIdx.x], h[threadIdx.x]);
+}
+__global__ __launch_bounds__(256) void pair_sort_kernel(WalkArgs A) {
+  __shared__ uint32_t h[16], base[16];
+  if (threadIdx.x < 16) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint32_t n = min((uint32_t)A.W.pair_cap, *A.W.npairs);
+  const uint32_t len = (n + gridDim.x - 1) / gridDim.x;
+  const uint32_t b0 = min(n, blockIdx.x * len), b1 = min(n, b0 + len);
+  for (uint32_t i = b0 + threadIdx.x; i < b1; i += 256) atomicAdd(&h[path_len(A.W.pairs[i], A.tech)], 1u);
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    uint32_t pre = 0;
+    for (int k = 0; k < (int)threadIdx.x; ++k) pre += A.W.kbins[k];
+    base[threadIdx.x] = pre + (h[threadIdx.x] ? atomicAdd(&A.W.kbins[16 + threadIdx.x], h[threadIdx.x]) : 0u);
+    h[threadIdx.x] = 0u;
+  }
+  __syncthreads();
+  for (uint32_t i = b0 + threadIdx.x; i < b1; i += 256) {
+    const uint32_t code = A.W.pairs[i];
+    const int k = path_len(code, A.tech);
+    A.W.pairs2[base[k] + atomicAdd(&h[k], 1u)] = code;
+  }
+}
+void launch_sort_pairs(const WalkArgs& A, hipStream_t st) {
+  hipLaunchKernelGGL(pair_hist_kernel, dim3(1024), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(pair_sort_kernel, dim3(1024), dim3(256), 0, st, A);
 }
 
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st) {
