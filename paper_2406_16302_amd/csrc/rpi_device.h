@@ -213,6 +213,15 @@ DEV bool interior_hit(const DevScene& S, const DevFrame& F, vec3 q, vec3 qn, uin
   return dot(qn, from - q) * dot(qn, c - q) > 0.0f;
 }
 
+// x lies inside a sealed object (in the ball about its centre that the
+// object contains): a ray from outside must cross the object before x, and
+// rays from x cannot leave it.
+DEV bool deep_inside(const DevScene& S, const DevFrame& F, vec3 x) {
+  if (!F.sealed) return false;
+  const vec3 d = x - pose_apply(F.pose, S.obj_center);
+  return dot(d, d) < S.obj_rin * S.obj_rin;
+}
+
 // ------------------------------------------------------------------ triangles
 
 // Scene arrays are reached through pointers read from the job table, which

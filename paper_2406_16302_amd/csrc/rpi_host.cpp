@@ -641,6 +641,13 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, rpi_scene** out) 
   D.obj_convex = object_convex(obj, 1e-6 * diag, D.obj_center, &S->obj_planes, &closed) ? 1 : 0;
   S->obj_sealed = D.obj_convex && closed;
   if (!S->obj_sealed) S->obj_planes.clear();
+  D.obj_rin = 0.0f;
+  if (S->obj_sealed) {  // the nearest face plane bounds a ball about the centre inside the object
+    double rin = INFINITY;
+    for (const auto& pl : S->obj_planes)
+      rin = std::min(rin, pl[3] - (pl[0] * D.obj_center.x + pl[1] * D.obj_center.y + pl[2] * D.obj_center.z));
+    D.obj_rin = rin > 0 ? (float)(0.999 * rin) : 0.0f;
+  }
   S->light_host.clear();
   for (size_t i = 0; i < light_flat.size(); i += 3) {
     const float4 a = light_flat[i], e1 = light_flat[i + 1], e2 = light_flat[i + 2];

@@ -99,6 +99,7 @@ struct DevScene {
   float eps;            // ray offset: 1e-4 of the scene diagonal
   int32_t obj_convex;   // the object bounds a convex solid (every vertex on the inner side of every face)
   vec3 obj_center;      // a point inside it (object space): the mean of its vertices
+  float obj_rin;        // closed convex object: radius of a ball about obj_center inside it (else 0)
 };
 
 struct Material {

@@ -387,6 +387,7 @@ DEV void tech4(Lane& L) {
   uint32_t gmd;
   int tri;
   object_point(S, A.F.ghost, u, xg, ng, gmd, tri);
+  if (deep_inside(S, A.F, xg)) return;  // x_G inside the object: no path of this start
   draw(L.g, 0, 0, 1, u);
   LightEnd E;
   if (!sample_light(S, u, E) || E.env) return;
@@ -419,6 +420,7 @@ DEV void tech5(Lane& L) {
   uint32_t gmd;
   int tri;
   object_point(S, A.F.ghost, u, xg, ng, gmd, tri);
+  if (deep_inside(S, A.F, xg)) return;  // x_G inside the object: no path of this start
   const vec3 w = unit(xg - S.cam.eye);
   const float tg = sqrtf(len2(xg - S.cam.eye));
   const Hit h = closest<CW>(S, A.F, S.cam.eye, w, L.stk, L.wc, RAY_CLOSEST, false, tg);
@@ -446,6 +448,7 @@ DEV void tech6(Lane& L) {
   uint32_t gmd;
   int tri;
   object_point(S, A.F.ghost, u, xg, ng, gmd, tri);
+  if (deep_inside(S, A.F, xg)) return;  // x_G inside the object: no path of this start
   draw(L.g, 0, 0, 2, u);
   const vec3 w = sphere_dir(u[0], u[1]);
   const Hit hl = closest<CW>(S, A.F, xg, w, L.stk, L.wc);
