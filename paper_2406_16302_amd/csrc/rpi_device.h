@@ -203,6 +203,14 @@ DEV bool leaves_convex(const DevScene& S, const Pose& pose, vec3 p, vec3 n, vec3
   return dot(n, p - c) * dot(n, dir) > 0.0f;
 }
 
+// A ray or segment from point p on a sealed object (below) into the object's
+// inner side: blocked by the object, or into its inside for good.
+DEV bool into_sealed(const DevScene& S, const DevFrame& F, vec3 p, vec3 n, vec3 dir) {
+  if (!F.sealed) return false;
+  const vec3 c = pose_apply(F.pose, S.obj_center);
+  return dot(n, p - c) * dot(n, dir) < 0.0f;
+}
+
 // A hit q on a sealed object (closed, convex, camera and emitters outside)
 // whose ray came from the inner side of q's face (from: the ray's start)
 // is inside the object for good: every later vertex of its walk is too, and

@@ -240,6 +240,7 @@ DEV void tech1(Lane& L) {
   if (!sample_light(S, u, E)) return;
   const End eL = end_light(E);
   if (!E.env && !(dot(E.n, p - E.p) > 0.0f)) return;
+  if (into_sealed(S, A.F, p, n, E.env ? E.n : E.p - p)) return;  // the object itself blocks the light
   if (!edge_visible<CW>(S, A.F, end_surf(p, n), eL, L.stk, L.wc, RAY_SHADOW,
                         leaves_convex(S, A.F.pose, p, n, E.env ? E.n : E.p - p)))
     return;
@@ -262,6 +263,7 @@ DEV void tech2(Lane& L) {
   object_point(S, A.F.pose, u, p, n, md, tri);
   if (raster(S.cam, p) < 0) return;
   const End e0 = end_eye(S), xd = end_surf(p, n);
+  if (into_sealed(S, A.F, p, n, S.cam.eye - p)) return;  // x_D faces away from the camera
   if (!edge_visible<CW>(S, A.F, e0, xd, L.stk, L.wc, RAY_CAMERA, leaves_convex(S, A.F.pose, p, n, S.cam.eye - p)))
     return;
   const Cross cam = edge_cross<CW>(S, A.F, e0, xd, L.stk, L.wc);
@@ -290,6 +292,7 @@ DEV void tech3(Lane& L) {
   draw(L.g, 0, 0, 2, u);
   const vec3 wl = cosine_dir(n, u[0], u[1]);
   if (!(dot(wl, n) > 0.0f)) return;
+  if (into_sealed(S, A.F, p, n, wl)) return;  // into the object: the light side would start inside
   const vec3 ol = spawn_dir(S, p, n, wl);
   const Hit hl = closest<CW>(S, A.F, ol, wl, L.stk, L.wc, RAY_CLOSEST,
                              leaves_convex(S, A.F.pose, p, n, wl));
@@ -304,6 +307,7 @@ DEV void tech3(Lane& L) {
   // the sensor-side BSDF sample sees x_{m+1} as its incoming direction
   vec3 we;
   if (!bsdf_sample(m, n, unit(l0 - p), u[0], u[1], we)) return;
+  if (into_sealed(S, A.F, p, n, we)) return;
   const vec3 oe = spawn_dir(S, p, n, we);
   const Hit he = closest<CW>(S, A.F, oe, we, L.stk, L.wc, RAY_CLOSEST,
                              leaves_convex(S, A.F.pose, p, n, we));
@@ -333,6 +337,7 @@ DEV void tech8(Lane& L) {
   const float4 a = STA(A.W, 0, L.s), b = STA(A.W, 1, L.s), c = STA(A.W, 3, L.s);
   const vec3 p = xyz(a), n = xyz(b), wl = xyz(c);
   const uint32_t md = __float_as_uint(a.w);
+  if (into_sealed(S, A.F, p, n, wl)) return;  // into the object: the light side would start inside
   const vec3 ol = spawn_dir(S, p, n, wl);
   const Hit hl = closest<CW>(S, A.F, ol, wl, L.stk, L.wc, RAY_CLOSEST,
                              leaves_convex(S, A.F.pose, p, n, wl));
@@ -345,7 +350,7 @@ DEV void tech8(Lane& L) {
   const End xd = end_surf(p, n);
   // the camera sees x_D, on the side of l0
   Cross cam = no_cross();
-  if (raster(S.cam, p) >= 0 && same_side(n, p, S.cam.eye, l0)) {
+  if (raster(S.cam, p) >= 0 && same_side(n, p, S.cam.eye, l0) && !into_sealed(S, A.F, p, n, S.cam.eye - p)) {
     const End e0 = end_eye(S);
     if (edge_visible<CW>(S, A.F, e0, xd, L.stk, L.wc, RAY_CAMERA, leaves_convex(S, A.F.pose, p, n, S.cam.eye - p))) {
       cam = edge_cross<CW>(S, A.F, e0, xd, L.stk, L.wc);
@@ -363,6 +368,7 @@ DEV void tech8(Lane& L) {
   const Material m = vmat(S, A.F, md);
   vec3 we;
   if (!bsdf_sample(m, n, unit(l0 - p), u[0], u[1], we)) return;
+  if (into_sealed(S, A.F, p, n, we)) return;
   const vec3 oe = spawn_dir(S, p, n, we);
   const Hit he = closest<CW>(S, A.F, oe, we, L.stk, L.wc, RAY_CLOSEST,
                              leaves_convex(S, A.F.pose, p, n, we));
@@ -652,6 +658,10 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 #define RPI_WALK_WAVES_PER_EU RPI_TRACE_WAVES_PER_EU
 #endif
 #define RPI_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_WALK_WAVES_PER_EU)))
+#ifndef RPI_CONNECT_WAVES_PER_EU
+#define RPI_CONNECT_WAVES_PER_EU RPI_TRACE_WAVES_PER_EU
+#endif
+#define RPI_CONNECT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_CONNECT_WAVES_PER_EU)))
 #if RPI_START_WAVES_PER_EU > 0
 #define RPI_START_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_START_WAVES_PER_EU)))
 #else
@@ -1728,7 +1738,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
 }
 
 template <bool CW>
-__global__ __launch_bounds__(kTraceBlock) RPI_TRACE_OCCUPANCY void connect_kernel(WalkArgs A) {
+__global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   __shared__ unsigned long long cnt[16];
   if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
