@@ -111,7 +111,11 @@ DEV uint32_t light_word(const LightEnd& E) { return E.mat | (E.env ? 0x40000000u
 // crossing pred0; prev0 = the neighbour towards the camera.  Next-event
 // estimation at each vertex.  dyn0: path-tracing dynamic state before slot 0.
 template <bool CW>
-DEV void light_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End prev0, int jmax, bool dyn0) {
+// dyn_only: only paths with a dynamic vertex or ghost crossing count (path
+// tracing with static paths rejected), so a light connection from a static
+// prefix is traced only if it may cross the ghost.
+DEV void light_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End prev0, int jmax, bool dyn0,
+                    bool dyn_only) {
   const Ctx& A = L.A;
   const DevScene& S = A.S;
   vec3 p = p0, n = n0;
@@ -131,6 +135,10 @@ DEV void light_walk(Lane& L, vec3 p0, vec3 n0, uint32_t md0, Cross pred0, End pr
       const End eL = end_light(E);
       ok = E.env ? same_side_dir(n, p, prev.p, E.n)
                  : (dot(E.n, p - E.p) > 0.0f && same_side(n, p, prev.p, E.p));
+      if (ok && dyn_only && !dyn) {
+        const Seg sg = canon(S, end_surf(p, n), eL);
+        ok = A.F.ghosts && near_ghost(A.F, sg.o, sg.d, sg.tmax);
+      }
       if (ok) {
         const End cur = end_surf(p, n);
         const bool noobj = (md & kDynBit) && leaves_convex(S, A.F.pose, p, n, E.env ? E.n : E.p - p);
@@ -723,7 +731,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_START_OCCUPANCY void walk_kernel(W
     // samples with walks left go to the task queue (techniques whose starts
     // fail often), or walk here (those whose walks follow most starts)
     if (!split_walks(TECH) && active) {
-      if (L.defer & 1u) light_walk<CW>(L, L.lw.p, L.lw.n, L.lw.md, L.lw.pred, L.lw.end, L.lw.lim, false);
+      if (L.defer & 1u) light_walk<CW>(L, L.lw.p, L.lw.n, L.lw.md, L.lw.pred, L.lw.end, L.lw.lim, false, TECH == 7);
       if (L.defer & 2u) eye_walk<CW>(L, L.ew.p, L.ew.n, L.ew.md, L.ew.pred, L.ew.end, L.ew.lim);
       L.defer = 0u;
       A.W.counts[s] = (uint32_t)L.nE | ((uint32_t)L.nL << 8);
