@@ -776,8 +776,8 @@ __global__ __launch_bounds__(kTraceBlock) RPI_START_OCCUPANCY void walk_kernel(W
 enum : int { QS_NONE = 0, QS_STAT = 1, QS_OBJ = 2, QS_GHOST = 3 };
 enum : int { QK_VIS = 0, QK_EXT = 1 };
 enum : int {
-  PH_IDLE = 0, PH_LNEE, PH_LNEE_RES, PH_LREC, PH_LEXT_RES,
-  PH_ESTART, PH_ECAM, PH_ECAM_RES, PH_EREC, PH_EEXT_RES, PH_FIN
+  PH_IDLE = 0, PH_LNEE, PH_LNEE_RES, PH_LREC, PH_LEXTEND, PH_LEXT_RES,
+  PH_ESTART, PH_ECAM, PH_ECAM_RES, PH_EREC, PH_EEXTEND, PH_EEXT_RES, PH_FIN
 };
 
 struct SmQuery {
@@ -807,7 +807,31 @@ struct SmLane {
                      // (p, n and material word in p, n, mat)
   int nE, nL, k2;
   uint32_t camok, neeok, dynpre;
+  // Two-sided tasks (techniques 3 and 6): 1 = the eye vertex 0 goes first,
+  // 2 = then the light walk, 3 = then the rest of the eye walk; elim: the eye
+  // walk's last slot.  A vertex is added only if some connected path could
+  // still use it (the pairs need i + j + extra <= depth).
+  int order, elim;
 };
+
+template <int TECH>
+DEV constexpr bool sm_two_sided() {
+  return TECH == 3 || TECH == 6;
+}
+DEV constexpr int pair_extra(int tech) { return (tech == 3 || tech == 8) ? 4 : 3; }
+// light vertex j1: an eye vertex i <= depth - extra - j1 that connects (e_0
+// is known; later ones might)
+DEV bool light_useful(const SmLane& L, int j1, int depth, int extra) {
+  const int imax = depth - extra - j1;
+  if (imax < 0) return false;
+  return (L.camok & 1u) || (imax >= 1 && L.elim >= 1);
+}
+// eye vertex i1: a light vertex j with a successful connection and i1 + j + extra <= depth
+DEV bool eye_useful(const SmLane& L, int i1, int depth, int extra) {
+  for (int j = 0; j < L.nL; ++j)
+    if ((L.neeok >> j & 1u) && i1 + j + extra <= depth) return true;
+  return false;
+}
 
 DEV void sm_stage(SmQuery& q, int stage, const DevBvh& B, vec3 ro, vec3 rd) {
   q.stage = stage;
@@ -974,6 +998,7 @@ DEV Rng sm_rng(const WalkArgs& A, const SmLane& L, int tech) {
              A.job_base + (uint32_t)(L.jd >> 1)};
 }
 
+template <int TECH>
 DEV void sm_begin(const WalkArgs& A, SmLane& L, uint32_t t) {
   const float4 h = TSK(A.W, 0, t);
   L.s = __float_as_uint(h.x);
@@ -985,6 +1010,12 @@ DEV void sm_begin(const WalkArgs& A, SmLane& L, uint32_t t) {
   L.nE = L.nL = 0;
   L.camok = L.neeok = L.dynpre = 0u;
   L.ph = PH_ESTART;
+  L.order = 0;
+  L.elim = 0;
+  if (sm_two_sided<TECH>() && (L.defer & 3u) == 3u) {
+    L.order = 1;  // the eye vertex 0 first
+    return;
+  }
   if (L.defer & 1u) {
     const WalkStart w = load_walk(A.W, 1, t);
     L.p = w.p;
@@ -1020,6 +1051,7 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
     const bool light = L.ph == PH_LEXT_RES;
     if (!q.hit || is_emitter(S, L.E.mat)) {
       L.ph = light ? PH_ESTART : PH_FIN;
+      if (light && L.order == 2) L.order = 3;
     } else {
       L.pred = q.c;
       // component copies: a struct copy inside the lane state keeps the
@@ -1050,8 +1082,10 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
       // environment direction
       L.other = w.end.kind == END_ENV ? L.p + w.end.n : w.end.p;
       L.lim = w.lim;
+      L.elim = w.lim;
       L.j = 0;
-      L.ph = PH_ECAM;
+      // resumed after the light walk: its vertex 0 is connected and recorded
+      L.ph = L.order == 3 ? PH_EEXTEND : PH_ECAM;
     }
   }
   // connections: next-event estimation (light walk), camera (eye walk)
@@ -1116,9 +1150,33 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
     L.nE = light ? L.nE : j + 1;
     L.neeok |= light ? bit : 0u;
     L.camok |= light ? 0u : bit;
-    const int end = light ? PH_ESTART : PH_FIN;
-    L.ph = end;
-    if (j < L.lim) {
+    L.ph = light ? PH_LEXTEND : PH_EEXTEND;
+  }
+  // the extension, if a connected path could use the next vertex
+  if (L.ph == PH_LEXTEND || L.ph == PH_EEXTEND) {
+    const bool light = L.ph == PH_LEXTEND;
+    const int j = L.j;
+    if (!light && L.order == 1) {  // eye vertex 0 done: now the light walk
+      const WalkStart w = load_walk(W, 1, t);
+      L.p = w.p;
+      L.n = w.n;
+      L.md = w.md;
+      L.pred = w.pred;
+      L.other = w.end.p;
+      L.lim = w.lim;
+      L.j = 0;
+      L.dyn = 0;
+      L.order = 2;
+      L.ph = PH_LNEE;
+      return;
+    }
+    bool ext = j < L.lim;
+    if (sm_two_sided<TECH>() && ext) {
+      if (light && L.order == 2) ext = light_useful(L, j + 1, A.depth, pair_extra(TECH));
+      if (!light && L.order == 3) ext = eye_useful(L, j + 1, A.depth, pair_extra(TECH));
+    }
+    L.ph = light ? PH_ESTART : PH_FIN;
+    if (ext) {
       float u[4];
       draw(sm_rng(A, L, TECH), light ? 0u : 1u, j + 1, 0, u);
       vec3 wo;
@@ -1128,6 +1186,7 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
         L.ph = light ? PH_LEXT_RES : PH_EEXT_RES;
       }
     }
+    if (L.ph == PH_ESTART && L.order == 2) L.order = 3;  // the light walk ends here
   }
 }
 
@@ -1179,7 +1238,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_WALK_OCCUPANCY void walk_task_kern
         if (base + k >= n) drained = true;
         if (L.ph == PH_IDLE) {
           t = base + (uint32_t)__popcll(idle & ((1ull << lane) - 1ull));
-          if (t < n) sm_begin(A, L, t);
+          if (t < n) sm_begin<TECH>(A, L, t);
         }
       }
     }
