@@ -196,9 +196,10 @@ typedef struct {
   double ms_per_msample;          /* measured device time per million technique samples */
 } rpi_tuning;
 
-/* Time a small grid of launch configurations (round size, persistent grid,
- * connect grid) on the first 2^22 samples of every stream of this edit and
- * keep the fastest for later calls on this scene whose queue_cap is 0.
+/* Time a small grid of launch configurations (round size 2^22..2^24,
+ * persistent walk grid 16 or 32 blocks per CU) on the first 2^24 samples of
+ * every stream of this edit and keep the fastest for later calls on this
+ * scene whose queue_cap is 0.
  * Synchronises hip_stream.  out may be NULL. */
 rpi_status rpi_autotune(rpi_scene* scene, const rpi_edit* edit, const rpi_render_params* params, rpi_tuning* out,
                         void* hip_stream);

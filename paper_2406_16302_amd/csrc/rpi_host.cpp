@@ -1370,14 +1370,16 @@ static rpi_status autotune_job(rpi_scene* s, const JobSpec& j, bool material_mod
   q.flags |= RPI_FLAG_ACCUMULATE;
   const int64_t N = (int64_t)p->spp * j.W * j.H;
   q.sample_begin = 0;
-  q.sample_end = std::min<int64_t>(N, 1 << 22);  // enough samples per stream to need several rounds at the smaller sizes
+  // up to 2^24 samples per stream: the largest round holds that many samples
+  // of one direction, so the window shows what rounds of each size cost
+  q.sample_end = std::min<int64_t>(N, 1 << 24);
   if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);
-  const int Qs[3] = {1 << 20, 1 << 21, 1 << 22};
-  const int walks[3] = {8, 16, 32};
+  const int Qs[3] = {1 << 22, 1 << 23, 1 << 24};
+  const int walks[2] = {16, 32};
   double best = 1e300;
   Tuning bt;
   for (int qi = 0; qi < 3; ++qi)
-    for (int wi = 0; wi < 3; ++wi) {
+    for (int wi = 0; wi < 2; ++wi) {
       Tuning t;
       t.Q = Qs[qi];
       t.walk_bpc = walks[wi];
