@@ -1022,7 +1022,7 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
   for (int j = 0; j < nj; ++j) total = std::max(total, pl.jobs[j].s1 - pl.jobs[j].s0);
   int64_t Q = std::min<int64_t>(tu.Q, std::max<int64_t>(total * nj * 2, kItem));
   Q = (Q + kItem - 1) / kItem * kItem;
-  Q = std::min<int64_t>(Q, 1 << 24);
+  Q = std::min<int64_t>(Q, kMaxRound);
   pl.Q = (int)Q;
   pl.pair_cap = Q * maxp;
   return RPI_OK;
@@ -1371,10 +1371,10 @@ static rpi_status autotune_job(rpi_scene* s, const JobSpec& j, bool material_mod
   const int64_t N = (int64_t)p->spp * j.W * j.H;
   q.sample_begin = 0;
   // up to 2^24 samples per stream: the largest round holds that many samples
-  // of one direction, so the window shows what rounds of each size cost
+  // of both directions, so the window shows what rounds of each size cost
   q.sample_end = std::min<int64_t>(N, 1 << 24);
   if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);
-  const int Qs[3] = {1 << 22, 1 << 23, 1 << 24};
+  const int Qs[3] = {1 << 23, 1 << 24, kMaxRound};
   const int walks[2] = {16, 32};
   double best = 1e300;
   Tuning bt;
@@ -1426,7 +1426,7 @@ extern "C" rpi_status rpi_autotune(rpi_scene* s, const rpi_edit* e, const rpi_re
 
 extern "C" rpi_status rpi_set_tuning(rpi_scene* s, const rpi_tuning* t) {
   if (!s || !t) return fail(RPI_ERR_INVALID_ARG, "null argument");
-  if (t->queue_cap <= 0 || t->queue_cap % kItem || t->queue_cap > (1 << 24) || t->walk_blocks_per_cu < 1 ||
+  if (t->queue_cap <= 0 || t->queue_cap % kItem || t->queue_cap > kMaxRound || t->walk_blocks_per_cu < 1 ||
       t->walk_blocks_per_cu > 64 || t->connect_blocks_per_cu < 1 || t->connect_blocks_per_cu > 64)
     return fail(RPI_ERR_INVALID_ARG, "bad tuning");
   s->tuned_Q = t->queue_cap;

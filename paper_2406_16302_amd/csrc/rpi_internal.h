@@ -136,7 +136,7 @@ struct Workspace {
   float4* light;
   float4* start;
   uint32_t* counts;    // per sample: nE | nL << 8
-  uint32_t* pairs;     // queue of connected paths: sample << 8 | (i+1) << 4 | (j+1)
+  uint32_t* pairs;     // queue of connected paths: slot << 6 | (i+1) << 3 | (j+1)
   uint32_t* npairs;    // [1] queue length
   float4* records;     // per queued path: pixel (int bits), rgb
   uint32_t* rec_keys;  // optional: dir | tech << 1 | pair << 8  (debug records)
@@ -169,6 +169,7 @@ struct DevJob {
 };
 
 constexpr int kItem = 64;  // samples per work item (one wave)
+constexpr int kMaxRound = 1 << 25;  // samples per round: the path code holds slots below 2^26
 
 // Kernel slots of the per-kernel statistics: 1..8 start phase of technique
 // t, 17..24 its walk phase, then connect, splat, frame, the proposal's

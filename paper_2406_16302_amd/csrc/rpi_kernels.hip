@@ -554,7 +554,12 @@ DEV int pair_count(const LaneT& L, int depth) {
   }
   return c;
 }
-DEV uint32_t pair_code(int s, int i, int j) { return ((uint32_t)s << 8) | ((uint32_t)(i + 1) << 4) | (uint32_t)(j + 1); }
+// Connected path code: sample slot << 6 | (i + 1) << 3 | (j + 1) (slots below
+// 2^26; i + 1 and j + 1 below 8 since paths have at most 8 vertices).
+DEV uint32_t pair_code(int s, int i, int j) { return ((uint32_t)s << 6) | ((uint32_t)(i + 1) << 3) | (uint32_t)(j + 1); }
+DEV int code_slot(uint32_t code) { return (int)(code >> 6); }
+DEV int code_i(uint32_t code) { return (int)((code >> 3) & 7u) - 1; }
+DEV int code_j(uint32_t code) { return (int)(code & 7u) - 1; }
 
 template <int TECH, class LaneT>
 DEV void write_pairs(const LaneT& L, uint32_t* out, int depth) {
@@ -1403,9 +1408,9 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
                      int& reason, TrainRec& tr) {
   const DevScene& S = A.S;
   const Workspace& W = A.W;
-  const int s = (int)(code >> 8);
-  const int i = (int)((code >> 4) & 15u) - 1;
-  const int j = (int)(code & 15u) - 1;
+  const int s = code_slot(code);
+  const int i = code_i(code);
+  const int j = code_j(code);
   const int T = A.tech;
   const bool mid = has_mid(T);
   const int nsc = (i + 1) + (mid ? 1 : 0) + (j + 1);  // scattering vertices
@@ -1823,7 +1828,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_ker
     tr.weight = 0.0f;
     if (act) {
       const uint32_t code = A.W.pairs[idx];
-      const int s = (int)(code >> 8);
+      const int s = code_slot(code);
       const int64_t g = A.item0 + s / kItem;
       const int jd = find_jd(A.item_prefix, 2 * A.njobs, g);
       const DevJob& J = A.jobs[jd >> 1];
@@ -1839,7 +1844,9 @@ __global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_ker
       A.W.records[idx] = rec;
       if (CW) wc.bytes += 16u;
       if (A.keep_records) {
-        A.W.rec_keys[idx] = (uint32_t)dir | ((uint32_t)A.tech << 1) | ((code & 0xffu) << 8);
+        // debug key: the pair as (i + 1) << 4 | (j + 1)
+        const uint32_t pr = ((uint32_t)(code_i(code) + 1) << 4) | (uint32_t)(code_j(code) + 1);
+        A.W.rec_keys[idx] = (uint32_t)dir | ((uint32_t)A.tech << 1) | (pr << 8);
         A.W.rec_sample[idx] = (uint32_t)(J.s0 + (g - A.item_prefix[jd]) * kItem + s % kItem);
       }
       if (A.stats && reason <= 6) atomicAdd(&cnt[reason], 1ull);
@@ -1888,9 +1895,9 @@ __global__ __launch_bounds__(kTraceBlock) void proposal_pdf_kernel(WalkArgs A) {
     const DevJob* J = A.jobs;
     if (act) {
       const uint32_t code = A.W.pairs[idx];
-      s = (int)(code >> 8);
-      i = (int)((code >> 4) & 15u) - 1;
-      const int j = (int)(code & 15u) - 1;
+      s = code_slot(code);
+      i = code_i(code);
+      const int j = code_j(code);
       k = (i + 1) + (has_mid(A.tech) ? 1 : 0) + (j + 1) + 2;
       const int jd = find_jd(A.item_prefix, 2 * A.njobs, A.item0 + s / kItem);
       J = A.jobs + (jd >> 1);
@@ -2265,7 +2272,7 @@ void launch_proposal_pdf(const WalkArgs& A, int blocks, hipStream_t st) {
 // passes: histogram, then each block reserves its slice's places per k and
 // scatters.  The order within one k is not kept.
 DEV int path_len(uint32_t code, int tech) {
-  const int i = (int)((code >> 4) & 15u) - 1, j = (int)(code & 15u) - 1;
+  const int i = code_i(code), j = code_j(code);
   return min((i + 1) + (has_mid(tech) ? 1 : 0) + (j + 1) + 2, 15);
 }
 __global__ __launch_bounds__(256) void pair_hist_kernel(WalkArgs A) {

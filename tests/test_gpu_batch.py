@@ -91,5 +91,5 @@ def test_autotune_returns_a_configuration():
     sc = native.Scene(ws.scene)
     ed = native.Edit(sc, ws.edit)
     t = native.autotune(sc, ed, native.Params.make(16, 3, 1))
-    assert t["queue_cap"] in (1 << 22, 1 << 23, 1 << 24) and t["walk_blocks_per_cu"] in (16, 32)
+    assert t["queue_cap"] in (1 << 23, 1 << 24, 1 << 25) and t["walk_blocks_per_cu"] in (16, 32)
     assert t["ms_per_msample"] > 0
