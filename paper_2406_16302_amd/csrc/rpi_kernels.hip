@@ -667,12 +667,16 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 #else
 #define RPI_START_OCCUPANCY
 #endif
+// the walk-phase state machine keeps a query and a walk per lane: at 3 waves
+// per SIMD (168 VGPRs) it spills less, which pays for the lower occupancy
 #ifndef RPI_WALK_WAVES_PER_EU
-#define RPI_WALK_WAVES_PER_EU RPI_TRACE_WAVES_PER_EU
+#define RPI_WALK_WAVES_PER_EU 3
 #endif
 #define RPI_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_WALK_WAVES_PER_EU)))
+// connect holds a whole path (vertices, crossing sums, pdf tables) in
+// registers: 3 waves per SIMD gives it 168 VGPRs and no spills
 #ifndef RPI_CONNECT_WAVES_PER_EU
-#define RPI_CONNECT_WAVES_PER_EU RPI_TRACE_WAVES_PER_EU
+#define RPI_CONNECT_WAVES_PER_EU 3
 #endif
 #define RPI_CONNECT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_CONNECT_WAVES_PER_EU)))
 #if RPI_START_WAVES_PER_EU > 0
@@ -1361,6 +1365,11 @@ struct PV {
 
 DEV vec3 lpos(const LightEnd& E, vec3 from) { return E.env ? from + E.n : E.p; }
 
+// Component selects.  A conditional over two lvalues selects an address; over
+// the vertex array that keeps the array in scratch memory.
+DEV vec3 pick(bool c, const vec3& a, const vec3& b) { return v3(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z); }
+DEV PV pick(bool c, const PV& a, const PV& b) { return PV{pick(c, a.p, b.p), pick(c, a.n, b.n), c ? a.md : b.md}; }
+
 
 // Path vertex q (1 <= q <= number of scattering vertices) of connected path
 // (s, i, j): eye slots i..0, then the start vertex x_D (techniques 2, 3, 8),
@@ -1421,7 +1430,11 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
 
   // ---- assemble x_0 .. x_{k-1}
   PV v[kMaxK];
-  Cross ex[kMaxK];
+  // edge crossings: bit a of exm marks a crossed edge a; exw[a] is the one sum
+  // the ghost densities of that edge use (s_b at the light end, s_a at the eye
+  // edge, s_0 between)
+  float exw[kMaxK];
+  uint32_t exm = 0u;
   v[0] = PV{S.cam.eye, S.cam.fwd, 0u};
 #pragma unroll
   for (int q = 1; q < kMaxK - 1; ++q) {
@@ -1448,7 +1461,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
   const bool motion = !A.material_mode;
 #pragma unroll
   for (int a = 0; a < kMaxK - 1; ++a) {
-    ex[a] = no_cross();
+    exw[a] = 0.0f;
     if (a > k - 2 || !motion) continue;
     float4 r1, r2;  // crossing record: count in r1.w, sums in r2.xyz
     if (a == 0 && k == 2) {
@@ -1457,7 +1470,8 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
     } else if (a == 0) {
       if (i >= 0) {
         const float4 c = EYE(W, i, 3, s);
-        ex[a] = Cross{c.x, c.y, c.z, c.w};
+        exw[a] = a == k - 2 ? c.w : c.z;
+        exm |= c.x > 0.0f ? 1u : 0u;
         continue;
       } else if (mid) {
         r1 = STA(W, 1, s);
@@ -1485,7 +1499,8 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
       r1 = LIT(W, bb, 1, s);
       r2 = LIT(W, bb, 2, s);
     }
-    ex[a] = Cross{r1.w, r2.x, r2.y, r2.z};
+    exw[a] = a == k - 2 ? r2.z : (a == 0 ? r2.y : r2.x);
+    exm |= r1.w > 0.0f ? 1u << a : 0u;
   }
 
   const DevCamera& C = S.cam;
@@ -1519,20 +1534,13 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
 #pragma unroll
     for (int q = 1; q < kMaxK - 1; ++q) {
       if (q > k - 2) break;
-      const PV cur = q == sub ? y : v[q];
-      const vec3 pp = q - 1 == sub ? y.p : v[q - 1].p;
-      vec3 pn;
-      vec3 nn;
-      bool envn = false;
-      if (q + 1 == k - 1) {
-        envn = E.env;
-        pn = E.env ? cur.p + E.n : E.p;
-        nn = E.n;
-      } else {
-        const PV nx = q + 1 == sub ? y : v[q + 1];
-        pn = nx.p;
-        nn = nx.n;
-      }
+      const PV cur = pick(q == sub, y, v[q]);
+      const vec3 pp = pick(q - 1 == sub, y.p, v[q - 1].p);
+      const bool last = q + 1 == k - 1;
+      const PV nx = pick(q + 1 == sub, y, v[q + 1]);
+      const bool envn = last && E.env;
+      const vec3 pn = pick(last, lpos(E, cur.p), nx.p);
+      const vec3 nn = pick(last, E.n, nx.n);
       const Material m = vmat(S, F, cur.md);
       const vec3 wi = unit(pp - cur.p), wo = envn ? E.n : unit(pn - cur.p);
       const vec3 rho = bsdf_eval(m, cur.n, wi, wo);
@@ -1568,22 +1576,22 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
   };
   auto to_area = [&](int r, int q, vec3 o) -> float {
     if (q == k - 1 && E.env) return 1.0f;
-    const vec3 d = (q == k - 1 ? E.p : v[q].p) - o;
-    const vec3 nq = q == k - 1 ? E.n : v[q].n;
+    const vec3 d = pick(q == k - 1, E.p, v[q].p) - o;
+    const vec3 nq = pick(q == k - 1, E.n, v[q].n);
     return fabsf(dot(nq, unit(d))) / len2(d);
   };
   auto dir_from = [&](int r, int q) -> vec3 {  // unit direction r -> q between path vertices
     if (q == k - 1 && E.env) return E.n;
     if (r == k - 1 && E.env) return -E.n;
-    const vec3 a = r == 0 ? C.eye : (r == k - 1 ? E.p : v[r].p);
-    const vec3 b = q == 0 ? C.eye : (q == k - 1 ? E.p : v[q].p);
+    const vec3 a = pick(r == 0, C.eye, pick(r == k - 1, E.p, v[r].p));
+    const vec3 b = pick(q == 0, C.eye, pick(q == k - 1, E.p, v[q].p));
     return unit(b - a);
   };
   // vertex-generation pdf: vertex q from r by BSDF sampling at r, incoming from o
   auto gen = [&](int r, int q, int inc) -> float {
     const Material m = vmat(S, A.F, v[r].md);
     vec3 og = origin(r, q);
-    const vec3 wo = (q == k - 1 && E.env) ? E.n : unit((q == k - 1 ? E.p : v[q].p) - og);
+    const vec3 wo = (q == k - 1 && E.env) ? E.n : unit(pick(q == k - 1, E.p, v[q].p) - og);
     return bsdf_pdf(m, v[r].n, dir_from(r, inc), wo) * to_area(r, q, og);
   };
   float Apre[kMaxK], Bsuf[kMaxK + 1];
@@ -1631,7 +1639,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
     const float pdir = 1.0f / (4.0f * kPi);
 #pragma unroll
     for (int a = 0; a < kMaxK - 1; ++a) {
-      if (a > k - 2 || !(ex[a].n > 0.0f)) continue;
+      if (a > k - 2 || !((exm >> a) & 1u)) continue;
       if (a == k - 2) {
         if (on(4) && !E.env) {
           const vec3 o = spawn(S, E.p, E.n, vl.p);  // the offset light point generating x_{k-2}
@@ -1640,18 +1648,18 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
 #pragma unroll
           for (int q = 1; q < kMaxK; ++q)
             if (q == k - 3) ak = Apre[q];
-          sum += pL * pG * ex[a].sb * fabsf(dot(vl.n, unit(d))) / len2(d) * ak;
+          sum += pL * pG * exw[a] * fabsf(dot(vl.n, unit(d))) / len2(d) * ak;
         }
       } else if (a == 0) {
         if (on(5)) {
           const vec3 d = v[1].p - C.eye;
-          sum += pG * ex[a].sa * fabsf(dot(v[1].n, unit(d))) / len2(d) * Bsuf[2] * pL;
+          sum += pG * exw[a] * fabsf(dot(v[1].n, unit(d))) / len2(d) * Bsuf[2] * pL;
         }
       } else if (on(6)) {
         const vec3 d = v[a + 1].p - v[a].p;
         const vec3 w = unit(d);
         const float G = fabsf(dot(v[a].n, w)) * fabsf(dot(v[a + 1].n, w)) / len2(d);
-        sum += pG * pdir * G * ex[a].s0 * Apre[a > 0 ? a - 1 : 0] * Bsuf[a + 2] * pL;
+        sum += pG * pdir * G * exw[a] * Apre[a > 0 ? a - 1 : 0] * Bsuf[a + 2] * pL;
       }
     }
   }
@@ -1674,9 +1682,9 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
     } else if (A.F.same_pose) {
 #pragma unroll
       for (int a = 0; a < kMaxK - 1; ++a)
-        if (a <= k - 2 && ex[a].n > 0.0f) rej = 5;
+        if (a <= k - 2 && ((exm >> a) & 1u)) rej = 5;
     } else {
-      const bool retrace = (v[1].md & kDynBit) || ex[0].n > 0.0f;
+      const bool retrace = (v[1].md & kDynBit) || (exm & 1u);
       int moved = retrace ? 1 : 0;
       istar = retrace ? 1 : 0;
 #pragma unroll
@@ -1726,7 +1734,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
           const float aj = light ? 1.0f : roughness(vmat(S, A.F, xj.md));
           if (fminf(fminf(ax, ay), aj) < A.alpha_min) rej = rej ? rej : 3;
           if (rej || (light && E.env)) continue;
-          const vec3 pj = light ? E.p : xj.p, nj = light ? E.n : xj.n;
+          const vec3 pj = pick(light, E.p, xj.p), nj = pick(light, E.n, xj.n);
           const vec3 dy = y.p - pj, dxv = xs.p - pj;
           const float ly2 = dot(dy, dy), lx2 = dot(dxv, dxv);
           if (fminf(sqrtf(ly2), sqrtf(lx2)) < A.d_min) {
@@ -1742,16 +1750,14 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
 #pragma unroll
         for (int q = 1; q < kMaxK - 1; ++q) {
           if (q > k - 2 || rej) continue;
-          const PV cur = q == istar ? y : v[q];
+          const PV cur = pick(q == istar, y, v[q]);
           if (is_emitter(S, cur.md)) rej = 6;
-          const vec3 a = q - 1 == 0 ? C.eye : (q - 1 == istar ? y.p : v[q - 1].p);
-          vec3 b;
-          if (q + 1 == k - 1) b = E.env ? cur.p + E.n : E.p;
-          else b = q + 1 == istar ? y.p : v[q + 1].p;
+          const vec3 a = pick(q - 1 == 0, C.eye, pick(q - 1 == istar, y.p, v[q - 1].p));
+          const vec3 b = pick(q + 1 == k - 1, lpos(E, cur.p), pick(q + 1 == istar, y.p, v[q + 1].p));
           if (!same_side(cur.n, cur.p, a, b)) rej = 6;
         }
         if (!rej && !E.env) {
-          const vec3 prv = k - 2 == istar ? y.p : vl.p;
+          const vec3 prv = pick(k - 2 == istar, y.p, vl.p);
           if (!(dot(E.n, prv - E.p) > 0.0f)) rej = 6;
         }
       }
@@ -1763,16 +1769,14 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
           const bool touches = moved == 1 && (a == istar - 1 || a == istar);
           if (touches) {
             if (a == 0) continue;
-            const PV pa = a == istar ? y : v[a];
+            const PV pa = pick(a == istar, y, v[a]);
             const End EA = end_surf(pa.p, pa.n);
-            End EB;
-            if (a + 1 == k - 1) EB = end_light(E);
-            else {
-              const PV pb = a + 1 == istar ? y : v[a + 1];
-              EB = end_surf(pb.p, pb.n);
-            }
+            const bool last = a + 1 == k - 1;
+            const PV pb = pick(a + 1 == istar, y, v[a + 1]);
+            const End EB{pick(last, E.p, pb.p), pick(last, E.n, pb.n),
+                         last ? (E.env ? END_ENV : END_LIGHT) : END_SURF};
             if (!edge_visible<CW>(S, Fp, EA, EB, stk, wc, RAY_MAPVIS)) rej = 5;
-          } else if (ex[a].n > 0.0f) {
+          } else if ((exm >> a) & 1u) {
             rej = 5;
           }
         }
