@@ -431,6 +431,131 @@ DEV Hit closest(const DevScene& S, const DevFrame& F, vec3 o, vec3 d, int* stk, 
   return h;
 }
 
+// Both closest hits of the line o + t d: hf along d (t > 0) and hb along -d
+// (t < 0, hb.t = -t), in one traversal.  tri_t and the slab test are odd in
+// d (every product and sum in them changes sign exactly), so hf and hb are
+// bit for bit the hits of two closest-hit queries along d and -d.
+DEV bool slab_line(float lx, float ly, float lz, float hx, float hy, float hz, vec3 inv, vec3 oi, float tf, float tb,
+                   float& tnear) {
+#pragma clang fp contract(fast)
+  const float ax = lx * inv.x - oi.x, bx = hx * inv.x - oi.x;
+  const float ay = ly * inv.y - oi.y, by = hy * inv.y - oi.y;
+  const float az = lz * inv.z - oi.z, bz = hz * inv.z - oi.z;
+  const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), -tb));
+  const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tf));
+  tnear = fabsf(t0) < fabsf(t1) ? fabsf(t0) : fabsf(t1);
+  return t0 <= t1;
+}
+
+// tri_t without the sign test: the line parameter of the hit, or NaN.
+DEV float tri_line(vec3 o, vec3 d, vec3 v0, vec3 e1, vec3 e2) {
+  const vec3 p = cross(d, e2);
+  const float det = dot(e1, p);
+  if (det == 0.0f) return __builtin_nanf("");
+  const float inv = 1.0f / det;
+  const vec3 s = o - v0;
+  const float u = dot(s, p) * inv;
+  if (u < 0.0f || u > 1.0f) return __builtin_nanf("");
+  const vec3 q = cross(s, e1);
+  const float v = dot(d, q) * inv;
+  if (v < 0.0f || u + v > 1.0f) return __builtin_nanf("");
+  return dot(e2, q) * inv;
+}
+
+// bvh_walk over the line: leaves whose box meets o + t d, -tb < t < tf.
+template <bool CW, class Leaf>
+DEV void bvh_walk_line(const float4* __restrict__ N, vec3 o, vec3 d, const float& tf, const float& tb,
+                       int* __restrict__ stk, WorkCount& wc, Leaf&& leaf) {
+  const vec3 inv = v3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+  const vec3 oi = v3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
+  const int lane = threadIdx.x;
+  constexpr int kDone = 0x7fffffff;
+  int sp = 0;
+  int node = 0;
+  int pl = 0;
+  while (node != kDone) {
+    while ((uint32_t)node < (uint32_t)kDone) {
+      const float4 a = gld(N, 4 * (size_t)node), b = gld(N, 4 * (size_t)node + 1), c = gld(N, 4 * (size_t)node + 2);
+      const int4 e = gld(reinterpret_cast<const int4*>(N), 4 * (size_t)node + 3);
+      if (CW) wc.nodes++;
+      float n0, n1;
+      const bool h0 = slab_line(a.x, a.y, a.z, a.w, b.x, b.y, inv, oi, tf, tb, n0);
+      const bool h1 = slab_line(b.z, b.w, c.x, c.y, c.z, c.w, inv, oi, tf, tb, n1);
+      const bool first0 = n0 <= n1;
+      if (h0 && h1) {
+        stk[sp * kTraceBlock + lane] = first0 ? e.y : e.x;
+        ++sp;
+        node = first0 ? e.x : e.y;
+      } else if (h0) {
+        node = e.x;
+      } else if (h1) {
+        node = e.y;
+      } else {
+        node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
+      }
+      if (node < 0 && pl == 0) {
+        pl = node;
+        node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
+      }
+      if (__ballot(pl == 0) == 0ull) break;
+    }
+    while (pl < 0) {
+      leaf(pl);
+      pl = 0;
+      if (node < 0) {
+        pl = node;
+        node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
+      }
+    }
+  }
+}
+
+template <bool CW>
+DEV void closest_line_in(const DevBvh& B, vec3 o, vec3 d, Hit& hf, Hit& hb, int dyn, int* stk, WorkCount& wc) {
+  bvh_walk_line<CW>(B.nodes, o, d, hf.t, hb.t, stk, wc, [&](int code) {
+    const int f = leaf_first(code), n = leaf_count(code);
+    for (int i = f; i < f + n; ++i) {
+      vec3 v0, e1, e2;
+      int id, mat;
+      load_tri(B.tris, i, v0, e1, e2, id, mat);
+      if (CW) wc.tris++;
+      const float t = tri_line(o, d, v0, e1, e2);
+      if (t > 0.0f && (t < hf.t || (t == hf.t && id < hf.id))) {
+        hf.t = t;
+        hf.id = id;
+        hf.idx = i;
+        hf.dyn = dyn;
+        hf.ok = 1;
+      }
+      if (-t > 0.0f && (-t < hb.t || (-t == hb.t && id < hb.id))) {
+        hb.t = -t;
+        hb.id = id;
+        hb.idx = i;
+        hb.dyn = dyn;
+        hb.ok = 1;
+      }
+    }
+  });
+}
+
+// closest(o, d) and closest(o, -d) of scene_f as one line query (counted as
+// one ray; the caller counts the second if it would have traced it).
+template <bool CW>
+DEV void closest_line(const DevScene& S, const DevFrame& F, vec3 o, vec3 d, Hit& hf, Hit& hb, int* stk,
+                      WorkCount& wc) {
+  const Pose& pose = F.pose;
+  if (CW) wc.rays[RAY_CLOSEST]++;
+  hf.t = INFINITY;
+  hf.id = 0x7fffffff;
+  hf.idx = -1;
+  hf.dyn = 0;
+  hf.ok = 0;
+  hb = hf;
+  closest_line_in<CW>(S.stat, o, d, hf, hb, 0, stk, wc);
+  if (near_object(F, o, d, hf.t) || near_object(F, o, -d, hb.t))
+    closest_line_in<CW>(S.obj, pose_inv_apply(pose, o), pose_inv_rot(pose, d), hf, hb, 1, stk, wc);
+}
+
 template <bool CW>
 DEV bool any_in(const DevBvh& B, vec3 o, vec3 d, float tmax, int* stk, WorkCount& wc) {
   bool hit = false;

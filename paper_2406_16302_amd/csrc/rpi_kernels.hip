@@ -465,14 +465,15 @@ DEV void tech6(Lane& L) {
   if (deep_inside(S, A.F, xg)) return;  // x_G inside the object: no path of this start
   draw(L.g, 0, 0, 2, u);
   const vec3 w = sphere_dir(u[0], u[1]);
-  const Hit hl = closest<CW>(S, A.F, xg, w, L.stk, L.wc);
+  Hit hl, he;  // the closest hits along w and -w, in one line query
+  closest_line<CW>(S, A.F, xg, w, hl, he, L.stk, L.wc);
   if (!hl.ok) return;
   vec3 l0, l0n;
   uint32_t l0md;
   hit_vertex(S, A.F.pose, hl, xg, w, l0, l0n, l0md);
   if (is_emitter(S, l0md)) return;
   if (interior_hit(S, A.F, l0, l0n, l0md, xg)) return;  // x_G inside the object: no path leaves it
-  const Hit he = closest<CW>(S, A.F, xg, -w, L.stk, L.wc);
+  if (CW) L.wc.rays[RAY_CLOSEST]++;  // the query along -w
   if (!he.ok) return;
   vec3 e0, e0n;
   uint32_t e0md;
