@@ -673,7 +673,13 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 #ifndef RPI_WALK_WAVES_PER_EU
 #define RPI_WALK_WAVES_PER_EU 3
 #endif
-#define RPI_WALK_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_WALK_WAVES_PER_EU)))
+// the eye walks of techniques 1 and 4 (one walk per task) spill little at
+// 4 waves per SIMD and gain from the occupancy
+#ifndef RPI_WALK_WAVES_T14
+#define RPI_WALK_WAVES_T14 4
+#endif
+#define RPI_WALK_OCCUPANCY(T) \
+  __attribute__((amdgpu_waves_per_eu((T) == 1 || (T) == 4 ? RPI_WALK_WAVES_T14 : RPI_WALK_WAVES_PER_EU)))
 // connect holds a whole path (vertices, crossing sums, pdf tables) in
 // registers: 3 waves per SIMD gives it 168 VGPRs and no spills
 #ifndef RPI_CONNECT_WAVES_PER_EU
@@ -1208,7 +1214,7 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
 // wave their finished tasks' connected paths with one queue reservation per
 // wave and take new tasks with one counter update per wave.
 template <int TECH, bool CW>
-__global__ __launch_bounds__(kTraceBlock) RPI_WALK_OCCUPANCY void walk_task_kernel(WalkArgs A) {
+__global__ __launch_bounds__(kTraceBlock) RPI_WALK_OCCUPANCY(TECH) void walk_task_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   constexpr int kDone = 0x7fffffff;  // no node left in the stage
   const int lane = threadIdx.x;
