@@ -88,7 +88,8 @@ typedef struct {
   float c_weight;         /* two-way weight of accepted pairs, default 0.5 */
   int64_t sample_begin;   /* sample-index range of every (technique, direction) stream */
   int64_t sample_end;     /* < 0: spp * width * height */
-  int32_t queue_cap;      /* samples per chunk (0: automatic) */
+  int32_t queue_cap;      /* samples per round, rounded up to a multiple of 64 and
+                             capped at 2^25 (0: the tuned or default size) */
   uint32_t job;           /* third Philox counter word (distinct jobs get independent streams) */
   /* Learned proposal (spec addition, not in the paper): with a non-NULL
    * proposal, strategy_mask bit 7 enables technique 8 -- a start x_D on the
@@ -196,7 +197,7 @@ typedef struct {
   double ms_per_msample;          /* measured device time per million technique samples */
 } rpi_tuning;
 
-/* Time a small grid of launch configurations (round size 2^22..2^24,
+/* Time a small grid of launch configurations (round size 2^23, 2^24 or 2^25,
  * persistent walk grid 16 or 32 blocks per CU) on the first 2^24 samples of
  * every stream of this edit and keep the fastest for later calls on this
  * scene whose queue_cap is 0.
@@ -206,8 +207,9 @@ rpi_status rpi_autotune(rpi_scene* scene, const rpi_edit* edit, const rpi_render
 
 /* Use a launch configuration measured earlier (for example by rpi_autotune
  * in another process) for later calls on this scene whose queue_cap is 0.
- * Errors: INVALID_ARG (queue_cap not a positive multiple of 64, or blocks
- * per CU outside [1, 64]). */
+ * Errors: INVALID_ARG (queue_cap not a positive multiple of 64 or above
+ * 2^25, the most samples a round's path codes can address, or blocks per CU
+ * outside [1, 64]). */
 rpi_status rpi_set_tuning(rpi_scene* scene, const rpi_tuning* tuning);
 
 /* Per-path records of the last rpi_render_residual call on this scene made
