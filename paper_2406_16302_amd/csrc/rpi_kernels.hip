@@ -681,7 +681,7 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 #define RPI_WALK_OCCUPANCY(T) \
   __attribute__((amdgpu_waves_per_eu((T) == 1 || (T) == 4 ? RPI_WALK_WAVES_T14 : RPI_WALK_WAVES_PER_EU)))
 // connect holds a whole path (vertices, crossing sums, pdf tables) in
-// registers: 3 waves per SIMD gives it 168 VGPRs and no spills
+// registers: 3 waves per SIMD gives it 168 VGPRs and leaves a few spills
 #ifndef RPI_CONNECT_WAVES_PER_EU
 #define RPI_CONNECT_WAVES_PER_EU 3
 #endif
@@ -1436,7 +1436,8 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
   tr.weight = 0.0f;
 
   // ---- assemble x_0 .. x_{k-1}
-  PV v[kMaxK];
+  PV v[kMaxK] = {};  // entries past the last scattering vertex stay zero (the
+                     // selects below read them and never take them)
   // edge crossings: bit a of exm marks a crossed edge a; exw[a] is the one sum
   // the ghost densities of that edge use (s_b at the light end, s_a at the eye
   // edge, s_0 between)
