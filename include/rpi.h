@@ -91,7 +91,7 @@ typedef struct {
   int32_t queue_cap;      /* samples per round, rounded up to a multiple of 64 and
                              capped at 2^25 (0: the tuned or default size) */
   uint32_t job;           /* third Philox counter word (distinct jobs get independent streams) */
-  /* Learned proposal (spec addition, not in the paper): with a non-NULL
+  /* Learned proposal (addition beyond the paper): with a non-NULL
    * proposal, strategy_mask bit 7 enables technique 8 -- a start x_D on the
    * object whose light-side direction is drawn from the proposal's lobes,
    * seen by the camera directly (the paths of technique 2) or followed by a
@@ -177,7 +177,7 @@ typedef struct {
 } rpi_job;
 
 /* Many residual jobs (e.g. consecutive frames of an animation) with uneven
- * image sizes (spec addition; the paper leaves batching to future work,
+ * image sizes (addition beyond the paper, which leaves batching to future work,
  * Sec. 6.3).  The launch sequence (persistent walk kernels pulling 64-sample
  * work items of all jobs, connect, batch-wide tile splat) is captured once
  * into a hipGraph on a library stream and replayed on hip_stream; later calls
@@ -219,7 +219,7 @@ rpi_status rpi_set_tuning(rpi_scene* scene, const rpi_tuning* tuning);
 rpi_status rpi_get_records(const rpi_scene* scene, void* host_out, int64_t cap, int64_t* count);
 
 /* ------------------------------------------------------------------------
- * Learned proposal (spec addition; the paper names better sampling of
+ * Learned proposal (addition beyond the paper, which names better sampling of
  * the residual integrand as future work, Sec. 7).  An MLP with inputs
  * (position of a point on the object normalised to the object's bounding box
  * in object space, its object-space normal), three hidden layers of 64 ReLU

@@ -16,6 +16,7 @@ _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 TECH_MASK_ALL = 0x7F
+EDIT_MATERIAL = 1  # edit kind of a material change in the shared input format (rigid motion is 0)
 
 
 def build(force: bool = True) -> str:
@@ -250,7 +251,6 @@ def map_check(osc: OracleScene, pose_new, spp, depth, seed, s0=0, s1=-1, alpha_m
 
 def residual_for(ws, osc: OracleScene, **kw):
     """Run the oracle's residual estimator for a scenes.Workload."""
-    from paper_2406_16302_amd.scenes import EDIT_MATERIAL
     e = ws.edit
     args = dict(spp=ws.spp, depth=ws.depth, seed=ws.seed, mask=ws.mask, two_way=ws.two_way)
     if e.kind == EDIT_MATERIAL:

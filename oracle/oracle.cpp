@@ -22,9 +22,9 @@
 // precision the GPU kernel takes those decisions in.  Contributions, pdfs,
 // MIS sums and the image are computed and accumulated in fp64.
 //
-// Where the paper is silent the readings are the ones listed in the design doc
-// (depth = segments, c = 1/2 two-way weights, one technique-independent map,
-// uniform sphere for technique (6), outward cosine lobe for technique (3)...).
+// Where the paper is silent it takes one reading and keeps it: depth counts
+// segments, c = 1/2 two-way weights, one technique-independent map, uniform
+// sphere for technique (6), outward cosine lobe for technique (3), etc.
 //
 // Parity pins: tests/test_oracle_*.py (identity edit, white furnace closed
 // form, depth-2 quadrature, convergence to the difference of two frames,
@@ -773,7 +773,7 @@ static bool supported(const Scene& S, const Frame& F, const Path& P, bool check_
 // ---------------------------------------------------------------- learned proposal
 // A small MLP maps a surface point of the object (position normalised to the
 // object's bounding box, geometric normal; object space) to a mixture of 8
-// von Mises-Fisher lobes over directions (spec addition: the paper
+// von Mises-Fisher lobes over directions (addition beyond the paper: the paper
 // names better importance sampling of the residual integrand as future work,
 // Sec. 7).  Layers 6 -> 64 -> 64 -> 64 -> 40 with ReLU; parameters in one
 // flat vector: W1[6][64], b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
@@ -2089,6 +2089,11 @@ int orc_trace(void* sp, const float* pose, const float* rays, int n, float* t_ou
   }
   return 0;
 }
+
+// GGX terms on their own, for the microfacet pins (normalisation of D, the
+// weak white furnace of Smith G1 with D).
+double orc_ggx_D(double a, double nh) { return ggx_D(a, nh); }
+double orc_ggx_G1(double a, double c) { return ggx_G1(a, c); }
 
 // BSDF helpers for the normalisation pins (Lambertian/GGX).
 double orc_bsdf_eval(const float* m, const double* n, const double* wi, const double* wo, double* rgb) {

@@ -1,7 +1,7 @@
 // Learned proposal on the matrix cores: a 6-64-64-64-40 ReLU MLP evaluated
 // by one wavefront for 64 rows at a time with BF16 operands and FP32
 // accumulation (v_mfma_f32_16x16x16bf16_1k), and the 8-lobe von Mises-Fisher
-// mixture it parameterises (spec addition; the paper leaves better
+// mixture it parameterises (addition beyond the paper, which leaves better
 // importance sampling of the residual integrand to future work, Sec. 7).
 #pragma once
 

@@ -1,4 +1,4 @@
-// Learned proposal kernels (spec addition to the estimator; the paper
+// Learned proposal kernels (addition beyond the paper; the paper
 // leaves better sampling of the residual integrand to future work, Sec. 7):
 // batched MLP inference, the gradient of the weighted negative log-likelihood
 // of the vMF mixture (the Monte Carlo KL objective of neural importance
