@@ -23,6 +23,7 @@
 #ifndef RPI_H
 #define RPI_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -45,10 +46,37 @@ typedef int32_t rpi_status;
 #define RPI_FLAG_COUNT_WORK 4u /* count BVH node visits and triangle tests (slower kernels) */
 #define RPI_FLAG_RECORDS 8u    /* keep per-path splat records for inspection (rpi_get_records) */
 #define RPI_FLAG_TIME_KERNELS 16u /* time every launch with HIP events (per-kernel durations in rpi_stats) */
+/* Path mapping off: the ablation of the paper's fig. ablat_pathmapping.
+ * Every connected path is treated as rejected (Sec. 5, path rejection), so
+ * each frame's dynamic paths keep weight 1 in their own frame and the
+ * residual becomes the difference of the two frames' dynamic parts (still
+ * unbiased, without the correlation the mapping buys).  Motion edits with
+ * RPI_FLAG_TWO_WAY only; anything else is UNSUPPORTED. */
+#define RPI_FLAG_NO_MAPPING 32u
+/* Per-technique images (the decomposition of the paper's fig.
+ * importance_sample): technique t's MIS-weighted share of the residual goes
+ * to image t-1 of params.d_technique_images, and d_out receives their sum,
+ * added pixel by pixel in technique order 1..8 (onto d_out's contents with
+ * RPI_FLAG_ACCUMULATE, else onto zero).  The technique images are always
+ * overwritten (zero for techniques that did not run). */
+#define RPI_FLAG_PER_TECHNIQUE 64u
 
 typedef struct rpi_scene rpi_scene;
 typedef struct rpi_edit rpi_edit;
 typedef struct rpi_proposal rpi_proposal;
+
+/* Device-memory hook.  allocate returns `bytes` of device memory (256-byte
+ * aligned) or NULL; deallocate returns it.  Both receive the HIP stream the
+ * memory is used on (NULL for the scene's own arrays).  deallocate may be
+ * called as soon as the work that uses the memory has been enqueued on that
+ * stream, before it has run: the allocator must hand the memory out again
+ * only in stream order (as hipFreeAsync and PyTorch's caching allocator do).
+ * The hook and ctx must stay valid until rpi_destroy_scene returns. */
+typedef struct {
+  void* (*allocate)(void* ctx, size_t bytes, void* hip_stream);
+  void (*deallocate)(void* ctx, void* ptr, void* hip_stream);
+  void* ctx;
+} rpi_allocator;
 
 /* Scene description.  Every array is host memory, copied by rpi_build_scene;
  * the caller may free it on return. */
@@ -113,13 +141,20 @@ typedef struct {
    * densities) (its second-moment contribution under the MIS combination:
    * directions the other strategies sample poorly weigh more). */
   int32_t train_weighting;
+  /* RPI_FLAG_PER_TECHNIQUE: 8 x H x W x 3 float32 device memory (technique
+   * t in image t-1); ignored without the flag. */
+  float* d_technique_images;
+  /* Splat tile edge in pixels: 16 or 32, 0 = automatic (16 unless the images
+   * need more than 16384 tiles).  The image does not depend on it beyond
+   * float rounding. */
+  int32_t tile;
 } rpi_render_params;
 
 typedef struct {
   int64_t samples;        /* technique samples drawn */
   int64_t paths;          /* connected paths evaluated and splatted (residual paths) */
   int64_t accepted;       /* paths whose mapped path was accepted */
-  int64_t rejected[7];    /* by rule R1..R6 (index 0 unused) */
+  int64_t rejected[7];    /* by rule R1..R6 of Sec. 5; index 0: mapping off (RPI_FLAG_NO_MAPPING) */
   int64_t by_tech[9];     /* paths by technique (index 1..8) */
   int64_t rays[6];        /* with RPI_FLAG_COUNT_WORK: closest, shadow, camera, ghost all-hit,
                              mapping re-trace, mapping visibility */
@@ -139,17 +174,26 @@ typedef struct {
   int64_t train_records;  /* training records produced (may exceed train_capacity) */
 } rpi_stats;
 
-/* Copy, validate and upload a scene; builds binned-SAH BVHs for the static
- * geometry and for the object in object space, and the area CDFs.
- * Errors: INVALID_ARG (NaN/inf vertex, index out of range, bad material id,
- * zero-area object or emitter, bad camera), UNSUPPORTED (emissive object,
- * no dynamic triangles), OUT_OF_MEMORY, DEVICE. */
-rpi_status rpi_build_scene(const rpi_scene_desc* desc, rpi_scene** out);
+/* Copy, validate and upload a scene: the static geometry and the object
+ * of both frames (Sec. 3.2: the inputs are the old frame and the new frame,
+ * which differ only by the edited object), with binned-SAH BVHs for the
+ * static geometry and for the object in object space, and the area CDFs of
+ * the object and the emitters.  allocator: NULL for hipMalloc /
+ * hipMallocAsync, else every device allocation of the scene and of the
+ * calls made on it goes through it (learned proposals keep their own).
+ * Errors: INVALID_ARG (NaN/inf vertex, index out of range, bad material id
+ * or type, zero-area object or emitter, bad camera), UNSUPPORTED (emissive
+ * object, object with several materials, no dynamic triangles, no emitter),
+ * OUT_OF_MEMORY, DEVICE.  Validation happens before any device work. */
+rpi_status rpi_build_scene(const rpi_scene_desc* desc, const rpi_allocator* allocator, rpi_scene** out);
 rpi_status rpi_destroy_scene(rpi_scene* scene);
 
-/* Record an edit of the scene's object.  Errors: INVALID_ARG (unknown kind,
- * non-orthonormal or mirrored transform, bad material), UNSUPPORTED
- * (emissive new material). */
+/* Record an edit of the scene's object: a rigid motion (Sec. 5, transform
+ * with object movement) or a material change (Sec. 6.2, material editing).
+ * The description is validated before the scene is used.  Errors:
+ * INVALID_ARG (unknown kind, non-finite, non-orthonormal or mirrored
+ * transform, bad or non-finite material, null scene), UNSUPPORTED (emissive
+ * new material). */
 rpi_status rpi_apply_edit(rpi_scene* scene, const rpi_edit_desc* desc, rpi_edit** out);
 rpi_status rpi_destroy_edit(rpi_edit* edit);
 
@@ -162,10 +206,22 @@ rpi_status rpi_render_residual(const rpi_scene* scene, const rpi_edit* edit, con
                                float* d_out, rpi_stats* stats, void* hip_stream);
 
 /* Plain path tracing (next-event estimation, emission seen directly) of one
- * frame (Sec. 3.1): which = 1 old frame, 2 new frame (edit may be NULL: the
- * scene as given). */
+ * frame (Sec. 3.1, eq. pathIntegral): which = 0 old frame, 1 new frame (edit
+ * may be NULL: the scene as given).  Sample s of a stream goes to pixel
+ * s mod (W*H); the Philox streams are those of technique 7 of
+ * rpi_render_residual in the same frame. */
 rpi_status rpi_render_frame(const rpi_scene* scene, const rpi_edit* edit, int32_t which,
                             const rpi_render_params* params, float* d_out, void* hip_stream);
+
+/* The baselines the paper compares against (Sec. 6.2, incremental
+ * re-rendering): the difference I_new - I_old of two path-traced frames
+ * (as rpi_render_frame) into d_out.  correlated = 1: both frames use the
+ * same random numbers per sample (correlated path tracing; paths that miss
+ * the object's old and new poses cancel exactly); correlated = 0: each frame
+ * from its own streams (path tracing from scratch).  Errors as
+ * rpi_render_frame; edit must not be NULL. */
+rpi_status rpi_render_frame_difference(const rpi_scene* scene, const rpi_edit* edit, int32_t correlated,
+                                       const rpi_render_params* params, float* d_out, void* hip_stream);
 
 /* One job of a batch: a rigid edit given by the object's poses in the two
  * frames (3x4 row-major, relative to the scene as given), its own image. */
@@ -276,6 +332,11 @@ rpi_status rpi_proposal_loss_grad(const rpi_proposal* proposal, const float* d_r
  * Errors: INVALID_ARG (n < 1, bad train params). */
 rpi_status rpi_proposal_train(rpi_proposal* proposal, const float* d_records, int64_t n,
                               const rpi_train_params* train, float* d_losses, void* hip_stream);
+
+/* Wait for the work enqueued on hip_stream and report a device error that
+ * it raised (kernel faults are sticky in HIP and would otherwise surface in
+ * a later call).  Returns RPI_OK or DEVICE. */
+rpi_status rpi_sync_status(void* hip_stream);
 
 /* Thread-local message of the last error. */
 const char* rpi_last_error(void);

@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("seed", C.c_uint64), ("job", C.c_uint32), ("alpha_min", C.c_float),
                 ("d_min", C.c_float), ("jac_max", C.c_float), ("c_weight", C.c_float),
                 ("s0", C.c_int64), ("s1", C.c_int64), ("threads", C.c_int),
-                ("material_mode", C.c_int)]
+                ("material_mode", C.c_int), ("no_mapping", C.c_int)]
 
 
 RECORD_DTYPE = np.dtype([("dir", "<i4"), ("tech", "<i4"), ("sample", "<u4"), ("k", "<i4"),
@@ -88,7 +88,7 @@ def vmf_sample(raw, u0, u1, u2):
 
 
 STAT_NAMES = ["samples", "paths", "accepted", "r1", "r2", "r3", "r4", "r5", "r6", "zero_mis",
-              "t1", "t2", "t3", "t4", "t5", "t6", "t7", "t8"]
+              "t1", "t2", "t3", "t4", "t5", "t6", "t7", "t8", "unmapped"]
 
 _lib = None
 
@@ -115,6 +115,8 @@ def lib():
         L.orc_bsdf_eval.argtypes = [f32p, f64p, f64p, f64p, f64p]
         L.orc_bsdf_sample.argtypes = [f32p, f32p, f32p, C.c_float, C.c_float, f32p]
         L.orc_render_frame.argtypes = [C.c_void_p, f32p, f32p, f32p, C.c_int, C.POINTER(Params), f64p, i64p]
+        L.orc_render_frame_dir.argtypes = [C.c_void_p, f32p, f32p, f32p, C.c_int, C.c_int, C.POINTER(Params), f64p,
+                                           i64p]
         L.orc_render_residual.argtypes = [C.c_void_p, f32p, f32p, f32p, C.POINTER(Params), f64p, f64p, i64p,
                                           C.c_void_p, C.c_int64, i64p, f32p]
         L.orc_mlp_forward.argtypes = [f32p, f64p, C.c_int, C.c_int, f64p]
@@ -190,31 +192,34 @@ class OracleScene:
         return t, ids
 
     def _params(self, spp, depth, mask, two_way, seed, job, alpha_min, d_min, jac_max, c_weight, s0, s1,
-                threads, material_mode):
+                threads, material_mode, no_mapping=False):
         if d_min is None:
             d_min = np.float32(0.01 * scene_diag(self.scene))
         return Params(spp, depth, mask, int(two_way), seed, job, alpha_min, float(d_min), jac_max, c_weight,
-                      s0, s1, threads, int(material_mode))
+                      s0, s1, threads, int(material_mode), int(no_mapping))
 
     def render_frame(self, which, spp, depth, seed, pose_old=IDENTITY, pose_new=IDENTITY, new_mat=None,
-                     s0=0, s1=-1, threads=1, job=0):
+                     s0=0, s1=-1, threads=1, job=0, stream_dir=None):
+        """which: 1 old frame, 2 new frame.  stream_dir: the Philox direction
+        word (default: the frame's own, 0 new / 1 old)."""
         pm = self._params(spp, depth, 0, 0, seed, job, 0.2, 1.0, 10.0, 0.5, s0, s1, threads, 0)
         img = np.zeros((self.H, self.W, 3), np.float64)
         st = np.zeros(4, np.int64)
         po = np.ascontiguousarray(pose_old, np.float32)
         pn = np.ascontiguousarray(pose_new, np.float32)
         nm = None if new_mat is None else np.ascontiguousarray(new_mat, np.float32)
-        lib().orc_render_frame(self.h, _p(po, C.c_float), _p(pn, C.c_float),
-                               None if nm is None else _p(nm, C.c_float), which, C.byref(pm),
-                               _p(img, C.c_double), _p(st, C.c_int64))
+        d = (0 if which == 2 else 1) if stream_dir is None else int(stream_dir)
+        lib().orc_render_frame_dir(self.h, _p(po, C.c_float), _p(pn, C.c_float),
+                                   None if nm is None else _p(nm, C.c_float), which, d, C.byref(pm),
+                                   _p(img, C.c_double), _p(st, C.c_int64))
         return img, {"samples": int(st[0]), "paths": int(st[1])}
 
     def render_residual(self, spp, depth, seed, pose_old=IDENTITY, pose_new=IDENTITY, new_mat=None,
                         material_mode=False, mask=TECH_MASK_ALL, two_way=True, alpha_min=0.2, d_min=None,
                         jac_max=10.0, c_weight=0.5, s0=0, s1=-1, threads=1, job=0, per_tech=False,
-                        records=False, rec_cap=4_000_000, mlp=None):
+                        records=False, rec_cap=4_000_000, mlp=None, no_mapping=False):
         pm = self._params(spp, depth, mask, two_way, seed, job, alpha_min, d_min, jac_max, c_weight, s0, s1,
-                          threads, material_mode)
+                          threads, material_mode, no_mapping)
         img = np.zeros((self.H, self.W, 3), np.float64)
         timg = np.zeros((8, self.H, self.W, 3), np.float64) if per_tech else None
         st = np.zeros(32, np.int64)

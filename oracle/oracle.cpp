@@ -1184,7 +1184,7 @@ static bool path_ok(const Scene& S, const Frame& F, const Path& P) {
 }
 
 // ---------------------------------------------------------------- path mapping (Sec. 5)
-enum { ACCEPT = 0, R1 = 1, R2 = 2, R3 = 3, R4 = 4, R5 = 5, R6 = 6 };
+enum { ACCEPT = 0, R1 = 1, R2 = 2, R3 = 3, R4 = 4, R5 = 5, R6 = 6, REJECT_UNMAPPED = 7 };
 
 struct MapParams {
   float alpha_min, d_min, jac_max;
@@ -1768,6 +1768,7 @@ struct Params {
   int64_t s0, s1;
   int threads;
   int material_mode;
+  int no_mapping;  // the path-mapping ablation: every pair is rejected
 };
 
 struct Record {
@@ -1858,7 +1859,9 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
       double cf = cam_factor(S, X);
       D3 fx = contribution_rest(S, F, X) * cf;
       Path Y = X;
-      int reason = Pm.material_mode ? ACCEPT : map_path(S, F, Fp, X, Y, M);
+      // Without the mapping (the paper's path-mapping ablation) every path is
+      // rejected: it keeps its own frame's term with weight 1.
+      int reason = Pm.material_mode ? ACCEPT : (Pm.no_mapping ? REJECT_UNMAPPED : map_path(S, F, Fp, X, Y, M));
       D3 val;
       if (reason == ACCEPT) {
         D3 fy = contribution_rest(S, Fp, Y) * cf;
@@ -1866,7 +1869,7 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
         st.accepted++;
       } else {
         val = fx;
-        st.rejected[reason]++;
+        st.rejected[reason == REJECT_UNMAPPED ? 0 : reason]++;
       }
       const D3 unweighted = val;
       val = val * (sigma / mt.total / N);
@@ -2112,9 +2115,11 @@ int orc_bsdf_sample(const float* m, const float* n, const float* wi, float u0, f
   return ok ? 1 : 0;
 }
 
-// Plain path tracing of one frame: which = 1 (old) or 2 (new).
-int orc_render_frame(void* sp, const float* pose_old, const float* pose_new, const float* new_mat, int which,
-                     const Params* pm, double* img, int64_t* stats_out) {
+// Plain path tracing of one frame: which = 1 (old) or 2 (new), on the Philox
+// streams of direction `dir` (the frame's own: 0 for the new frame, 1 for the
+// old; tracing both frames on one direction's streams correlates them).
+int orc_render_frame_dir(void* sp, const float* pose_old, const float* pose_new, const float* new_mat, int which,
+                         int dir, const Params* pm, double* img, int64_t* stats_out) {
   Scene& S = *(Scene*)sp;
   Frame F;
   F.ghosts = false;
@@ -2126,7 +2131,6 @@ int orc_render_frame(void* sp, const float* pose_old, const float* pose_new, con
   int64_t s0 = pm->s0, s1 = pm->s1 < 0 ? N : pm->s1;
   Stats st;
   std::memset(&st, 0, sizeof st);
-  int dir = which == 2 ? 0 : 1;
   parallel(pm->threads, s0, s1, P, img, nullptr, 0, st,
            [&](int64_t a, int64_t b, double* im, double*, Stats& s) { frame_range(S, F, dir, *pm, a, b, (double)N, im, s); });
   if (stats_out) {
@@ -2134,6 +2138,10 @@ int orc_render_frame(void* sp, const float* pose_old, const float* pose_new, con
     stats_out[1] = st.paths;
   }
   return 0;
+}
+int orc_render_frame(void* sp, const float* pose_old, const float* pose_new, const float* new_mat, int which,
+                     const Params* pm, double* img, int64_t* stats_out) {
+  return orc_render_frame_dir(sp, pose_old, pose_new, new_mat, which, which == 2 ? 0 : 1, pm, img, stats_out);
 }
 
 // Residual I2 - I1.  Motion edits: pose_old/pose_new are the object poses of
@@ -2218,6 +2226,7 @@ int orc_render_residual(void* sp, const float* pose_old, const float* pose_new, 
     for (int r = 1; r <= 6; ++r) stats_out[2 + r] = st.rejected[r];
     stats_out[9] = st.zero_mis;
     for (int t = 1; t <= 8; ++t) stats_out[9 + t] = st.by_tech[t];
+    stats_out[18] = st.rejected[0];
   }
   if (rec_count) {
     *rec_count = (int64_t)rv.size();

@@ -298,15 +298,6 @@ class Builder {
   int median_depth_ = kMedianDepth;
 };
 
-template <class T>
-rpi_status upload(const std::vector<T>& v, T** out) {
-  *out = nullptr;
-  if (v.empty()) return RPI_OK;
-  HIP_OK(hipMalloc((void**)out, v.size() * sizeof(T)));
-  HIP_OK(hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-  return RPI_OK;
-}
-
 Pose pose_of(const float* m) {
   Pose P;
   for (int i = 0; i < 3; ++i) {
@@ -334,6 +325,9 @@ static void destroy_batch_cache(BatchCache* c);
 
 struct rpi_scene {
   DevScene dev;
+  // device-memory hook (rpi_build_scene); without one: hipMalloc / hipMallocAsync
+  rpi_allocator al{};
+  bool has_al = false;
   // autotuned launch configuration (0 = not tuned)
   int tuned_Q = 0, tuned_walk = 0, tuned_conn = 0;
   BatchCache* batch = nullptr;
@@ -367,6 +361,43 @@ struct rpi_proposal {
   int steps = 0;          // Adam steps taken
   MlpDev view() const { return mlp_view(B, center, inv_half); }
 };
+
+// Device memory of a scene and of the calls on it: through the caller's hook
+// when one was given, else hipMallocAsync on the stream (async) or hipMalloc.
+static rpi_status dev_alloc(const rpi_scene* s, size_t bytes, hipStream_t st, bool async, void** out) {
+  *out = nullptr;
+  if (bytes == 0) return RPI_OK;
+  if (s->has_al) {
+    *out = s->al.allocate(s->al.ctx, bytes, (void*)st);
+    if (!*out) return fail(RPI_ERR_OUT_OF_MEMORY, "the allocator hook returned no memory for " + std::to_string(bytes) + " bytes");
+    return RPI_OK;
+  }
+  hipError_t e = async ? hipMallocAsync(out, bytes, st) : hipMalloc(out, bytes);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return fail(e == hipErrorOutOfMemory ? RPI_ERR_OUT_OF_MEMORY : RPI_ERR_DEVICE,
+                std::string("device allocation of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+  }
+  return RPI_OK;
+}
+static void dev_free(const rpi_scene* s, void* p, hipStream_t st, bool async) {
+  if (!p) return;
+  if (s->has_al) s->al.deallocate(s->al.ctx, p, (void*)st);
+  else if (async) (void)hipFreeAsync(p, st);
+  else (void)hipFree(p);
+}
+
+template <class T>
+static rpi_status upload(const rpi_scene* s, const std::vector<T>& v, T** out) {
+  *out = nullptr;
+  if (v.empty()) return RPI_OK;
+  void* p = nullptr;
+  rpi_status rc = dev_alloc(s, v.size() * sizeof(T), nullptr, false, &p);
+  if (rc) return rc;
+  *out = (T*)p;
+  HIP_OK(hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return RPI_OK;
+}
 
 static bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
@@ -454,11 +485,19 @@ static bool object_convex(const std::vector<HostTri>& obj, double tol, vec3& cen
 }
 
 extern "C" const char* rpi_last_error(void) { return g_err.c_str(); }
-extern "C" const char* rpi_version(void) { return "rpi 0.1 (gfx950)"; }
+extern "C" const char* rpi_version(void) { return "rpi 0.2 (gfx950)"; }
 
-extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, rpi_scene** out) {
+extern "C" rpi_status rpi_sync_status(void* stream) {
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("device error: ") + hipGetErrorString(e));
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, const rpi_allocator* al, rpi_scene** out) {
   if (!d || !out) return fail(RPI_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
+  if (al && (!al->allocate || !al->deallocate)) return fail(RPI_ERR_INVALID_ARG, "allocator hook without functions");
   if (d->num_vertices <= 0 || d->num_triangles <= 0 || !d->positions || !d->indices || !d->tri_material ||
       !d->tri_object || !d->materials || d->num_materials <= 0 || !d->camera)
     return fail(RPI_ERR_INVALID_ARG, "missing scene arrays");
@@ -598,9 +637,13 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, rpi_scene** out) 
   std::memset(&D, 0, sizeof D);
   std::vector<float> mats(d->materials, d->materials + 8 * d->num_materials);
   rpi_status rc;
+  if (al) {
+    S->al = *al;
+    S->has_al = true;
+  }
   auto up = [&](auto& v, auto** p) -> rpi_status {
-    rpi_status r = upload(v, p);
-    if (r == RPI_OK && *p) S->allocs.push_back((void*)*p);
+    rpi_status r = upload(S.get(), v, p);
+    if (*p) S->allocs.push_back((void*)*p);
     return r;
   };
   float4 *sn, *stt, *on, *ot, *of, *lf;
@@ -608,7 +651,7 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, rpi_scene** out) 
   if ((rc = up(bs.nodes, &sn)) || (rc = up(bs.tris, &stt)) || (rc = up(bo.nodes, &on)) || (rc = up(bo.tris, &ot)) ||
       (rc = up(obj_flat, &of)) || (rc = up(light_flat, &lf)) || (rc = up(ocdf, &oc)) || (rc = up(lcdf, &lc)) ||
       (rc = up(mats, &mt))) {
-    for (void* p : S->allocs) (void)hipFree(p);
+    for (void* p : S->allocs) dev_free(S.get(), p, nullptr, false);
     return rc;
   }
   D.stat = DevBvh{sn, stt, (int)stat.size()};
@@ -663,7 +706,8 @@ extern "C" rpi_status rpi_destroy_scene(rpi_scene* s) {
   if (!s) return RPI_OK;
   destroy_batch_cache(s->batch);
   s->batch = nullptr;
-  for (void* p : s->allocs) (void)hipFree(p);
+  (void)hipDeviceSynchronize();  // no call on the scene may still be running
+  for (void* p : s->allocs) dev_free(s, p, nullptr, false);
   delete s;
   return RPI_OK;
 }
@@ -687,26 +731,33 @@ static rpi_status check_rigid(const float* m) {
 }
 
 extern "C" rpi_status rpi_apply_edit(rpi_scene* s, const rpi_edit_desc* d, rpi_edit** out) {
-  if (!s || !d || !out) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  if (!d || !out) return fail(RPI_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
-  std::unique_ptr<rpi_edit> e(new rpi_edit());
-  e->kind = d->kind;
-  std::memcpy(e->pose_old, kIdentity, sizeof kIdentity);
+  // the description is checked first, on its own (no device work, no scene state)
   if (d->kind == RPI_EDIT_RIGID) {
     rpi_status rc = check_rigid(d->old_to_new);
     if (rc) return rc;
-    std::memcpy(e->pose_new, d->old_to_new, sizeof e->pose_new);
-    e->new_mat = s->obj_mat;
   } else if (d->kind == RPI_EDIT_MATERIAL) {
-    std::memcpy(e->pose_new, kIdentity, sizeof kIdentity);
     const float* m = d->new_material;
     const int t = (int)m[0];
     if (t == MAT_EMITTER) return fail(RPI_ERR_UNSUPPORTED, "emissive new material");
     if (!(t == MAT_DIFFUSE || t == MAT_GGX) || (float)t != m[0]) return fail(RPI_ERR_INVALID_ARG, "bad material type");
     if (t == MAT_GGX && !(m[4] > 0.0f && m[4] <= 1.0f)) return fail(RPI_ERR_INVALID_ARG, "GGX roughness must be in (0, 1]");
-    e->new_mat = mat_of(m);
+    for (int i = 1; i < 8; ++i)
+      if (!std::isfinite(m[i])) return fail(RPI_ERR_INVALID_ARG, "non-finite material parameter");
   } else {
     return fail(RPI_ERR_INVALID_ARG, "unknown edit kind");
+  }
+  if (!s) return fail(RPI_ERR_INVALID_ARG, "null scene");
+  std::unique_ptr<rpi_edit> e(new rpi_edit());
+  e->kind = d->kind;
+  std::memcpy(e->pose_old, kIdentity, sizeof kIdentity);
+  if (d->kind == RPI_EDIT_RIGID) {
+    std::memcpy(e->pose_new, d->old_to_new, sizeof e->pose_new);
+    e->new_mat = s->obj_mat;
+  } else {
+    std::memcpy(e->pose_new, kIdentity, sizeof kIdentity);
+    e->new_mat = mat_of(d->new_material);
   }
   *out = e.release();
   return RPI_OK;
@@ -777,6 +828,11 @@ static rpi_status check_params(const rpi_scene* s, const rpi_render_params* p) {
   if ((p->strategy_mask & 0x80u) && !p->proposal) return fail(RPI_ERR_INVALID_ARG, "technique 8 needs a proposal");
   if (p->d_train_records && p->train_capacity < 0) return fail(RPI_ERR_INVALID_ARG, "negative train_capacity");
   if (p->train_weighting != 0 && p->train_weighting != 1) return fail(RPI_ERR_INVALID_ARG, "train_weighting must be 0 or 1");
+  if (p->tile != 0 && p->tile != 16 && p->tile != 32) return fail(RPI_ERR_INVALID_ARG, "tile must be 0, 16 or 32");
+  if ((p->flags & RPI_FLAG_PER_TECHNIQUE) && !p->d_technique_images)
+    return fail(RPI_ERR_INVALID_ARG, "RPI_FLAG_PER_TECHNIQUE needs d_technique_images");
+  if ((p->flags & RPI_FLAG_NO_MAPPING) && !(p->flags & RPI_FLAG_TWO_WAY))
+    return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING needs RPI_FLAG_TWO_WAY (a motion edit sampled in both frames)");
   if (!(p->jac_max > 1.0f) || !(p->alpha_min >= 0.0f) || !(p->c_weight > 0.0f && p->c_weight < 1.0f))
     return fail(RPI_ERR_INVALID_ARG, "bad rejection / weight parameters");
   const int64_t N = (int64_t)p->spp * s->W * s->H;
@@ -822,6 +878,7 @@ struct JobSpec {
   Material mat_old, mat_new;
   int W, H;
   float* out;
+  float* tech = nullptr;  // RPI_FLAG_PER_TECHNIQUE: 8 images of W x H x 3
 };
 
 // Launch configuration (chosen by the autotuner or defaults).
@@ -834,6 +891,7 @@ struct Tuning {
 // Device workspace for rounds of Q samples over a batch of jobs.
 struct Ws {
   void* mem = nullptr;
+  const rpi_scene* owner = nullptr;  // whose allocator holds mem
   bool async = true;
   Workspace W{};
   DevStats* stats = nullptr;
@@ -845,8 +903,8 @@ struct Ws {
   size_t bytes = 0;
 };
 
-rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep, bool t8, hipStream_t st,
-                    bool async) {
+rpi_status ws_alloc(const rpi_scene* s, Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep,
+                    bool t8, hipStream_t st, bool async) {
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t o = off;
@@ -880,8 +938,9 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
   const size_t o_nt = take(256);
   w.bytes = off;
   w.async = async;
-  if (async) HIP_OK(hipMallocAsync(&w.mem, off, st));
-  else HIP_OK(hipMalloc(&w.mem, off));
+  w.owner = s;
+  rpi_status rc = dev_alloc(s, off, st, async, &w.mem);
+  if (rc) return rc;
   char* b = (char*)w.mem;
   w.W.eye = (float4*)(b + o_eye);
   w.W.light = (float4*)(b + o_light);
@@ -917,8 +976,7 @@ rpi_status ws_alloc(Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int n
 
 void ws_free(Ws& w, hipStream_t st) {
   if (!w.mem) return;
-  if (w.async) (void)hipFreeAsync(w.mem, st);
-  else (void)hipFree(w.mem);
+  dev_free(w.owner, w.mem, st, w.async);
   w.mem = nullptr;
 }
 
@@ -974,10 +1032,11 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
   pl.jobs.resize(nj);
   pl.ntiles = 0;
   pl.tile_job.clear();
-  // 16x16 tiles unless the batch needs more than kMaxTiles of them
+  // 16x16 tiles unless the batch needs more than kMaxTiles of them (or the
+  // caller asks for a tile edge)
   int64_t t16 = 0;
   for (const JobSpec& q : js) t16 += (int64_t)((q.W + 15) / 16) * ((q.H + 15) / 16);
-  pl.ts = t16 <= kMaxTiles ? 16 : 32;
+  pl.ts = p->tile ? p->tile : (t16 <= kMaxTiles ? 16 : 32);
   const int kTileSize = pl.ts;
   for (int j = 0; j < nj; ++j) {
     const JobSpec& q = js[j];
@@ -987,6 +1046,7 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
     J.F[0] = make_frame(s, q.pose_new, q.pose_old, material_mode ? q.mat_new : q.mat_old, !material_mode);
     J.F[1] = make_frame(s, q.pose_old, q.pose_new, q.mat_old, !material_mode);
     J.image = q.out;
+    J.tech_images = q.tech;
     const int64_t N = (int64_t)p->spp * q.W * q.H;
     if (N > 0xffffffffLL) return fail(RPI_ERR_UNSUPPORTED, "more than 2^32 samples per technique stream");
     J.s0 = p->sample_begin;
@@ -1001,7 +1061,9 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
     for (int t = 0; t < nt; ++t) pl.tile_job.push_back(j);
     pl.ntiles += nt;
   }
-  if (pl.ntiles > kMaxTiles) return fail(RPI_ERR_UNSUPPORTED, "images exceed 16384 tiles of 32x32 pixels");
+  if (pl.ntiles > kMaxTiles)
+    return fail(RPI_ERR_UNSUPPORTED, "images exceed 16384 tiles of " + std::to_string(kTileSize) + "x" +
+                                         std::to_string(kTileSize) + " pixels");
   const bool two_way = !material_mode && (p->flags & RPI_FLAG_TWO_WAY);
   pl.prefix.assign((size_t)kTechs * (2 * nj + 1), 0);
   for (int t = 1; t <= kTechs; ++t) {
@@ -1043,7 +1105,8 @@ struct Timed {
 static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* p, const RunOpts& o, hipStream_t st,
                           std::vector<Timed>* evs, std::vector<uint32_t>* rec_out) {
   const int nj = (int)pl.jobs.size();
-  if (!o.accumulate) launch_zero_images(w.jobs, nj, st);
+  const bool per_tech = (p->flags & RPI_FLAG_PER_TECHNIQUE) != 0;
+  if (!o.accumulate || per_tech) launch_zero_images(w.jobs, nj, !o.accumulate, st);
   WalkArgs A;
   std::memset(&A, 0, sizeof A);
   A.jobs = w.jobs;
@@ -1061,6 +1124,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
   A.alpha_min = p->alpha_min;
   A.d_min = p->d_min;
   A.jac_max = p->jac_max;
+  A.no_mapping = (p->flags & RPI_FLAG_NO_MAPPING) ? 1 : 0;
   A.count_work = o.count_work ? 1 : 0;
   A.keep_records = o.keep ? 1 : 0;
   const bool t8 = (p->strategy_mask & 0x80u) && p->proposal;
@@ -1095,6 +1159,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
   sa.ntiles = pl.ntiles;
   sa.nblk = kSplatBlocks;
   sa.ts = pl.ts;
+  sa.tech = 0;
   const int wblocks = device_cus() * o.tu.walk_bpc;
   const int cblocks = device_cus() * o.tu.conn_bpc;
   const int R = pl.Q / kItem;
@@ -1147,6 +1212,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       }
       r = timed(kKidConnect, [&] { launch_connect(As, cblocks, st); });
       if (r) return r;
+      sa.tech = per_tech ? t : 0;
       r = timed(kKidSplat, [&] { launch_splat(sa, st); });
       if (r) return r;
       if (o.keep && rec_out) {
@@ -1178,6 +1244,8 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       }
     }
   }
+  // the total of the technique images, added in technique order
+  if (per_tech) launch_sum_technique_images(w.jobs, nj, o.accumulate, st);
   hipError_t le = hipGetLastError();
   if (le != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
   return RPI_OK;
@@ -1232,7 +1300,7 @@ static rpi_status run_jobs(const rpi_scene* s, const std::vector<JobSpec>& js, b
   o.tu = tu;
   Ws w;
   const bool t8 = (p->strategy_mask & 0x80u) && p->proposal;
-  rc = ws_alloc(w, pl.Q, p->max_depth, pl.pair_cap, pl.ntiles, (int)pl.jobs.size(), o.keep, t8, st, true);
+  rc = ws_alloc(s, w, pl.Q, p->max_depth, pl.pair_cap, pl.ntiles, (int)pl.jobs.size(), o.keep, t8, st, true);
   if (rc) return rc;
   rc = upload_plan(pl, w, st);
   if (rc) {
@@ -1291,6 +1359,8 @@ extern "C" rpi_status rpi_render_residual(const rpi_scene* s, const rpi_edit* e,
   rpi_status rc = check_params(s, p);
   if (rc) return rc;
   if (p->d_train_records && !stats) return fail(RPI_ERR_INVALID_ARG, "training-record collection needs stats");
+  if ((p->flags & RPI_FLAG_NO_MAPPING) && e->kind == RPI_EDIT_MATERIAL)
+    return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING applies to motion edits only");
   hipStream_t st = (hipStream_t)stream;
   JobSpec j;
   std::memcpy(j.pose_old, e->pose_old, sizeof j.pose_old);
@@ -1300,6 +1370,7 @@ extern "C" rpi_status rpi_render_residual(const rpi_scene* s, const rpi_edit* e,
   j.W = s->W;
   j.H = s->H;
   j.out = out;
+  j.tech = (p->flags & RPI_FLAG_PER_TECHNIQUE) ? p->d_technique_images : nullptr;
   std::vector<uint32_t> recs;
   rpi_render_params q = *p;
   if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);
@@ -1322,28 +1393,55 @@ extern "C" rpi_status rpi_get_records(const rpi_scene* s, void* host_out, int64_
   return RPI_OK;
 }
 
-extern "C" rpi_status rpi_render_frame(const rpi_scene* s, const rpi_edit* e, int32_t which, const rpi_render_params* p,
-                                       float* out, void* stream) {
+static rpi_status frame_common(const rpi_scene* s, const rpi_render_params* p, float* out, FrameArgs& A) {
   if (!s || !out) return fail(RPI_ERR_INVALID_ARG, "null argument");
-  if (which != 1 && which != 2) return fail(RPI_ERR_INVALID_ARG, "which must be 1 (old) or 2 (new)");
   if (!p || p->spp <= 0 || p->max_depth < 2 || p->max_depth > 7) return fail(RPI_ERR_INVALID_ARG, "bad params");
   const int64_t N = (int64_t)p->spp * s->W * s->H;
-  FrameArgs A;
+  if (N > 0xffffffffLL) return fail(RPI_ERR_UNSUPPORTED, "more than 2^32 samples per stream");
+  const int64_t e = p->sample_end < 0 ? N : p->sample_end;
+  if (p->sample_begin < 0 || e > N || p->sample_begin > e) return fail(RPI_ERR_INVALID_ARG, "bad sample range");
   std::memset(&A, 0, sizeof A);
   A.S = s->dev;
-  const float* pose = (e && which == 2) ? e->pose_new : kIdentity;
-  const Material m = (e && which == 2) ? e->new_mat : s->obj_mat;
-  A.F = make_frame(s, pose, pose, m, false);
   A.image = out;
   A.k0 = (uint32_t)p->seed;
   A.k1 = (uint32_t)(p->seed >> 32);
   A.job = p->job;
-  A.dir = which == 2 ? 0 : 1;
   A.depth = p->max_depth;
   A.spp = p->spp;
   A.accumulate = (p->flags & RPI_FLAG_ACCUMULATE) ? 1 : 0;
   A.s0 = p->sample_begin;
-  A.s1 = p->sample_end < 0 ? N : p->sample_end;
+  A.s1 = e;
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_render_frame(const rpi_scene* s, const rpi_edit* e, int32_t which, const rpi_render_params* p,
+                                       float* out, void* stream) {
+  if (which != 0 && which != 1) return fail(RPI_ERR_INVALID_ARG, "which must be 0 (old frame) or 1 (new frame)");
+  FrameArgs A;
+  rpi_status rc = frame_common(s, p, out, A);
+  if (rc) return rc;
+  const float* pose = (e && which == 1) ? e->pose_new : kIdentity;
+  const Material m = (e && which == 1) ? e->new_mat : s->obj_mat;
+  A.F = make_frame(s, pose, pose, m, false);
+  A.dir = which == 1 ? 0 : 1;  // the residual's direction index of that frame
+  A.mode = 0;
+  launch_frame(A, (hipStream_t)stream);
+  hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_render_frame_difference(const rpi_scene* s, const rpi_edit* e, int32_t correlated,
+                                                  const rpi_render_params* p, float* out, void* stream) {
+  if (!e) return fail(RPI_ERR_INVALID_ARG, "null edit");
+  if (correlated != 0 && correlated != 1) return fail(RPI_ERR_INVALID_ARG, "correlated must be 0 or 1");
+  FrameArgs A;
+  rpi_status rc = frame_common(s, p, out, A);
+  if (rc) return rc;
+  A.F = make_frame(s, e->pose_new, e->pose_new, e->new_mat, false);
+  A.F2 = make_frame(s, kIdentity, kIdentity, s->obj_mat, false);
+  A.dir = 0;
+  A.mode = correlated ? 1 : 2;
   launch_frame(A, (hipStream_t)stream);
   hipError_t le = hipGetLastError();
   if (le != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
@@ -1417,10 +1515,12 @@ extern "C" rpi_status rpi_autotune(rpi_scene* s, const rpi_edit* e, const rpi_re
   j.W = s->W;
   j.H = s->H;
   void* tmp = nullptr;
-  HIP_OK(hipMalloc(&tmp, (size_t)s->W * s->H * 3 * sizeof(float)));
+  rc = dev_alloc(s, (size_t)s->W * s->H * 3 * sizeof(float), (hipStream_t)stream, true, &tmp);
+  if (rc) return rc;
   j.out = (float*)tmp;
+  j.tech = nullptr;
   rc = autotune_job(s, j, e->kind == RPI_EDIT_MATERIAL, p, (hipStream_t)stream, out);
-  (void)hipFree(tmp);
+  dev_free(s, tmp, (hipStream_t)stream, true);
   return rc;
 }
 
@@ -1456,7 +1556,7 @@ static void destroy_batch_cache(BatchCache* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->staged) (void)hipEventDestroy(c->staged);
   if (c->pinned) (void)hipHostFree(c->pinned);
-  if (c->ws.mem) (void)hipFree(c->ws.mem);
+  ws_free(c->ws, nullptr);
   delete c;
 }
 
@@ -1464,7 +1564,7 @@ static bool same_params(const rpi_render_params& a, const rpi_render_params& b) 
   return a.spp == b.spp && a.max_depth == b.max_depth && a.seed == b.seed && a.strategy_mask == b.strategy_mask &&
          a.flags == b.flags && a.alpha_min == b.alpha_min && a.d_min == b.d_min && a.jac_max == b.jac_max &&
          a.c_weight == b.c_weight && a.sample_begin == b.sample_begin && a.sample_end == b.sample_end &&
-         a.queue_cap == b.queue_cap && a.job == b.job && a.proposal == b.proposal;
+         a.queue_cap == b.queue_cap && a.job == b.job && a.proposal == b.proposal && a.tile == b.tile;
 }
 
 extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_job* jobs, int32_t n,
@@ -1476,8 +1576,12 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
       ((p->strategy_mask & 0x80u) && !p->proposal))
     return fail(RPI_ERR_INVALID_ARG, "bad params");
   if (p->d_train_records) return fail(RPI_ERR_UNSUPPORTED, "training-record collection is not available for batches");
-  if (p->flags & (RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_TIME_KERNELS))
-    return fail(RPI_ERR_UNSUPPORTED, "records, work counting and kernel timing are not available for batches");
+  if (p->flags & (RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_TIME_KERNELS | RPI_FLAG_PER_TECHNIQUE))
+    return fail(RPI_ERR_UNSUPPORTED,
+                "records, work counting, kernel timing and per-technique images are not available for batches");
+  if (p->tile != 0 && p->tile != 16 && p->tile != 32) return fail(RPI_ERR_INVALID_ARG, "tile must be 0, 16 or 32");
+  if ((p->flags & RPI_FLAG_NO_MAPPING) && !(p->flags & RPI_FLAG_TWO_WAY))
+    return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING needs RPI_FLAG_TWO_WAY");
   hipStream_t st = (hipStream_t)stream;
   rpi_render_params q = *p;
   if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);
@@ -1521,7 +1625,7 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
     c->params = q;
     rpi_status rc = make_plan(s, js, false, &q, scene_tuning(s, &q), c->plan);
     if (!rc)
-      rc = ws_alloc(c->ws, c->plan.Q, q.max_depth, c->plan.pair_cap, c->plan.ntiles, n, false,
+      rc = ws_alloc(s, c->ws, c->plan.Q, q.max_depth, c->plan.pair_cap, c->plan.ntiles, n, false,
                     (q.strategy_mask & 0x80u) && q.proposal, st, false);
     if (rc) {
       destroy_batch_cache(c);

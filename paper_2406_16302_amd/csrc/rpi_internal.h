@@ -161,6 +161,7 @@ struct DevJob {
   DevScene S;
   DevFrame F[2];
   float* image;
+  float* tech_images;  // per-technique images (8 x W x H x 3) or null
   int64_t s0, s1;
   float inv_n;      // 1 / (spp * W * H)
   int32_t tile0;    // first tile of this job in the batch-wide tile index space
@@ -226,6 +227,7 @@ struct WalkArgs {
   uint32_t mask;
   float cweight;
   float alpha_min, d_min, jac_max;
+  int32_t no_mapping;          // every path rejected (the path-mapping ablation)
   int32_t count_work;
   int32_t keep_records;
   MlpDev mlp;                  // technique (8) and its MIS term (mask bit 7)
@@ -252,14 +254,17 @@ struct SplatArgs {
   float4* binned;     // [cap]
   int ntiles, nblk;
   int ts;             // tile edge in pixels: 16 or 32
+  int tech;           // 0: splat into the job's image; t: into its technique image t-1
 };
 
 struct FrameArgs {
   DevScene S;
   DevFrame F;
+  DevFrame F2;  // mode 1, 2: the frame subtracted
   float* image;
   uint32_t k0, k1, job;
   int dir, depth, spp, accumulate;
+  int mode;     // 0 frame F; 1 F - F2 on the same streams; 2 F - F2 on independent streams
   int64_t s0, s1;
   DevStats* stats;
 };
@@ -269,7 +274,10 @@ void launch_walk(const WalkArgs& A, int blocks, hipStream_t st);        // start
 void launch_walk_tasks(const WalkArgs& A, int blocks, hipStream_t st);  // walk phase (over the task queue)
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st);
 void launch_sort_pairs(const WalkArgs& A, hipStream_t st);
-void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st);
+// zero the jobs' images (if `images`) and their technique images (if any)
+void launch_zero_images(const DevJob* jobs, int njobs, bool images, hipStream_t st);
+// image = (accumulate ? image : 0) + technique image 1 + ... + technique image 8
+void launch_sum_technique_images(const DevJob* jobs, int njobs, bool accumulate, hipStream_t st);
 void launch_splat(const SplatArgs& a, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
 void launch_zero_f32(float* p, int64_t n, hipStream_t st);

@@ -1416,6 +1416,7 @@ struct CCtx {
   int job;
   const MlpDev* mlp;  // training-record input normalisation (collection on), else null
   int train_weighting;
+  int no_mapping;     // the path-mapping ablation: every pair rejected
 };
 
 // q8a, q8b: the proposal's densities at x_1..x_4 and x_5 (technique (8) in the mask).
@@ -1685,7 +1686,9 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
     PV y = v[0];
     int istar = 0;
     const DevFrame& Fp = A.Fp;
-    if (k <= 2) {
+    if (A.no_mapping) {
+      rej = 9;  // the path-mapping ablation: every path keeps its own frame's term
+    } else if (k <= 2) {
       rej = 1;
     } else if (A.F.same_pose) {
 #pragma unroll
@@ -1847,7 +1850,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_ker
       const int dir = jd & 1;
       const CCtx C{J.S, J.F[dir], J.F[1 - dir], A.W, A.tech, A.material_mode, A.mask, dir ? -1.0f : 1.0f,
                    A.cweight, J.inv_n, A.alpha_min, A.d_min, A.jac_max, jd >> 1, A.train ? &A.mlp : nullptr,
-                   A.train_weighting};
+                   A.train_weighting, A.no_mapping};
       const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
       const float4 q8a = A.W.t8q ? A.W.t8q[2 * (size_t)idx] : z4, q8b = A.W.t8q ? A.W.t8q[2 * (size_t)idx + 1] : z4;
       float4 rec;
@@ -1861,7 +1864,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_ker
         A.W.rec_keys[idx] = (uint32_t)dir | ((uint32_t)A.tech << 1) | (pr << 8);
         A.W.rec_sample[idx] = (uint32_t)(J.s0 + (g - A.item_prefix[jd]) * kItem + s % kItem);
       }
-      if (A.stats && reason <= 6) atomicAdd(&cnt[reason], 1ull);
+      if (A.stats && (reason <= 6 || reason == 9)) atomicAdd(&cnt[reason == 9 ? 7 : reason], 1ull);
     }
     if (A.train) {
       const int c = tr.weight > 0.0f ? 1 : 0;
@@ -1879,11 +1882,11 @@ __global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_ker
     }
   }
   __syncthreads();
-  if (A.stats && threadIdx.x < 7) {
+  if (A.stats && threadIdx.x < 8) {
     const unsigned long long c = cnt[threadIdx.x];
     if (c) {
       if (threadIdx.x == 0) atomicAdd(&A.stats->accepted, c);
-      else atomicAdd(&A.stats->rejected[threadIdx.x], c);
+      else atomicAdd(&A.stats->rejected[threadIdx.x == 7 ? 0 : threadIdx.x], c);
       atomicAdd(&A.stats->paths, c);
       atomicAdd(&A.stats->by_tech[A.tech], c);
     }
@@ -2097,10 +2100,11 @@ __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
     const DevJob& J = a.jobs[a.tile_job[t]];
     const int lt = t - J.tile0;
     const int tx = lt % J.tilesx, ty = lt / J.tilesx;
+    float* img = a.tech ? J.tech_images + (size_t)(a.tech - 1) * J.W * J.H * 3 : J.image;
     for (int l = threadIdx.x; l < tp; l += 256) {
       const int px = tx * a.ts + (l % a.ts), py = ty * a.ts + (l / a.ts);
       if (px < J.W && py < J.H) {
-        float* o = J.image + 3 * ((size_t)py * J.W + px);
+        float* o = img + 3 * ((size_t)py * J.W + px);
         if (shared) {
           unsafeAtomicAdd(o + 0, acc[3 * l]);  // the hardware float add (device memory)
           unsafeAtomicAdd(o + 1, acc[3 * l + 1]);
@@ -2116,102 +2120,143 @@ __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
   }
 }
 
-__global__ __launch_bounds__(256) void zero_images(const DevJob* jobs, int njobs) {
+__global__ __launch_bounds__(256) void zero_images(const DevJob* jobs, int njobs, int images) {
   for (int j = 0; j < njobs; ++j) {
     const int64_t n = (int64_t)jobs[j].W * jobs[j].H * 3;
     float* p = jobs[j].image;
-    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0f;
+    if (images)
+      for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0f;
+    float* q = jobs[j].tech_images;
+    if (q)
+      for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < kTechs * n; i += (int64_t)gridDim.x * 256) q[i] = 0.0f;
+  }
+}
+
+// The total of the technique images, pixel by pixel in technique order, so
+// that it equals their sum taken in that order bit for bit.
+__global__ __launch_bounds__(256) void sum_technique_images(const DevJob* jobs, int njobs, int accumulate) {
+  for (int j = 0; j < njobs; ++j) {
+    const int64_t n = (int64_t)jobs[j].W * jobs[j].H * 3;
+    float* p = jobs[j].image;
+    const float* q = jobs[j].tech_images;
+    if (!q) continue;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+      float acc = accumulate ? p[i] : 0.0f;
+#pragma unroll
+      for (int t = 0; t < kTechs; ++t) acc += q[(size_t)t * n + i];
+      p[i] = acc;
+    }
   }
 }
 
 // ------------------------------------------------------------------ frames
-// One lane per pixel; samples s = pixel + m * P (the residual technique (7)
-// uses the same pixel-of-sample rule).
-__global__ __launch_bounds__(kTraceBlock) void frame_kernel(FrameArgs A) {
-  __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
+// One camera sample of plain path tracing in frame F (Sec. 3.1): next-event
+// estimation at every vertex and emission seen directly from the camera.
+// The Philox stream is that of sample smp of technique 7 in direction dir.
+DEV vec3 frame_sample(const FrameArgs& A, const DevFrame& F, int dir, int pixel, int64_t smp, int* stk, WorkCount& wc) {
   const DevScene& S = A.S;
   const DevCamera& C = S.cam;
+  const int P = C.W * C.H;
+  const float Pf = (float)P;
+  const float invN = 1.0f / ((float)A.spp * Pf);
+  vec3 sum = v3(0, 0, 0);
+  Rng g{A.k0, A.k1, (uint32_t)smp, (uint32_t)dir << 23, A.job};
+  float u[4];
+  draw(g, 0, 0, 0, u);
+  const vec3 w = camera_dir(C, pixel, u[0], u[1]);
+  const Hit h = closest<false>(S, F, C.eye, w, stk, wc);
+  if (!h.ok) {
+    if (S.p_env > 0.0f && raster(C, C.eye + w) >= 0) sum = sum + S.env * (Pf * invN);
+    return sum;
+  }
+  vec3 p, n;
+  uint32_t md;
+  hit_vertex(S, F.pose, h, C.eye, w, p, n, md);
+  const int pix1 = raster(C, p);
+  if (pix1 < 0) return sum;
+  if (is_emitter(S, md)) {
+    if (dot(n, C.eye - p) > 0.0f) {
+      const float* em = S.mats + 8 * (md & ~kDynBit) + 5;
+      sum = sum + v3(em[0], em[1], em[2]) * (Pf * invN);
+    }
+    return sum;
+  }
+  // throughput f / p up to the current vertex (camera factor / camera pdf = P)
+  vec3 beta = v3(Pf, Pf, Pf);
+  vec3 prev = C.eye;
+  for (int b = 0; b + 2 <= A.depth; ++b) {
+    const Material mt = vmat(S, F, md);
+    draw(g, 0, b + 1, 1, u);
+    LightEnd E;
+    if (sample_light(S, u, E)) {
+      const bool face = E.env ? true : dot(E.n, p - E.p) > 0.0f;
+      const vec3 lp = E.env ? p + E.n : E.p;
+      if (face && same_side(n, p, prev, lp) &&
+          edge_visible<false>(S, F, end_surf(p, n), end_light(E), stk, wc, RAY_SHADOW)) {
+        const vec3 wl = E.env ? E.n : unit(E.p - p);
+        const vec3 rho = bsdf_eval(mt, n, unit(prev - p), wl);
+        float gg;
+        if (E.env) {
+          gg = fabsf(dot(n, wl));
+        } else {
+          const vec3 d = E.p - p;
+          gg = fabsf(dot(n, wl)) * fabsf(dot(E.n, wl)) / len2(d);
+        }
+        const vec3 c = vmul(vmul(beta, rho), light_Le(S, E)) * (gg / light_pdf(S, E.env));
+        sum = sum + c * invN;
+      }
+    }
+    if (b + 3 > A.depth) break;
+    draw(g, 0, b + 1, 0, u);
+    vec3 wo;
+    if (!bsdf_sample(mt, n, unit(prev - p), u[0], u[1], wo)) break;
+    const vec3 o = spawn_dir(S, p, n, wo);
+    const Hit h2 = closest<false>(S, F, o, wo, stk, wc);
+    if (!h2.ok) break;
+    vec3 q, qn;
+    uint32_t qmd;
+    hit_vertex(S, F.pose, h2, o, wo, q, qn, qmd);
+    if (is_emitter(S, qmd)) break;
+    // f/p update: rho G / (pdf_w * cos_q / r^2 from the offset origin)
+    const vec3 wi = unit(prev - p);
+    const vec3 rho = bsdf_eval(mt, n, wi, unit(q - p));
+    const vec3 d = q - p;
+    const vec3 du = unit(d);
+    const float G = fabsf(dot(n, du)) * fabsf(dot(qn, du)) / len2(d);
+    const vec3 dq = q - o;
+    const float pa = bsdf_pdf(mt, n, wi, wo) * fabsf(dot(qn, unit(dq))) / len2(dq);
+    if (!(pa > 0.0f)) break;  // a direction of zero density (rounding at grazing angles) ends the walk
+    beta = vmul(beta, rho) * (G / pa);
+    prev = p;
+    p = q;
+    n = qn;
+    md = qmd;
+  }
+  return sum;
+}
+
+// One lane per pixel; samples s = pixel + m * P (the residual technique (7)
+// uses the same pixel-of-sample rule).  mode 0: frame F in stream direction
+// A.dir; 1: the difference F - F2 with the same random numbers in both
+// frames (correlated path tracing); 2: F - F2 from independent streams
+// (direction 0 for F, 1 for F2: path tracing each frame from scratch).
+__global__ __launch_bounds__(kTraceBlock) void frame_kernel(FrameArgs A) {
+  __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
+  const DevCamera& C = A.S.cam;
   const int P = C.W * C.H;
   const int pixel = blockIdx.x * kTraceBlock + threadIdx.x;
   if (pixel >= P) return;
   WorkCount wc{};
   vec3 sum = v3(0, 0, 0);
-  const float Pf = (float)P;
-  const float invN = 1.0f / ((float)A.spp * Pf);
   for (int m = 0; m < A.spp; ++m) {
     const int64_t smp = (int64_t)pixel + (int64_t)m * P;
     if (smp < A.s0 || smp >= A.s1) continue;
-    Rng g{A.k0, A.k1, (uint32_t)smp, (uint32_t)A.dir << 23, A.job};
-    float u[4];
-    draw(g, 0, 0, 0, u);
-    const vec3 w = camera_dir(C, pixel, u[0], u[1]);
-    const Hit h = closest<false>(S, A.F, C.eye, w, stk, wc);
-    if (!h.ok) {
-      if (S.p_env > 0.0f && raster(C, C.eye + w) >= 0) sum = sum + S.env * (Pf * invN);
-      continue;
-    }
-    vec3 p, n;
-    uint32_t md;
-    hit_vertex(S, A.F.pose, h, C.eye, w, p, n, md);
-    const int pix1 = raster(C, p);
-    if (pix1 < 0) continue;
-    if (is_emitter(S, md)) {
-      if (dot(n, C.eye - p) > 0.0f) {
-        const float* em = S.mats + 8 * (md & ~kDynBit) + 5;
-        sum = sum + v3(em[0], em[1], em[2]) * (Pf * invN);
-      }
-      continue;
-    }
-    // throughput f / p up to the current vertex (camera factor / camera pdf = P)
-    vec3 beta = v3(Pf, Pf, Pf);
-    vec3 prev = C.eye;
-    for (int b = 0; b + 2 <= A.depth; ++b) {
-      const Material mt = vmat(S, A.F, md);
-      draw(g, 0, b + 1, 1, u);
-      LightEnd E;
-      if (sample_light(S, u, E)) {
-        const bool face = E.env ? true : dot(E.n, p - E.p) > 0.0f;
-        const vec3 lp = E.env ? p + E.n : E.p;
-        if (face && same_side(n, p, prev, lp) &&
-            edge_visible<false>(S, A.F, end_surf(p, n), end_light(E), stk, wc, RAY_SHADOW)) {
-          const vec3 wl = E.env ? E.n : unit(E.p - p);
-          const vec3 rho = bsdf_eval(mt, n, unit(prev - p), wl);
-          float gg;
-          if (E.env) {
-            gg = fabsf(dot(n, wl));
-          } else {
-            const vec3 d = E.p - p;
-            gg = fabsf(dot(n, wl)) * fabsf(dot(E.n, wl)) / len2(d);
-          }
-          const vec3 c = vmul(vmul(beta, rho), light_Le(S, E)) * (gg / light_pdf(S, E.env));
-          sum = sum + c * invN;
-        }
-      }
-      if (b + 3 > A.depth) break;
-      draw(g, 0, b + 1, 0, u);
-      vec3 wo;
-      if (!bsdf_sample(mt, n, unit(prev - p), u[0], u[1], wo)) break;
-      const vec3 o = spawn_dir(S, p, n, wo);
-      const Hit h2 = closest<false>(S, A.F, o, wo, stk, wc);
-      if (!h2.ok) break;
-      vec3 q, qn;
-      uint32_t qmd;
-      hit_vertex(S, A.F.pose, h2, o, wo, q, qn, qmd);
-      if (is_emitter(S, qmd)) break;
-      // f/p update: rho G / (pdf_w * cos_q / r^2 from the offset origin)
-      const vec3 wi = unit(prev - p);
-      const vec3 rho = bsdf_eval(mt, n, wi, unit(q - p));
-      const vec3 d = q - p;
-      const vec3 du = unit(d);
-      const float G = fabsf(dot(n, du)) * fabsf(dot(qn, du)) / len2(d);
-      const vec3 dq = q - o;
-      const float pa = bsdf_pdf(mt, n, wi, wo) * fabsf(dot(qn, unit(dq))) / len2(dq);
-      if (!(pa > 0.0f)) break;  // a direction of zero density (rounding at grazing angles) ends the walk
-      beta = vmul(beta, rho) * (G / pa);
-      prev = p;
-      p = q;
-      n = qn;
-      md = qmd;
+    if (A.mode == 0) {
+      sum = sum + frame_sample(A, A.F, A.dir, pixel, smp, stk, wc);
+    } else {
+      const vec3 a = frame_sample(A, A.F, 0, pixel, smp, stk, wc);
+      const vec3 b = frame_sample(A, A.F2, A.mode == 1 ? 0 : 1, pixel, smp, stk, wc);
+      sum = sum + (a - b);
     }
   }
   float* o = A.image + 3 * (size_t)pixel;
@@ -2270,8 +2315,11 @@ void launch_walk_tasks(const WalkArgs& A, int blocks, hipStream_t st) {
   if (A.count_work) launch_walk_task_cw<true>(A, blocks, st);
   else launch_walk_task_cw<false>(A, blocks, st);
 }
-void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st) {
-  hipLaunchKernelGGL(zero_images, dim3(1024), dim3(256), 0, st, jobs, njobs);
+void launch_sum_technique_images(const DevJob* jobs, int njobs, bool accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(sum_technique_images, dim3(1024), dim3(256), 0, st, jobs, njobs, accumulate ? 1 : 0);
+}
+void launch_zero_images(const DevJob* jobs, int njobs, bool images, hipStream_t st) {
+  hipLaunchKernelGGL(zero_images, dim3(1024), dim3(256), 0, st, jobs, njobs, images ? 1 : 0);
 }
 void launch_t8_start(const WalkArgs& A, int blocks, hipStream_t st) {
   hipLaunchKernelGGL(t8_start_kernel, dim3(blocks), dim3(kTraceBlock), 0, st, A);

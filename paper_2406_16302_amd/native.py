@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "librpi.so")
 RPI_OK = 0
 EDIT_RIGID, EDIT_MATERIAL = 0, 1
 FLAG_TWO_WAY, FLAG_ACCUMULATE, FLAG_COUNT_WORK, FLAG_RECORDS, FLAG_TIME_KERNELS = 1, 2, 4, 8, 16
+FLAG_NO_MAPPING, FLAG_PER_TECHNIQUE = 32, 64
+FRAME_OLD, FRAME_NEW = 0, 1
 PROPOSAL_NPARAM, TRAIN_RECORD_FLOATS = 11368, 10
 
 
@@ -44,16 +46,24 @@ class Params(C.Structure):
                 ("d_min", C.c_float), ("jac_max", C.c_float), ("c_weight", C.c_float),
                 ("sample_begin", C.c_int64), ("sample_end", C.c_int64), ("queue_cap", C.c_int32),
                 ("job", C.c_uint32), ("proposal", C.c_void_p), ("d_train_records", C.c_void_p),
-                ("train_capacity", C.c_int64), ("train_weighting", C.c_int32)]
+                ("train_capacity", C.c_int64), ("train_weighting", C.c_int32),
+                ("d_technique_images", C.c_void_p), ("tile", C.c_int32)]
 
     @staticmethod
     def make(spp, depth, seed, mask=0x7F, flags=FLAG_TWO_WAY, alpha_min=0.2, d_min=-1.0, jac_max=10.0,
              c_weight=0.5, sample_begin=0, sample_end=-1, queue_cap=0, job=0, proposal=None, train_records=None,
-             train_weighting=0):
+             train_weighting=0, technique_images=None, tile=0):
         """proposal: a Proposal (technique 8 with mask bit 7); train_records: a
-        float32 device tensor [cap, 10] receiving technique-3 training records."""
+        float32 device tensor [cap, 10] receiving technique-3 training records;
+        technique_images: a float32 device tensor [8, H, W, 3] (sets
+        FLAG_PER_TECHNIQUE)."""
         p = Params(spp, depth, seed, mask, flags, alpha_min, d_min, jac_max, c_weight, sample_begin,
                    sample_end, queue_cap, job)
+        p.tile = int(tile)
+        if technique_images is not None:
+            p.d_technique_images = _devptr(technique_images, technique_images.numel()).value
+            p._technique_ref = technique_images
+            p.flags |= FLAG_PER_TECHNIQUE
         if proposal is not None:
             p.proposal = proposal.h.value
             p._proposal_ref = proposal
@@ -93,6 +103,33 @@ class TrainParams(C.Structure):
                 ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("allocate", _ALLOC_FN), ("deallocate", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+def torch_allocator():
+    """An rpi_allocator backed by PyTorch's caching allocator (memory
+    handed back is reused in stream order, as the library requires)."""
+    import torch
+
+    def alloc(ctx, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:  # out of memory: the library reports OUT_OF_MEMORY
+            return None
+
+    def free(ctx, ptr, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = Allocator(_ALLOC_FN(alloc), _FREE_FN(free), None)
+    a._keep = (alloc, free)
+    return a
+
+
 class Job(C.Structure):
     _fields_ = [("pose_old", C.c_float * 12), ("pose_new", C.c_float * 12), ("width", C.c_int32),
                 ("height", C.c_int32), ("d_out", C.c_void_p)]
@@ -109,12 +146,14 @@ def load_library():
                                "python paper_2406_16302_amd/build.py)")
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
-        L.rpi_build_scene.argtypes = [C.POINTER(SceneDesc), C.POINTER(vp)]
+        L.rpi_build_scene.argtypes = [C.POINTER(SceneDesc), C.POINTER(Allocator), C.POINTER(vp)]
+        L.rpi_sync_status.argtypes = [vp]
         L.rpi_destroy_scene.argtypes = [vp]
         L.rpi_apply_edit.argtypes = [vp, C.POINTER(EditDesc), C.POINTER(vp)]
         L.rpi_destroy_edit.argtypes = [vp]
         L.rpi_render_residual.argtypes = [vp, vp, C.POINTER(Params), vp, C.POINTER(Stats), vp]
         L.rpi_render_frame.argtypes = [vp, vp, C.c_int32, C.POINTER(Params), vp, vp]
+        L.rpi_render_frame_difference.argtypes = [vp, vp, C.c_int32, C.POINTER(Params), vp, vp]
         L.rpi_render_residual_batch.argtypes = [vp, C.POINTER(Job), C.c_int32, C.POINTER(Params),
                                                 C.POINTER(Stats), vp]
         L.rpi_get_records.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
@@ -129,7 +168,7 @@ def load_library():
         L.rpi_proposal_train.argtypes = [vp, vp, C.c_int64, C.POINTER(TrainParams), vp, vp]
         L.rpi_last_error.restype = C.c_char_p
         L.rpi_version.restype = C.c_char_p
-        for f in ("rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
+        for f in ("rpi_render_frame_difference", "rpi_sync_status", "rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
                   "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records",
                   "rpi_autotune", "rpi_set_tuning", "rpi_proposal_create", "rpi_proposal_destroy", "rpi_proposal_set_weights",
                   "rpi_proposal_get_weights", "rpi_proposal_forward", "rpi_proposal_loss_grad",
@@ -167,9 +206,11 @@ def _devptr(t, n):
 
 
 class Scene:
-    """rpi_build_scene over a scenes.Scene (host arrays copied by the library)."""
+    """rpi_build_scene over a scenes.Scene (host arrays copied by the library).
+    allocator: None (hipMalloc / hipMallocAsync), "torch" (PyTorch's caching
+    allocator) or an Allocator."""
 
-    def __init__(self, sc):
+    def __init__(self, sc, allocator=None):
         L = load_library()
         self.src = sc
         arrs = [np.ascontiguousarray(sc.positions, np.float32), np.ascontiguousarray(sc.indices, np.int32),
@@ -179,8 +220,11 @@ class Scene:
         pos, idx, tm, to, mats, env, cam = arrs
         d = SceneDesc(_fp(pos), len(pos), _fp(idx, C.c_int32), len(idx), _fp(tm, C.c_int32), _fp(to, C.c_int32),
                       _fp(mats), len(mats), _fp(env), _fp(cam))
+        if allocator == "torch":
+            allocator = torch_allocator()
+        self.allocator = allocator  # kept alive as long as the scene
         h = C.c_void_p()
-        _check(L.rpi_build_scene(C.byref(d), C.byref(h)))
+        _check(L.rpi_build_scene(C.byref(d), C.byref(allocator) if allocator is not None else None, C.byref(h)))
         self.h = h
         self.width, self.height = sc.width, sc.height
 
@@ -233,9 +277,23 @@ def render_residual(scene: Scene, edit: Edit, params: Params, out, stats=False, 
 
 
 def render_frame(scene: Scene, edit: Edit | None, which: int, params: Params, out, stream=None):
+    """Plain path tracing of one frame: which = FRAME_OLD (0) or FRAME_NEW (1)."""
     L = load_library()
     _check(L.rpi_render_frame(scene.h, edit.h if edit is not None else None, int(which), C.byref(params),
                               _devptr(out, scene.width * scene.height * 3), _stream(stream)))
+
+
+def render_frame_difference(scene: Scene, edit: Edit, correlated: bool, params: Params, out, stream=None):
+    """I_new - I_old by path tracing: correlated (the same random numbers in
+    both frames) or from scratch (independent streams)."""
+    L = load_library()
+    _check(L.rpi_render_frame_difference(scene.h, edit.h, 1 if correlated else 0, C.byref(params),
+                                         _devptr(out, scene.width * scene.height * 3), _stream(stream)))
+
+
+def sync_status(stream=None):
+    """rpi_sync_status: wait for the stream, raise on a device error."""
+    _check(load_library().rpi_sync_status(_stream(stream)))
 
 
 def autotune(scene: Scene, edit: Edit, params: Params, stream=None):

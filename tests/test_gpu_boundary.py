@@ -1,0 +1,138 @@
+"""The boundary's options through the C ABI on the GPU, against the oracle
+on the same Philox streams: per-technique images (fig. importance_sample),
+path mapping off (fig. ablat_pathmapping), the splat tile edge, PyTorch's
+caching allocator behind the allocator hook, and rpi_sync_status."""
+import numpy as np
+import pytest
+
+from paper_2406_16302_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _render(sc, ed, p):
+    from paper_2406_16302_amd import native
+    out = torch.zeros((sc.height, sc.width, 3), dtype=torch.float32, device="cuda")
+    st = native.render_residual(sc, ed, p, out, stats=True)
+    native.sync_status()
+    return out, st
+
+
+def test_per_technique_images_match_oracle_and_sum_to_total():
+    import oracle
+    from gpu_parity import rel_l2
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_motion(width=32, height=32, depth=5, spp=8)
+    print("cornell_motion 32x32 d5 spp8 per-technique", flush=True)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    timg = torch.full((8, 32, 32, 3), 7.0, dtype=torch.float32, device="cuda")  # overwritten
+    p = native.Params.make(ws.spp, ws.depth, ws.seed, technique_images=timg)
+    out, st = _render(sc, ed, p)
+    t = timg.cpu()
+    # the total is the technique images added in technique order, bit for bit
+    acc = torch.zeros_like(t[0])
+    for k in range(8):
+        acc = acc + t[k]
+    assert torch.equal(acc, out.cpu())
+    assert torch.count_nonzero(t[7]) == 0  # technique 8 did not run
+    o = oracle.residual_for(ws, oracle.OracleScene(ws.scene), threads=8, per_tech=True)
+    assert rel_l2(out.cpu().numpy().astype(np.float64), o["image"]) < 1e-3
+    for k in range(7):
+        ref = o["per_tech"][k]
+        assert np.abs(ref).sum() > 0, k
+        assert rel_l2(t[k].numpy().astype(np.float64), ref) < 1e-3, k
+    # the same call without the flag gives the same total up to float rounding
+    out2, _ = _render(sc, ed, native.Params.make(ws.spp, ws.depth, ws.seed))
+    assert rel_l2(out2.cpu().numpy().astype(np.float64), out.cpu().numpy().astype(np.float64)) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["cornell", "clutter"])
+def test_mapping_off_matches_oracle(name):
+    import oracle
+    from gpu_parity import rel_l2
+    from paper_2406_16302_amd import native
+    if name == "cornell":
+        ws = scenes.cornell_motion(width=32, height=32, depth=5, spp=8)
+    else:
+        ws = scenes.clutter_motion(width=48, height=48, depth=4, spp=4, n_spheres=60)
+    print(name, "mapping off", flush=True)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    p = native.Params.make(ws.spp, ws.depth, ws.seed, flags=native.FLAG_TWO_WAY | native.FLAG_NO_MAPPING)
+    out, st = _render(sc, ed, p)
+    assert st["paths"] > 1000 and st["accepted"] == 0 and st["rejected"][0] == st["paths"]
+    o = oracle.residual_for(ws, oracle.OracleScene(ws.scene), threads=8, no_mapping=True)
+    assert o["stats"]["unmapped"] == o["stats"]["paths"]
+    assert rel_l2(out.cpu().numpy().astype(np.float64), o["image"]) < 1e-3
+    # with the mapping the result differs (correlated pairs are subtracted)
+    with_map, st2 = _render(sc, ed, native.Params.make(ws.spp, ws.depth, ws.seed))
+    assert st2["accepted"] > 0
+    assert rel_l2(with_map.cpu().numpy().astype(np.float64), out.cpu().numpy().astype(np.float64)) > 1e-2
+
+
+def test_mapping_off_is_rejected_where_it_does_not_apply():
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_material(width=16, height=16, depth=4, spp=2)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    out = torch.zeros((16, 16, 3), dtype=torch.float32, device="cuda")
+    for flags in (native.FLAG_NO_MAPPING, native.FLAG_NO_MAPPING | native.FLAG_TWO_WAY):
+        with pytest.raises(native.RpiError) as e:
+            native.render_residual(sc, ed, native.Params.make(2, 4, 1, mask=0x07, flags=flags), out)
+        assert e.value.code == -2
+
+
+def test_tile_edge_only_changes_rounding():
+    from gpu_parity import rel_l2
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_motion(width=40, height=24, depth=4, spp=8)  # ragged tiles at both edges
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    imgs = [_render(sc, ed, native.Params.make(ws.spp, ws.depth, ws.seed, tile=t))[0].cpu().numpy()
+            for t in (16, 32, 0)]
+    assert np.abs(imgs[0]).sum() > 0
+    assert rel_l2(imgs[1].astype(np.float64), imgs[0].astype(np.float64)) < 1e-5
+    assert rel_l2(imgs[2].astype(np.float64), imgs[0].astype(np.float64)) < 1e-5
+    out = torch.zeros((24, 40, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(native.RpiError):
+        native.render_residual(sc, ed, native.Params.make(2, 4, 1, tile=8), out)
+
+
+def test_torch_allocator_backs_the_scene_and_workspace():
+    from gpu_parity import rel_l2
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_motion(width=32, height=32, depth=4, spp=8)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    sc_t = native.Scene(ws.scene, allocator="torch")
+    held = torch.cuda.memory_allocated() - before
+    assert held > 0  # the scene's BVHs and tables live in torch's pool
+    ed_t = native.Edit(sc_t, ws.edit)
+    peak0 = torch.cuda.max_memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    a, st = _render(sc_t, ed_t, native.Params.make(ws.spp, ws.depth, ws.seed, queue_cap=1 << 16))
+    assert torch.cuda.max_memory_allocated() - torch.cuda.memory_allocated() > 1 << 20  # the workspace came from torch
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    b, _ = _render(sc, ed, native.Params.make(ws.spp, ws.depth, ws.seed, queue_cap=1 << 16))
+    assert rel_l2(a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) < 1e-5
+    del ed_t, sc_t
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - before <= 2 * a.numel() * 4 + (1 << 12)
+    del peak0
+
+
+def test_sync_status_reports_ok():
+    from paper_2406_16302_amd import native
+    native.sync_status()
+    s = torch.cuda.Stream()
+    native.sync_status(s)

@@ -59,11 +59,12 @@ def test_frame_matches_oracle():
     ed = native.Edit(sc, ws.edit)
     out = torch.zeros((32, 32, 3), dtype=torch.float32, device="cuda")
     o = oracle.OracleScene(ws.scene)
-    for which in (1, 2):
+    for which in (native.FRAME_OLD, native.FRAME_NEW):
         p = native.Params.make(8, 4, 77)
         native.render_frame(sc, ed, which, p, out)
         torch.cuda.synchronize()
-        ref, _ = o.render_frame(which, 8, 4, 77, pose_new=ws.edit.old_to_new, threads=8)
+        # the oracle numbers the frames 1 (old) and 2 (new)
+        ref, _ = o.render_frame(which + 1, 8, 4, 77, pose_new=ws.edit.old_to_new, threads=8)
         assert rel_l2(out.cpu().numpy().astype(np.float64), ref) < 1e-3
 
 
@@ -120,8 +121,8 @@ def test_motion_residual_matches_frame_difference_at_bench_scene():
         f1 = torch.zeros((128, 128, 3), dtype=torch.float32, device="cuda")
         f2 = torch.zeros_like(f1)
         p = native.Params.make(4096, 5, 80_000 + c)
-        native.render_frame(sc, ed, 1, p, f1)
-        native.render_frame(sc, ed, 2, p, f2)
+        native.render_frame(sc, ed, native.FRAME_OLD, p, f1)
+        native.render_frame(sc, ed, native.FRAME_NEW, p, f2)
         frames.append((f2.double() - f1.double()).sum().item())
     res = []
     for k in range(16):

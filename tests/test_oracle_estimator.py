@@ -149,12 +149,14 @@ def test_mapping_is_an_involution_with_symmetric_rejection(oracle_lib):
 
 # --- unbiasedness against the difference of two independent frames -------------
 
-@pytest.mark.parametrize("kind", ["motion", "material"])
+@pytest.mark.parametrize("kind", ["motion", "material", "motion_no_mapping"])
 def test_residual_converges_to_frame_difference(oracle_lib, kind):
-    if kind == "motion":
+    """motion_no_mapping: the path-mapping ablation (every pair rejected,
+    each frame's dynamic paths with weight 1) is also unbiased."""
+    if kind.startswith("motion"):
         w = scenes.cornell_motion(width=8, height=8, depth=4)
         frame_kw = dict(pose_new=w.edit.old_to_new)
-        res_kw = dict(pose_new=w.edit.old_to_new)
+        res_kw = dict(pose_new=w.edit.old_to_new, no_mapping=kind.endswith("no_mapping"))
     else:
         w = scenes.cornell_material(width=8, height=8, depth=4)
         frame_kw = dict(new_mat=w.edit.new_material)
@@ -164,6 +166,9 @@ def test_residual_converges_to_frame_difference(oracle_lib, kind):
     D, dse = batched(lambda s: o.render_frame(2, 4096, d, s, threads=T, **frame_kw)[0]
                      - o.render_frame(1, 4096, d, s + 777, threads=T, **frame_kw)[0], range(10, 34))
     R, se = batched(lambda s: o.render_residual(256, d, s, threads=T, **res_kw)["image"], range(500, 524))
+    if kind == "motion_no_mapping":
+        st = o.render_residual(16, d, 1, threads=T, **res_kw)["stats"]
+        assert st["paths"] > 0 and st["accepted"] == 0 and st["unmapped"] == st["paths"]
     z, _ = zscores(R, se, D, dse)
     assert (np.abs(z) < 3).mean() > 0.98
     assert np.abs(z).max() < 5.5
@@ -360,3 +365,28 @@ def test_per_technique_images_carry_their_mis_share(sphere_records):
         assert abs(est - direct) < 3 * se + 1e-12 * direct, (t, direct, est, se)
         if t != 7:
             assert 3 * se / direct < 0.15, (t, se / direct)
+
+
+# --- the path-tracing baselines (correlated and from scratch) -----------------
+
+def test_correlated_frames_cancel_off_the_edit_and_lower_the_variance(oracle_lib):
+    """Correlated path tracing (both frames on the same random numbers)
+    cancels exactly wherever a sample's path misses the object in both
+    poses, and so has a far smaller variance than two independent frames;
+    both are unbiased estimates of the same difference."""
+    w = scenes.cornell_motion(width=8, height=8, depth=4)
+    o = oracle_lib.OracleScene(w.scene)
+    kw = dict(pose_new=w.edit.old_to_new, threads=T)
+
+    def diff(seed, correlated):
+        a = o.render_frame(2, 64, 4, seed, stream_dir=0, **kw)[0]
+        b = o.render_frame(1, 64, 4, seed, stream_dir=0 if correlated else 1, **kw)[0]
+        return a - b
+    same = o.render_frame(2, 16, 4, 5, stream_dir=0, pose_new=oracle_lib.IDENTITY, threads=T)[0] - \
+        o.render_frame(1, 16, 4, 5, stream_dir=0, threads=T)[0]
+    assert np.count_nonzero(same) == 0
+    C, cse = batched(lambda s: diff(s, True), range(30, 46))
+    I, ise = batched(lambda s: diff(s, False), range(30, 46))
+    z, _ = zscores(C, cse, I, ise)
+    assert (np.abs(z) < 3).mean() > 0.95
+    assert (cse ** 2).sum() < 0.5 * (ise ** 2).sum()
