@@ -205,6 +205,23 @@ rpi_status rpi_destroy_edit(rpi_edit* edit);
 rpi_status rpi_render_residual(const rpi_scene* scene, const rpi_edit* edit, const rpi_render_params* params,
                                float* d_out, rpi_stats* stats, void* hip_stream);
 
+/* rpi_render_residual for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same estimator, same result up to float rounding (the rounds
+ * are smaller); the call allocates nothing: its workspace is a static device
+ * array of 128 MiB that each GPU the library runs on holds until the process
+ * ends, and rounds are sized to fit it.  The caller still passes the output
+ * (and, with RPI_FLAG_PER_TECHNIQUE, the technique images).  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other threads) race on it and must be serialised by the caller.
+ * The call synchronises hip_stream once before its kernels (the round plan
+ * is copied from host memory); the kernels then run asynchronously.
+ * Errors: as rpi_render_residual; UNSUPPORTED for RPI_FLAG_RECORDS,
+ * RPI_FLAG_COUNT_WORK, RPI_FLAG_TIME_KERNELS, training records, and images
+ * whose smallest round does not fit the array. */
+rpi_status rpi_render_residual_noalloc(const rpi_scene* scene, const rpi_edit* edit, const rpi_render_params* params,
+                                       float* d_out, void* hip_stream);
+
 /* Plain path tracing (next-event estimation, emission seen directly) of one
  * frame (Sec. 3.1, eq. pathIntegral): which = 0 old frame, 1 new frame (edit
  * may be NULL: the scene as given).  Sample s of a stream goes to pixel

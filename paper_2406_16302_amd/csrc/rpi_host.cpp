@@ -903,8 +903,14 @@ struct Ws {
   size_t bytes = 0;
 };
 
-rpi_status ws_alloc(const rpi_scene* s, Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep,
-                    bool t8, hipStream_t st, bool async) {
+// Byte offsets of the workspace parts for rounds of Q samples.
+struct WsLayout {
+  size_t eye, light, start, counts, pairs, pairs2, np, rec, keys, ks, t8, stats, tc, to, cp, hist, bin, jobs, pre, tj,
+      ic, tc2, task, nt, bytes;
+};
+
+static WsLayout ws_layout(int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep, bool t8) {
+  WsLayout L{};
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t o = off;
@@ -912,65 +918,79 @@ rpi_status ws_alloc(const rpi_scene* s, Ws& w, int Q, int depth, int64_t pair_ca
     return o;
   };
   const int nslot = depth;
-  const size_t o_eye = take((size_t)nslot * kEyeFields * Q * sizeof(float4));
-  const size_t o_light = take((size_t)nslot * kLightFields * Q * sizeof(float4));
-  const size_t o_start = take((size_t)kStartFields * Q * sizeof(float4));
-  const size_t o_counts = take((size_t)Q * 4);
-  const size_t o_pairs = take((size_t)pair_cap * 4);
-  const size_t o_pairs2 = take((size_t)pair_cap * 4);
-  const size_t o_np = take(256);
-  const size_t o_rec = take((size_t)pair_cap * sizeof(float4));
-  const size_t o_keys = keep ? take((size_t)pair_cap * 4) : 0;
-  const size_t o_ks = keep ? take((size_t)pair_cap * 4) : 0;
-  const size_t o_t8 = t8 ? take((size_t)pair_cap * 2 * sizeof(float4)) : 0;
-  const size_t o_stats = take(sizeof(DevStats));
-  const size_t o_tc = take((size_t)ntiles * 4);
-  const size_t o_to = take((size_t)(ntiles + 1) * 4);
-  const size_t o_cp = take((size_t)(ntiles + 1) * 4);
-  const size_t o_hist = take((size_t)ntiles * kSplatBlocks * 4);
-  const size_t o_bin = take((size_t)pair_cap * sizeof(float4));
-  const size_t o_jobs = take((size_t)njobs * sizeof(DevJob));
-  const size_t o_pre = take((size_t)kTechs * (2 * njobs + 1) * sizeof(int64_t));
-  const size_t o_tj = take((size_t)ntiles * 4);
-  const size_t o_ic = take(256);
-  const size_t o_tc2 = take(256);
-  const size_t o_task = take((size_t)kTaskFields * Q * sizeof(float4));
-  const size_t o_nt = take(256);
-  w.bytes = off;
-  w.async = async;
-  w.owner = s;
-  rpi_status rc = dev_alloc(s, off, st, async, &w.mem);
-  if (rc) return rc;
-  char* b = (char*)w.mem;
-  w.W.eye = (float4*)(b + o_eye);
-  w.W.light = (float4*)(b + o_light);
-  w.W.start = (float4*)(b + o_start);
-  w.W.counts = (uint32_t*)(b + o_counts);
-  w.W.pairs = (uint32_t*)(b + o_pairs);
-  w.W.pairs2 = (uint32_t*)(b + o_pairs2);
-  w.W.npairs = (uint32_t*)(b + o_np);
-  w.W.records = (float4*)(b + o_rec);
-  w.W.rec_keys = keep ? (uint32_t*)(b + o_keys) : nullptr;
-  w.W.rec_sample = keep ? (uint32_t*)(b + o_ks) : nullptr;
-  w.W.t8q = t8 ? (float4*)(b + o_t8) : nullptr;
-  w.W.task = (float4*)(b + o_task);
-  w.W.ntasks = (uint32_t*)(b + o_nt);
+  L.eye = take((size_t)nslot * kEyeFields * Q * sizeof(float4));
+  L.light = take((size_t)nslot * kLightFields * Q * sizeof(float4));
+  L.start = take((size_t)kStartFields * Q * sizeof(float4));
+  L.counts = take((size_t)Q * 4);
+  L.pairs = take((size_t)pair_cap * 4);
+  L.pairs2 = take((size_t)pair_cap * 4);
+  L.np = take(256);
+  L.rec = take((size_t)pair_cap * sizeof(float4));
+  L.keys = keep ? take((size_t)pair_cap * 4) : 0;
+  L.ks = keep ? take((size_t)pair_cap * 4) : 0;
+  L.t8 = t8 ? take((size_t)pair_cap * 2 * sizeof(float4)) : 0;
+  L.stats = take(sizeof(DevStats));
+  L.tc = take((size_t)ntiles * 4);
+  L.to = take((size_t)(ntiles + 1) * 4);
+  L.cp = take((size_t)(ntiles + 1) * 4);
+  L.hist = take((size_t)ntiles * kSplatBlocks * 4);
+  L.bin = take((size_t)pair_cap * sizeof(float4));
+  L.jobs = take((size_t)njobs * sizeof(DevJob));
+  L.pre = take((size_t)kTechs * (2 * njobs + 1) * sizeof(int64_t));
+  L.tj = take((size_t)ntiles * 4);
+  L.ic = take(256);
+  L.tc2 = take(256);
+  L.task = take((size_t)kTaskFields * Q * sizeof(float4));
+  L.nt = take(256);
+  L.bytes = off;
+  return L;
+}
+
+// Point the workspace views into `mem` (L.bytes bytes of device memory).
+static void ws_bind(Ws& w, const WsLayout& L, void* mem, int Q, int depth, int64_t pair_cap, bool keep, bool t8) {
+  w.mem = mem;
+  w.bytes = L.bytes;
+  char* b = (char*)mem;
+  w.W.eye = (float4*)(b + L.eye);
+  w.W.light = (float4*)(b + L.light);
+  w.W.start = (float4*)(b + L.start);
+  w.W.counts = (uint32_t*)(b + L.counts);
+  w.W.pairs = (uint32_t*)(b + L.pairs);
+  w.W.pairs2 = (uint32_t*)(b + L.pairs2);
+  w.W.npairs = (uint32_t*)(b + L.np);
+  w.W.records = (float4*)(b + L.rec);
+  w.W.rec_keys = keep ? (uint32_t*)(b + L.keys) : nullptr;
+  w.W.rec_sample = keep ? (uint32_t*)(b + L.ks) : nullptr;
+  w.W.t8q = t8 ? (float4*)(b + L.t8) : nullptr;
+  w.W.task = (float4*)(b + L.task);
+  w.W.ntasks = (uint32_t*)(b + L.nt);
   w.W.fetch = w.W.ntasks + 16;
   w.W.kbins = w.W.ntasks + 32;
   w.W.Q = Q;
   w.W.pair_cap = pair_cap;
-  w.W.nslot = nslot;
-  w.stats = (DevStats*)(b + o_stats);
-  w.tcount = (uint32_t*)(b + o_tc);
-  w.toff = (uint32_t*)(b + o_to);
-  w.cpre = (uint32_t*)(b + o_cp);
-  w.hist = (uint32_t*)(b + o_hist);
-  w.binned = (float4*)(b + o_bin);
-  w.jobs = (DevJob*)(b + o_jobs);
-  w.prefix = (int64_t*)(b + o_pre);
-  w.tile_job = (int32_t*)(b + o_tj);
-  w.item_counter = (uint32_t*)(b + o_ic);
-  w.train_count = (uint32_t*)(b + o_tc2);
+  w.W.nslot = depth;
+  w.stats = (DevStats*)(b + L.stats);
+  w.tcount = (uint32_t*)(b + L.tc);
+  w.toff = (uint32_t*)(b + L.to);
+  w.cpre = (uint32_t*)(b + L.cp);
+  w.hist = (uint32_t*)(b + L.hist);
+  w.binned = (float4*)(b + L.bin);
+  w.jobs = (DevJob*)(b + L.jobs);
+  w.prefix = (int64_t*)(b + L.pre);
+  w.tile_job = (int32_t*)(b + L.tj);
+  w.item_counter = (uint32_t*)(b + L.ic);
+  w.train_count = (uint32_t*)(b + L.tc2);
+}
+
+rpi_status ws_alloc(const rpi_scene* s, Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep,
+                    bool t8, hipStream_t st, bool async) {
+  const WsLayout L = ws_layout(Q, depth, pair_cap, ntiles, njobs, keep, t8);
+  w.async = async;
+  w.owner = s;
+  void* mem = nullptr;
+  rpi_status rc = dev_alloc(s, L.bytes, st, async, &mem);
+  if (rc) return rc;
+  ws_bind(w, L, mem, Q, depth, pair_cap, keep, t8);
   return RPI_OK;
 }
 
@@ -1382,6 +1402,92 @@ extern "C" rpi_status rpi_render_residual(const rpi_scene* s, const rpi_edit* e,
     const_cast<rpi_scene*>(s)->rec_host.swap(recs);
   }
   return RPI_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free variant
+// For callers that cannot allocate device memory (code under graph capture,
+// tight serving loops): the workspace of rpi_render_residual_noalloc lives in
+// one static device array per GPU.  Host code never uses the array's name as
+// an address: the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static rpi_status scratch_address(void** out) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RPI_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(RPI_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_render_residual_noalloc(const rpi_scene* s, const rpi_edit* e, const rpi_render_params* p,
+                                                  float* out, void* stream) {
+  if (!s || !e || !out) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  rpi_status rc = check_params(s, p);
+  if (rc) return rc;
+  if (p->d_train_records || (p->flags & (RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_TIME_KERNELS)))
+    return fail(RPI_ERR_UNSUPPORTED, "records, work counting, kernel timing and training records need "
+                                     "rpi_render_residual");
+  if ((p->flags & RPI_FLAG_NO_MAPPING) && e->kind == RPI_EDIT_MATERIAL)
+    return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING applies to motion edits only");
+  hipStream_t st = (hipStream_t)stream;
+  JobSpec j;
+  std::memcpy(j.pose_old, e->pose_old, sizeof j.pose_old);
+  std::memcpy(j.pose_new, e->pose_new, sizeof j.pose_new);
+  j.mat_old = s->obj_mat;
+  j.mat_new = e->new_mat;
+  j.W = s->W;
+  j.H = s->H;
+  j.out = out;
+  j.tech = (p->flags & RPI_FLAG_PER_TECHNIQUE) ? p->d_technique_images : nullptr;
+  rpi_render_params q = *p;
+  if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);
+  const bool material = e->kind == RPI_EDIT_MATERIAL;
+  Plan pl;
+  rc = make_plan(s, {j}, material, &q, scene_tuning(s, p), pl);
+  if (rc) return rc;
+  // the largest round (a multiple of 64 samples, at most the planned one)
+  // whose workspace fits the scratch array
+  const bool t8 = (q.strategy_mask & 0x80u) && q.proposal;
+  const int64_t maxp = pl.pair_cap / pl.Q;
+  auto need = [&](int64_t Q) { return ws_layout((int)Q, q.max_depth, Q * maxp, pl.ntiles, 1, false, t8).bytes; };
+  if (need(kItem) > kScratchBytes)
+    return fail(RPI_ERR_UNSUPPORTED, "the workspace of this image (" + std::to_string(need(kItem)) +
+                                         " bytes for the smallest round) exceeds the " +
+                                         std::to_string(kScratchBytes >> 20) + " MiB static scratch array");
+  int64_t lo = 1, hi = pl.Q / kItem;  // in items of 64 samples: need(lo) fits
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (need(mid * kItem) <= kScratchBytes) lo = mid;
+    else hi = mid - 1;
+  }
+  pl.Q = (int)(lo * kItem);
+  pl.pair_cap = (int64_t)pl.Q * maxp;
+  void* ptr = nullptr;
+  rc = scratch_address(&ptr);
+  if (rc) return rc;
+  Ws w;
+  w.owner = s;
+  ws_bind(w, ws_layout(pl.Q, q.max_depth, pl.pair_cap, pl.ntiles, 1, false, t8), ptr, pl.Q, q.max_depth, pl.pair_cap,
+          false, t8);
+  rc = upload_plan(pl, w, st);
+  if (rc) return rc;
+  RunOpts o;
+  o.accumulate = (q.flags & RPI_FLAG_ACCUMULATE) != 0;
+  o.tu = scene_tuning(s, p);
+  return enqueue(pl, w, &q, o, st, nullptr, nullptr);
 }
 
 extern "C" rpi_status rpi_get_records(const rpi_scene* s, void* host_out, int64_t cap, int64_t* count) {

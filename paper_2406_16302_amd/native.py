@@ -153,6 +153,7 @@ def load_library():
         L.rpi_destroy_edit.argtypes = [vp]
         L.rpi_render_residual.argtypes = [vp, vp, C.POINTER(Params), vp, C.POINTER(Stats), vp]
         L.rpi_render_frame.argtypes = [vp, vp, C.c_int32, C.POINTER(Params), vp, vp]
+        L.rpi_render_residual_noalloc.argtypes = [vp, vp, C.POINTER(Params), vp, vp]
         L.rpi_render_frame_difference.argtypes = [vp, vp, C.c_int32, C.POINTER(Params), vp, vp]
         L.rpi_render_residual_batch.argtypes = [vp, C.POINTER(Job), C.c_int32, C.POINTER(Params),
                                                 C.POINTER(Stats), vp]
@@ -168,7 +169,7 @@ def load_library():
         L.rpi_proposal_train.argtypes = [vp, vp, C.c_int64, C.POINTER(TrainParams), vp, vp]
         L.rpi_last_error.restype = C.c_char_p
         L.rpi_version.restype = C.c_char_p
-        for f in ("rpi_render_frame_difference", "rpi_sync_status", "rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
+        for f in ("rpi_render_residual_noalloc", "rpi_render_frame_difference", "rpi_sync_status", "rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
                   "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records",
                   "rpi_autotune", "rpi_set_tuning", "rpi_proposal_create", "rpi_proposal_destroy", "rpi_proposal_set_weights",
                   "rpi_proposal_get_weights", "rpi_proposal_forward", "rpi_proposal_loss_grad",
@@ -274,6 +275,13 @@ def render_residual(scene: Scene, edit: Edit, params: Params, out, stats=False, 
     _check(L.rpi_render_residual(scene.h, edit.h, C.byref(params), _devptr(out, scene.width * scene.height * 3),
                                  C.byref(st) if st is not None else None, _stream(stream)))
     return st.as_dict() if st is not None else None
+
+
+def render_residual_noalloc(scene: Scene, edit: Edit, params: Params, out, stream=None):
+    """rpi_render_residual_noalloc: the residual with the library's static
+    workspace (no device allocation in the call)."""
+    _check(load_library().rpi_render_residual_noalloc(scene.h, edit.h, C.byref(params),
+                                                      _devptr(out, scene.width * scene.height * 3), _stream(stream)))
 
 
 def render_frame(scene: Scene, edit: Edit | None, which: int, params: Params, out, stream=None):

@@ -48,8 +48,10 @@ def test_frame_difference_matches_oracle(name, correlated):
     assert err <= 1e-3 * np.sqrt((ref ** 2).sum()) + 1e-6 * np.sqrt((frame ** 2).sum()), \
         (err, rel_l2(g, ref))
     if correlated:
-        # off the object's two footprints the difference cancels exactly
-        assert (g == 0).mean() > 0.3
+        # where every sample's path misses the object in both poses the
+        # difference cancels exactly, on both sides
+        assert (ref == 0).mean() > 0.1
+        assert ((ref == 0) == (g == 0)).mean() > 0.99
 
 
 def test_frame_difference_equals_two_frames():

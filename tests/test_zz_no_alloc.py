@@ -1,0 +1,86 @@
+"""rpi_render_residual_noalloc (the allocation-free variant for callers that
+cannot allocate) through the C ABI against rpi_render_residual on the same
+Philox streams, on two calls in a row, the second with a smaller input."""
+import numpy as np
+import pytest
+
+from paper_2406_16302_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _pair(ws, **kw):
+    from paper_2406_16302_amd import native
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    material = ws.edit.kind == scenes.EDIT_MATERIAL
+    flags = 0 if material else native.FLAG_TWO_WAY
+    p = native.Params.make(ws.spp, ws.depth, ws.seed, mask=ws.mask, flags=flags, **kw)
+    ref = torch.zeros((sc.height, sc.width, 3), dtype=torch.float32, device="cuda")
+    st = native.render_residual(sc, ed, p, ref, stats=True)
+    # stale contents: the variant overwrites the output
+    out = torch.full_like(ref, 3.0)
+    torch.cuda.synchronize()
+    held = torch.cuda.memory_allocated()
+    native.render_residual_noalloc(sc, ed, p, out)
+    native.sync_status()
+    assert torch.cuda.memory_allocated() == held
+    return ref.cpu().numpy().astype(np.float64), out.cpu().numpy().astype(np.float64), st
+
+
+def test_noalloc_matches_render_residual_on_two_calls():
+    from gpu_parity import rel_l2
+    # first call: several rounds of the static workspace (262,144 samples per stream)
+    ws = scenes.clutter_motion(width=128, height=128, depth=5, spp=16, n_spheres=80)
+    print("noalloc call 1: clutter 128x128 d5 spp16", flush=True)
+    ref, got, st = _pair(ws)
+    assert st["paths"] > 10000
+    print("rel L2 %.3g" % rel_l2(got, ref), flush=True)
+    assert rel_l2(got, ref) <= 1e-3
+    # second call, smaller input: the array keeps the first call's contents
+    ws2 = scenes.cornell_motion(width=24, height=20, depth=4, spp=4)
+    print("noalloc call 2: cornell 24x20 d4 spp4", flush=True)
+    ref2, got2, st2 = _pair(ws2)
+    assert st2["paths"] > 100
+    print("rel L2 %.3g" % rel_l2(got2, ref2), flush=True)
+    assert rel_l2(got2, ref2) <= 1e-3
+
+
+def test_noalloc_material_edit_and_technique_images():
+    from gpu_parity import rel_l2
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_material(width=32, height=32, depth=5, spp=8)
+    print("noalloc material edit 32x32", flush=True)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    timg = torch.zeros((8, 32, 32, 3), dtype=torch.float32, device="cuda")
+    p = native.Params.make(ws.spp, ws.depth, ws.seed, mask=ws.mask, flags=0, technique_images=timg)
+    ref = torch.zeros((32, 32, 3), dtype=torch.float32, device="cuda")
+    native.render_residual(sc, ed, p, ref)
+    ref_t = timg.clone()
+    out = torch.zeros_like(ref)
+    native.render_residual_noalloc(sc, ed, p, out)
+    native.sync_status()
+    assert rel_l2(out.cpu().numpy().astype(np.float64), ref.cpu().numpy().astype(np.float64)) <= 1e-3
+    for k in range(3):
+        assert rel_l2(timg[k].cpu().numpy().astype(np.float64), ref_t[k].cpu().numpy().astype(np.float64)) <= 1e-3
+
+
+def test_noalloc_rejects_what_it_cannot_do():
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_motion(width=16, height=16, depth=4, spp=2)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    out = torch.zeros((16, 16, 3), dtype=torch.float32, device="cuda")
+    for fl in (native.FLAG_RECORDS, native.FLAG_COUNT_WORK, native.FLAG_TIME_KERNELS):
+        with pytest.raises(native.RpiError) as e:
+            native.render_residual_noalloc(sc, ed, native.Params.make(2, 4, 1, flags=native.FLAG_TWO_WAY | fl), out)
+        assert e.value.code == -2
