@@ -258,7 +258,9 @@ typedef struct {
  * output pointers.  Runs the autotuner on the largest job first if the scene
  * is not tuned.  Job j uses Philox counter word params->job + j.  Up to 127
  * jobs and 16384 tiles of 32x32 pixels in total.  stats may be NULL.
- * Errors as above; records, work counting and kernel timing are UNSUPPORTED. */
+ * With RPI_FLAG_COUNT_WORK or RPI_FLAG_TIME_KERNELS the same plan and kernels
+ * run without the graph (instrumented or timed per launch; the scene must be
+ * tuned).  Errors as above; records and per-technique images are UNSUPPORTED. */
 rpi_status rpi_render_residual_batch(const rpi_scene* scene, const rpi_job* jobs, int32_t num_jobs,
                                      const rpi_render_params* params, rpi_stats* stats, void* hip_stream);
 
@@ -284,6 +286,11 @@ rpi_status rpi_autotune(rpi_scene* scene, const rpi_edit* edit, const rpi_render
  * 2^25, the most samples a round's path codes can address, or blocks per CU
  * outside [1, 64]). */
 rpi_status rpi_set_tuning(rpi_scene* scene, const rpi_tuning* tuning);
+
+/* The launch configuration later calls on this scene with queue_cap 0 use
+ * (the tuned one, else the defaults: rounds of 2^20 samples, 16 walk and 16
+ * connect workgroups per CU); ms_per_msample is 0. */
+rpi_status rpi_get_tuning(const rpi_scene* scene, rpi_tuning* out);
 
 /* Per-path records of the last rpi_render_residual call on this scene made
  * with RPI_FLAG_RECORDS (host copy): each record is 8 int32/float words

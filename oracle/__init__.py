@@ -88,7 +88,8 @@ def vmf_sample(raw, u0, u1, u2):
 
 
 STAT_NAMES = ["samples", "paths", "accepted", "r1", "r2", "r3", "r4", "r5", "r6", "zero_mis",
-              "t1", "t2", "t3", "t4", "t5", "t6", "t7", "t8", "unmapped"]
+              "t1", "t2", "t3", "t4", "t5", "t6", "t7", "t8", "unmapped",
+              "rays"]
 
 _lib = None
 

@@ -381,8 +381,13 @@ static void all_in(const Scene& S, const std::vector<Tri>& tris, const Bvh& B, V
   }
 }
 
+// Ray queries made by the calling thread (closest hits, any-hit tests and
+// ghost all-hit enumerations), for the CPU baseline's rays/s.
+static thread_local int64_t t_ray_queries = 0;
+
 // Closest hit in scene_f = static geometry + object at pose.
 static Hit closest(const Scene& S, const Pose& pose, V3 o, V3 d) {
+  ++t_ray_queries;
   float bt = INFINITY;
   int bid = 0x7fffffff, bk = -1, ok = -1;
   closest_in(S, S.stat, S.bstat, o, d, bt, bid, bk);
@@ -409,6 +414,7 @@ static Hit closest(const Scene& S, const Pose& pose, V3 o, V3 d) {
 
 // Any hit of scene_f on the open segment o + t (e - o), 0 < t < 1 (tmax = inf for rays).
 static bool blocked(const Scene& S, const Pose& pose, V3 o, V3 d, float tmax) {
+  ++t_ray_queries;
   std::vector<std::pair<float, int>> hits;
   all_in(S, S.stat, S.bstat, o, d, tmax, hits);
   if (!hits.empty()) return true;
@@ -658,6 +664,7 @@ struct Cross {
 static Cross crossings(const Scene& S, const Frame& F, const Path& P, int a) {
   Cross c{0, 0, 0, 0};
   if (!F.ghosts) return c;
+  ++t_ray_queries;
   Seg s = edge_seg(S, P, a);
   std::vector<std::pair<float, int>> hits;
   all_in(S, S.obj, S.bobj, pose_inv_apply(F.ghost, s.o), pose_inv_rot(F.ghost, s.d), s.tmax, hits);
@@ -1783,7 +1790,7 @@ struct Record {
 };
 
 struct Stats {
-  int64_t paths, accepted, rejected[7], by_tech[9], zero_mis, samples;
+  int64_t paths, accepted, rejected[7], by_tech[9], zero_mis, samples, rays;
 };
 
 static int n_starts_for(const Scene& S, const Frame& F, const Path& P, int tech) {
@@ -1933,7 +1940,9 @@ template <class Fn>
 static void parallel(int threads, int64_t s0, int64_t s1, int npix, double* img, double* tech_img, int ntech,
                      Stats& st, Fn&& body) {
   if (threads <= 1 || s1 - s0 < 2 * threads) {
+    const int64_t r0 = t_ray_queries;
     body(s0, s1, img, tech_img, st);
+    st.rays += t_ray_queries - r0;
     return;
   }
   std::vector<std::vector<double>> imgs(threads, std::vector<double>((size_t)3 * npix, 0.0));
@@ -1945,7 +1954,11 @@ static void parallel(int threads, int64_t s0, int64_t s1, int npix, double* img,
     std::memset(&sts[t], 0, sizeof(Stats));
     if (tech_img) timgs[t].assign((size_t)3 * npix * ntech, 0.0);
     int64_t a = s0 + n * t / threads, b = s0 + n * (t + 1) / threads;
-    th.emplace_back([&, t, a, b] { body(a, b, imgs[t].data(), tech_img ? timgs[t].data() : nullptr, sts[t]); });
+    th.emplace_back([&, t, a, b] {
+      const int64_t r0 = t_ray_queries;
+      body(a, b, imgs[t].data(), tech_img ? timgs[t].data() : nullptr, sts[t]);
+      sts[t].rays = t_ray_queries - r0;
+    });
   }
   for (auto& x : th) x.join();
   for (int t = 0; t < threads; ++t) {
@@ -1956,6 +1969,7 @@ static void parallel(int threads, int64_t s0, int64_t s1, int npix, double* img,
     st.accepted += sts[t].accepted;
     st.zero_mis += sts[t].zero_mis;
     st.samples += sts[t].samples;
+    st.rays += sts[t].rays;
     for (int r = 0; r < 7; ++r) st.rejected[r] += sts[t].rejected[r];
     for (int r = 0; r < 9; ++r) st.by_tech[r] += sts[t].by_tech[r];
   }
@@ -2227,6 +2241,7 @@ int orc_render_residual(void* sp, const float* pose_old, const float* pose_new, 
     stats_out[9] = st.zero_mis;
     for (int t = 1; t <= 8; ++t) stats_out[9 + t] = st.by_tech[t];
     stats_out[18] = st.rejected[0];
+    stats_out[19] = st.rays;
   }
   if (rec_count) {
     *rec_count = (int64_t)rv.size();

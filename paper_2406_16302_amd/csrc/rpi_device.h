@@ -538,8 +538,8 @@ DEV void closest_line_in(const DevBvh& B, vec3 o, vec3 d, Hit& hf, Hit& hb, int 
   });
 }
 
-// closest(o, d) and closest(o, -d) of scene_f as one line query (counted as
-// one ray; the caller counts the second if it would have traced it).
+// closest(o, d) and closest(o, -d) of scene_f as one line query (one
+// traversal, counted as one ray query).
 template <bool CW>
 DEV void closest_line(const DevScene& S, const DevFrame& F, vec3 o, vec3 d, Hit& hf, Hit& hb, int* stk,
                       WorkCount& wc) {

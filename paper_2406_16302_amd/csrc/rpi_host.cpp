@@ -1641,6 +1641,18 @@ extern "C" rpi_status rpi_set_tuning(rpi_scene* s, const rpi_tuning* t) {
   return RPI_OK;
 }
 
+extern "C" rpi_status rpi_get_tuning(const rpi_scene* s, rpi_tuning* t) {
+  if (!s || !t) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  rpi_render_params p;
+  std::memset(&p, 0, sizeof p);
+  const Tuning tu = scene_tuning(s, &p);
+  t->queue_cap = tu.Q;
+  t->walk_blocks_per_cu = tu.walk_bpc;
+  t->connect_blocks_per_cu = tu.conn_bpc;
+  t->ms_per_msample = 0.0;
+  return RPI_OK;
+}
+
 // A captured batch: persistent workspace, job table staging, graph.
 struct BatchCache {
   std::vector<int> sizes;      // W, H per job
@@ -1682,9 +1694,8 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
       ((p->strategy_mask & 0x80u) && !p->proposal))
     return fail(RPI_ERR_INVALID_ARG, "bad params");
   if (p->d_train_records) return fail(RPI_ERR_UNSUPPORTED, "training-record collection is not available for batches");
-  if (p->flags & (RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_TIME_KERNELS | RPI_FLAG_PER_TECHNIQUE))
-    return fail(RPI_ERR_UNSUPPORTED,
-                "records, work counting, kernel timing and per-technique images are not available for batches");
+  if (p->flags & (RPI_FLAG_RECORDS | RPI_FLAG_PER_TECHNIQUE))
+    return fail(RPI_ERR_UNSUPPORTED, "records and per-technique images are not available for batches");
   if (p->tile != 0 && p->tile != 16 && p->tile != 32) return fail(RPI_ERR_INVALID_ARG, "tile must be 0, 16 or 32");
   if ((p->flags & RPI_FLAG_NO_MAPPING) && !(p->flags & RPI_FLAG_TWO_WAY))
     return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING needs RPI_FLAG_TWO_WAY");
@@ -1709,6 +1720,12 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
     js[i].out = jb.d_out;
     sizes.push_back(jb.width);
     sizes.push_back(jb.height);
+  }
+  if (q.flags & (RPI_FLAG_COUNT_WORK | RPI_FLAG_TIME_KERNELS)) {
+    // instrumented or per-kernel-timed: the same plan and kernels launched
+    // directly instead of through the captured graph
+    if (s->tuned_Q == 0 && p->queue_cap <= 0) return fail(RPI_ERR_INVALID_ARG, "tune the scene first");
+    return run_jobs(s, js, false, &q, scene_tuning(s, &q), stats, st, nullptr);
   }
   std::lock_guard<std::mutex> lk(s->mu);
   BatchCache* c = s->batch;

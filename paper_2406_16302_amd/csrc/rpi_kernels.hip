@@ -473,7 +473,6 @@ DEV void tech6(Lane& L) {
   hit_vertex(S, A.F.pose, hl, xg, w, l0, l0n, l0md);
   if (is_emitter(S, l0md)) return;
   if (interior_hit(S, A.F, l0, l0n, l0md, xg)) return;  // x_G inside the object: no path leaves it
-  if (CW) L.wc.rays[RAY_CLOSEST]++;  // the query along -w
   if (!he.ok) return;
   vec3 e0, e0n;
   uint32_t e0md;
@@ -1511,6 +1510,9 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
     exw[a] = a == k - 2 ? r2.z : (a == 0 ? r2.y : r2.x);
     exm |= r1.w > 0.0f ? 1u << a : 0u;
   }
+  // records read: the path code, two float4 per scattering vertex, two for
+  // the light end, up to two per edge's crossing record
+  if (CW) wc.bytes += 4u + 32u * (uint32_t)nsc + 32u + (motion ? 32u * (uint32_t)(k - 1) : 0u);
 
   const DevCamera& C = S.cam;
   const float P = (float)(C.W * C.H);

@@ -160,6 +160,7 @@ def load_library():
         L.rpi_get_records.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.rpi_autotune.argtypes = [vp, vp, C.POINTER(Params), C.POINTER(Tuning), vp]
         L.rpi_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.rpi_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.rpi_proposal_create.argtypes = [vp, vp, C.c_uint64, C.POINTER(vp)]
         L.rpi_proposal_destroy.argtypes = [vp]
         L.rpi_proposal_set_weights.argtypes = [vp, vp]
@@ -169,7 +170,7 @@ def load_library():
         L.rpi_proposal_train.argtypes = [vp, vp, C.c_int64, C.POINTER(TrainParams), vp, vp]
         L.rpi_last_error.restype = C.c_char_p
         L.rpi_version.restype = C.c_char_p
-        for f in ("rpi_render_residual_noalloc", "rpi_render_frame_difference", "rpi_sync_status", "rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
+        for f in ("rpi_get_tuning", "rpi_render_residual_noalloc", "rpi_render_frame_difference", "rpi_sync_status", "rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
                   "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records",
                   "rpi_autotune", "rpi_set_tuning", "rpi_proposal_create", "rpi_proposal_destroy", "rpi_proposal_set_weights",
                   "rpi_proposal_get_weights", "rpi_proposal_forward", "rpi_proposal_loss_grad",
@@ -315,6 +316,14 @@ def autotune(scene: Scene, edit: Edit, params: Params, stream=None):
 def set_tuning(scene: Scene, queue_cap, walk_blocks_per_cu, connect_blocks_per_cu):
     t = Tuning(int(queue_cap), int(walk_blocks_per_cu), int(connect_blocks_per_cu), 0.0)
     _check(load_library().rpi_set_tuning(scene.h, C.byref(t)))
+
+
+def get_tuning(scene: Scene):
+    """rpi_get_tuning: the launch configuration of later calls with queue_cap 0."""
+    t = Tuning()
+    _check(load_library().rpi_get_tuning(scene.h, C.byref(t)))
+    return {"queue_cap": t.queue_cap, "walk_blocks_per_cu": t.walk_blocks_per_cu,
+            "connect_blocks_per_cu": t.connect_blocks_per_cu}
 
 
 def render_residual_batch(scene: Scene, jobs, params: Params, stats=False, stream=None):

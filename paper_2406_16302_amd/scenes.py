@@ -119,6 +119,15 @@ def rotation_y(deg, t=(0, 0, 0)) -> np.ndarray:
     return np.array([c, 0, s, t[0], 0, 1, 0, t[1], -s, 0, c, t[2]], np.float32)
 
 
+def rotation_y_about(deg, center, t=(0, 0, 0)) -> np.ndarray:
+    """Rotation by deg about the vertical axis through center, then a
+    translation t: x -> R (x - center) + center + t."""
+    m = rotation_y(deg).reshape(3, 4).astype(np.float64)
+    c = np.asarray(center, np.float64)
+    m[:, 3] = c - m[:, :3] @ c + np.asarray(t, np.float64)
+    return m.astype(np.float32).reshape(12)
+
+
 # --- primitive meshes -------------------------------------------------------
 
 def icosphere(level: int):
@@ -197,10 +206,13 @@ def box_mesh(center, half):
 # --- workloads --------------------------------------------------------------
 
 def cornell_motion(width=64, height=64, spp=16, depth=3, seed=1001,
-                   offset=(0.1, 0.0, 0.05), two_cubes=False) -> Workload:
+                   offset=(0.1, 0.0, 0.05), two_cubes=False, lift=1e-3, rotate_deg=0.0) -> Workload:
     """Tiny Cornell box with a moving 12-triangle cube (24 triangles), or with
     a moving object made of two cubes with a gap between them (a non-convex
-    object that shadows and reflects onto itself)."""
+    object that shadows and reflects onto itself).  lift: height of the
+    object above the floor (0: resting on it, its bottom face coplanar with
+    the floor); rotate_deg: the edit also turns the cube about its vertical
+    axis."""
     mats = [mat(DIFFUSE, (0.7, 0.7, 0.7)), mat(DIFFUSE, (0.7, 0.1, 0.1)),
             mat(DIFFUSE, (0.1, 0.7, 0.1)), mat(EMITTER, emission=(15, 15, 15)),
             mat(DIFFUSE, (0.7, 0.7, 0.7))]
@@ -214,18 +226,20 @@ def cornell_motion(width=64, height=64, spp=16, depth=3, seed=1001,
     ly, lh = 0.499, 0.1
     m.add_quad((-lh, ly, -lh), (lh, ly, -lh), (lh, ly, lh), (-lh, ly, lh), 3)  # light, -y
     if two_cubes:
-        # two cubes of side 0.16, 0.06 apart, lifted 1e-3 above the floor
+        # two cubes of side 0.16, 0.06 apart
         for cx in (-0.16, 0.06):
-            v, f = box_mesh((cx, -0.419, -0.05), (0.08, 0.08, 0.08))
+            v, f = box_mesh((cx, -0.42 + lift, -0.05), (0.08, 0.08, 0.08))
             m.add(v, f, 4, obj=1)
+        center = (-0.05, -0.42 + lift, -0.05)
     else:
-        # cube of side 0.3 lifted 1e-3 above the floor (no coplanar contact)
-        v, f = box_mesh((-0.05, -0.349, -0.05), (0.15, 0.15, 0.15))
+        # cube of side 0.3
+        center = (-0.05, -0.35 + lift, -0.05)
+        v, f = box_mesh(center, (0.15, 0.15, 0.15))
         m.add(v, f, 4, obj=1)
     cam = [0, 0, 1.7, 0, 0, 0, 0, 1, 0, 40.0, width, height]
     scene = m.build(mats, (0, 0, 0), cam)
-    return Workload("cornell_motion", scene, Edit(EDIT_RIGID, translation(offset)),
-                    spp, depth, 0x7F, True, seed)
+    xf = rotation_y_about(rotate_deg, center, offset) if rotate_deg else translation(offset)
+    return Workload("cornell_motion", scene, Edit(EDIT_RIGID, xf), spp, depth, 0x7F, True, seed)
 
 
 def cornell_material(width=64, height=64, spp=16, depth=3, seed=1011) -> Workload:
@@ -236,7 +250,7 @@ def cornell_material(width=64, height=64, spp=16, depth=3, seed=1011) -> Workloa
 
 
 def clutter_motion(width=512, height=512, spp=64, depth=5, seed=1002,
-                   n_spheres=400) -> Workload:
+                   n_spheres=400, env=(0.0, 0.0, 0.0)) -> Workload:
     """Ground plane, seeded icosphere clutter and a 20,480-triangle moving sphere."""
     rng = np.random.default_rng(seed)
     mats = [mat(DIFFUSE, (0.5, 0.5, 0.5)), mat(EMITTER, emission=(20, 20, 20)),
@@ -266,7 +280,7 @@ def clutter_motion(width=512, height=512, spp=64, depth=5, seed=1002,
     m.add(vs * 0.5 + np.array([0.0, 0.5, 0.0]), fs, 2, obj=1)
     t = rng.uniform(-0.5, 0.5, 2)
     cam = [0, 4, 9, 0, 0.5, 0, 0, 1, 0, 45.0, width, height]
-    scene = m.build(mats, (0, 0, 0), cam)
+    scene = m.build(mats, env, cam)
     return Workload("clutter_motion", scene,
                     Edit(EDIT_RIGID, translation((t[0], 0.0, t[1]))),
                     spp, depth, 0x7F, True, seed)

@@ -92,6 +92,24 @@ def test_ghost_plane_open_object():
     _parity(scenes.ghost_plane(width=24, height=24, open_object=True))
 
 
+def test_object_resting_on_the_floor():
+    """The cube rests on the floor: its bottom face is coplanar with the floor
+    in both poses (coplanar contact, grazing visibility along the seam)."""
+    _parity(scenes.cornell_motion(width=32, height=32, spp=8, depth=5, lift=0.0))
+
+
+def test_rotation_edit():
+    """A rigid edit with a rotation (25 degrees about the cube's vertical
+    axis, then a translation): the vertex map of Sec. 5 rotates normals too."""
+    _parity(scenes.cornell_motion(width=32, height=32, spp=8, depth=5, lift=0.0, rotate_deg=25.0))
+
+
+def test_motion_with_environment_light():
+    """A moving object under an area light and a constant environment (next
+    event estimation picks the environment half the time)."""
+    _parity(scenes.clutter_motion(width=48, height=48, spp=2, depth=5, n_spheres=60, env=(0.2, 0.25, 0.3)))
+
+
 def test_nonconvex_object_motion():
     """A moving object of two cubes: rays leaving one cube can meet the other,
     so the object's BVH must not be skipped for them (it is for convex
