@@ -341,6 +341,7 @@ struct rpi_scene {
   std::vector<std::array<float, 9>> light_host;
   Material obj_mat;
   float diag;
+  float lmax = 1.0f;  // largest emission of the scene (emitters, environment): the fixed-point splat's scale
   int W, H;
   int bvh_depth_static, bvh_depth_obj;
   // last records (RPI_FLAG_RECORDS)
@@ -698,6 +699,15 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, const rpi_allocat
   }
   S->W = C.W;
   S->H = C.H;
+  {
+    double lm = 0.0;
+    for (int m = 0; m < d->num_materials; ++m)
+      if ((int)d->materials[8 * m] == MAT_EMITTER)
+        for (int c = 0; c < 3; ++c) lm = std::max(lm, (double)std::fabs(d->materials[8 * m + 5 + c]));
+    if (has_env)
+      for (int c = 0; c < 3; ++c) lm = std::max(lm, (double)std::fabs(d->env[c]));
+    S->lmax = lm > 0.0 && std::isfinite(lm) ? (float)lm : 1.0f;
+  }
   *out = S.release();
   return RPI_OK;
 }
@@ -900,16 +910,18 @@ struct Ws {
   DevJob* jobs;
   int64_t* prefix;  // [kTechs][2 * njobs + 1]
   int32_t* tile_job;
+  unsigned long long* acc;  // fixed-point images of the jobs
   size_t bytes = 0;
 };
 
 // Byte offsets of the workspace parts for rounds of Q samples.
 struct WsLayout {
   size_t eye, light, start, counts, pairs, pairs2, np, rec, keys, ks, t8, stats, tc, to, cp, hist, bin, jobs, pre, tj,
-      ic, tc2, task, nt, bytes;
+      ic, tc2, task, nt, acc, bytes;
 };
 
-static WsLayout ws_layout(int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep, bool t8) {
+static WsLayout ws_layout(int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep, bool t8,
+                          int64_t acc_elems) {
   WsLayout L{};
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -942,6 +954,7 @@ static WsLayout ws_layout(int Q, int depth, int64_t pair_cap, int ntiles, int nj
   L.tc2 = take(256);
   L.task = take((size_t)kTaskFields * Q * sizeof(float4));
   L.nt = take(256);
+  L.acc = take((size_t)acc_elems * 8);
   L.bytes = off;
   return L;
 }
@@ -980,11 +993,13 @@ static void ws_bind(Ws& w, const WsLayout& L, void* mem, int Q, int depth, int64
   w.tile_job = (int32_t*)(b + L.tj);
   w.item_counter = (uint32_t*)(b + L.ic);
   w.train_count = (uint32_t*)(b + L.tc2);
+  w.acc = (unsigned long long*)(b + L.acc);
 }
 
+
 rpi_status ws_alloc(const rpi_scene* s, Ws& w, int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep,
-                    bool t8, hipStream_t st, bool async) {
-  const WsLayout L = ws_layout(Q, depth, pair_cap, ntiles, njobs, keep, t8);
+                    bool t8, int64_t acc_elems, hipStream_t st, bool async) {
+  const WsLayout L = ws_layout(Q, depth, pair_cap, ntiles, njobs, keep, t8, acc_elems);
   w.async = async;
   w.owner = s;
   void* mem = nullptr;
@@ -1021,8 +1036,15 @@ struct Plan {
   int64_t pair_cap = 0;
   int Q = 0;
   bool material_mode = false;
+  std::vector<int64_t> acc_off;  // per job: first element of its fixed-point image
+  int64_t acc_elems = 0;
   vec3 obj_center, obj_inv_half;  // training-record input normalisation
 };
+
+// Point every job of the plan at its part of the workspace's fixed-point image.
+static void bind_jobs(Plan& pl, const Ws& w) {
+  for (size_t j = 0; j < pl.jobs.size(); ++j) pl.jobs[j].acc = w.acc + pl.acc_off[j];
+}
 
 }  // namespace
 
@@ -1052,6 +1074,12 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
   pl.jobs.resize(nj);
   pl.ntiles = 0;
   pl.tile_job.clear();
+  pl.acc_off.assign(nj, 0);
+  pl.acc_elems = 0;
+  for (int j = 0; j < nj; ++j) {
+    pl.acc_off[j] = pl.acc_elems;
+    pl.acc_elems += (int64_t)js[j].W * js[j].H * 3;
+  }
   // 16x16 tiles unless the batch needs more than kMaxTiles of them (or the
   // caller asks for a tile edge)
   int64_t t16 = 0;
@@ -1067,6 +1095,8 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
     J.F[1] = make_frame(s, q.pose_old, q.pose_new, q.mat_old, !material_mode);
     J.image = q.out;
     J.tech_images = q.tech;
+    J.fx_scale = (float)(1099511627776.0 / (double)s->lmax);  // 2^40 / largest emission
+    J.fx_unit = (double)s->lmax / 1099511627776.0;
     const int64_t N = (int64_t)p->spp * q.W * q.H;
     if (N > 0xffffffffLL) return fail(RPI_ERR_UNSUPPORTED, "more than 2^32 samples per technique stream");
     J.s0 = p->sample_begin;
@@ -1126,7 +1156,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
                           std::vector<Timed>* evs, std::vector<uint32_t>* rec_out) {
   const int nj = (int)pl.jobs.size();
   const bool per_tech = (p->flags & RPI_FLAG_PER_TECHNIQUE) != 0;
-  if (!o.accumulate || per_tech) launch_zero_images(w.jobs, nj, !o.accumulate, st);
+  launch_zero_images(w.jobs, nj, st);  // the fixed-point images (and technique images)
   WalkArgs A;
   std::memset(&A, 0, sizeof A);
   A.jobs = w.jobs;
@@ -1179,7 +1209,6 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
   sa.ntiles = pl.ntiles;
   sa.nblk = kSplatBlocks;
   sa.ts = pl.ts;
-  sa.tech = 0;
   const int wblocks = device_cus() * o.tu.walk_bpc;
   const int cblocks = device_cus() * o.tu.conn_bpc;
   const int R = pl.Q / kItem;
@@ -1232,7 +1261,6 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       }
       r = timed(kKidConnect, [&] { launch_connect(As, cblocks, st); });
       if (r) return r;
-      sa.tech = per_tech ? t : 0;
       r = timed(kKidSplat, [&] { launch_splat(sa, st); });
       if (r) return r;
       if (o.keep && rec_out) {
@@ -1263,9 +1291,12 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
         }
       }
     }
+    // this technique's share into its own image
+    if (per_tech) launch_flush_acc(w.jobs, nj, t, false, st);
   }
   // the total of the technique images, added in technique order
   if (per_tech) launch_sum_technique_images(w.jobs, nj, o.accumulate, st);
+  else launch_flush_acc(w.jobs, nj, 0, o.accumulate, st);
   hipError_t le = hipGetLastError();
   if (le != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
   return RPI_OK;
@@ -1320,8 +1351,10 @@ static rpi_status run_jobs(const rpi_scene* s, const std::vector<JobSpec>& js, b
   o.tu = tu;
   Ws w;
   const bool t8 = (p->strategy_mask & 0x80u) && p->proposal;
-  rc = ws_alloc(s, w, pl.Q, p->max_depth, pl.pair_cap, pl.ntiles, (int)pl.jobs.size(), o.keep, t8, st, true);
+  rc = ws_alloc(s, w, pl.Q, p->max_depth, pl.pair_cap, pl.ntiles, (int)pl.jobs.size(), o.keep, t8, pl.acc_elems, st,
+                true);
   if (rc) return rc;
+  bind_jobs(pl, w);
   rc = upload_plan(pl, w, st);
   if (rc) {
     ws_free(w, st);
@@ -1462,7 +1495,9 @@ extern "C" rpi_status rpi_render_residual_noalloc(const rpi_scene* s, const rpi_
   // whose workspace fits the scratch array
   const bool t8 = (q.strategy_mask & 0x80u) && q.proposal;
   const int64_t maxp = pl.pair_cap / pl.Q;
-  auto need = [&](int64_t Q) { return ws_layout((int)Q, q.max_depth, Q * maxp, pl.ntiles, 1, false, t8).bytes; };
+  auto need = [&](int64_t Q) {
+    return ws_layout((int)Q, q.max_depth, Q * maxp, pl.ntiles, 1, false, t8, pl.acc_elems).bytes;
+  };
   if (need(kItem) > kScratchBytes)
     return fail(RPI_ERR_UNSUPPORTED, "the workspace of this image (" + std::to_string(need(kItem)) +
                                          " bytes for the smallest round) exceeds the " +
@@ -1480,8 +1515,9 @@ extern "C" rpi_status rpi_render_residual_noalloc(const rpi_scene* s, const rpi_
   if (rc) return rc;
   Ws w;
   w.owner = s;
-  ws_bind(w, ws_layout(pl.Q, q.max_depth, pl.pair_cap, pl.ntiles, 1, false, t8), ptr, pl.Q, q.max_depth, pl.pair_cap,
-          false, t8);
+  ws_bind(w, ws_layout(pl.Q, q.max_depth, pl.pair_cap, pl.ntiles, 1, false, t8, pl.acc_elems), ptr, pl.Q, q.max_depth,
+          pl.pair_cap, false, t8);
+  bind_jobs(pl, w);
   rc = upload_plan(pl, w, st);
   if (rc) return rc;
   RunOpts o;
@@ -1749,7 +1785,8 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
     rpi_status rc = make_plan(s, js, false, &q, scene_tuning(s, &q), c->plan);
     if (!rc)
       rc = ws_alloc(s, c->ws, c->plan.Q, q.max_depth, c->plan.pair_cap, c->plan.ntiles, n, false,
-                    (q.strategy_mask & 0x80u) && q.proposal, st, false);
+                    (q.strategy_mask & 0x80u) && q.proposal, c->plan.acc_elems, st, false);
+    if (!rc) bind_jobs(c->plan, c->ws);
     if (rc) {
       destroy_batch_cache(c);
       return rc;
@@ -1795,6 +1832,7 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
     if (rc) return rc;
     HIP_OK(hipEventSynchronize(c->staged));
     c->plan.jobs = pl.jobs;
+    bind_jobs(c->plan, c->ws);
   }
   std::memcpy(c->pinned, c->plan.jobs.data(), sizeof(DevJob) * n);
   HIP_OK(hipMemcpyAsync(c->ws.jobs, c->pinned, sizeof(DevJob) * n, hipMemcpyHostToDevice, st));

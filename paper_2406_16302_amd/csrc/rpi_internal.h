@@ -162,6 +162,13 @@ struct DevJob {
   DevFrame F[2];
   float* image;
   float* tech_images;  // per-technique images (8 x W x H x 3) or null
+  // Fixed-point accumulation image (W x H x 3, two's complement in units of
+  // fx_unit): the splat adds integers, whose sum does not depend on the
+  // order of the additions, so the image is the same bit for bit whatever
+  // the scheduling, the round size or the tile size.
+  unsigned long long* acc;
+  float fx_scale;   // fixed-point units per unit of radiance: 2^40 / (largest emission of the scene)
+  double fx_unit;   // 1 / fx_scale
   int64_t s0, s1;
   float inv_n;      // 1 / (spp * W * H)
   int32_t tile0;    // first tile of this job in the batch-wide tile index space
@@ -254,7 +261,6 @@ struct SplatArgs {
   float4* binned;     // [cap]
   int ntiles, nblk;
   int ts;             // tile edge in pixels: 16 or 32
-  int tech;           // 0: splat into the job's image; t: into its technique image t-1
 };
 
 struct FrameArgs {
@@ -274,8 +280,12 @@ void launch_walk(const WalkArgs& A, int blocks, hipStream_t st);        // start
 void launch_walk_tasks(const WalkArgs& A, int blocks, hipStream_t st);  // walk phase (over the task queue)
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st);
 void launch_sort_pairs(const WalkArgs& A, hipStream_t st);
-// zero the jobs' images (if `images`) and their technique images (if any)
-void launch_zero_images(const DevJob* jobs, int njobs, bool images, hipStream_t st);
+// zero the jobs' technique images (if any) and fixed-point accumulation images
+void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st);
+// fixed-point accumulation -> float: tech = 0: into the job's image (added to
+// it with `accumulate`), else into technique image tech - 1; the accumulation
+// image is zeroed
+void launch_flush_acc(const DevJob* jobs, int njobs, int tech, bool accumulate, hipStream_t st);
 // image = (accumulate ? image : 0) + technique image 1 + ... + technique image 8
 void launch_sum_technique_images(const DevJob* jobs, int njobs, bool accumulate, hipStream_t st);
 void launch_splat(const SplatArgs& a, hipStream_t st);

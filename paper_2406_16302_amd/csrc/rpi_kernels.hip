@@ -12,9 +12,12 @@
 //                      (Sec. 4.3), path mapping and rejection (Sec. 5),
 //                      evaluation in both frames (eq. shiftmapped), one signed
 //                      splat record per path.
-//   splat kernels      counting sort of the records by 16x16 tile, then one
-//                      workgroup per tile accumulates in LDS and writes the
-//                      tile once (no float atomics on the image in HBM).
+//   splat kernels      counting sort of the records by tile (16x16 or 32x32),
+//                      then workgroups take chunks of a tile's records and
+//                      sum them per pixel in LDS in fixed point; the sums go
+//                      to a fixed-point image that is turned into the float
+//                      image at the end of the call (no float atomics: the
+//                      image is the same bit for bit whatever the order).
 // frame_kernel renders a frame by plain path tracing (Sec. 3.1).
 #include "rpi_device.h"
 #include "rpi_mlp.h"
@@ -2069,13 +2072,25 @@ __global__ __launch_bounds__(256) void splat_scatter(SplatArgs a) {
   }
 }
 
+// Record value -> fixed point (units of 2^-40 of the scene's largest
+// emission).  Clamped to +-2^56 units so that sums of many records cannot
+// wrap; rintf of a float already holding an integer is exact.
+constexpr float kFxClamp = 72057594037927936.0f;  // 2^56
+DEV unsigned long long to_fixed(float v, float scale) {
+  const float x = fminf(fmaxf(v * scale, -kFxClamp), kFxClamp);
+  return (unsigned long long)(long long)rintf(x);
+}
+
 // Workgroups take chunks of at most kSplatChunk binned records of one tile
 // (a few tiles near the edit hold most records, so one workgroup per tile
-// would leave the chip idle behind them), accumulate them in LDS and add
-// the sums to the tile's pixels: a plain read-modify-write when the tile has
-// one chunk, float atomics when several chunks share it.
+// would leave the chip idle behind them) and sum them per pixel in LDS in
+// fixed point; the tile's sums go to the job's fixed-point image: a plain
+// read-modify-write when the tile has one chunk, integer adds when several
+// chunks share it.  Integer addition is associative, so the image does not
+// depend on the order in which records, chunks or rounds arrive, and no
+// floating-point atomic is used.
 __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
-  __shared__ float acc[kTileMax * kTileMax * 3];
+  __shared__ unsigned long long acc[kTileMax * kTileMax * 3];
   const uint32_t nch = a.cpre[a.ntiles];
   const int tp = a.ts * a.ts;
   for (uint32_t g = blockIdx.x; g < nch; g += gridDim.x) {
@@ -2089,28 +2104,28 @@ __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
     const uint32_t b = a.toff[t] + (g - a.cpre[t]) * kSplatChunk;
     const uint32_t e = min(b + kSplatChunk, a.toff[t + 1]);
     const bool shared = a.cpre[t + 1] - a.cpre[t] > 1;
-    for (int i = threadIdx.x; i < tp * 3; i += 256) acc[i] = 0.0f;
+    const DevJob& J = a.jobs[a.tile_job[t]];
+    const float scale = J.fx_scale;
+    for (int i = threadIdx.x; i < tp * 3; i += 256) acc[i] = 0ull;
     __syncthreads();
     for (uint32_t i = b + threadIdx.x; i < e; i += 256) {
       const float4 r = a.binned[i];
       const int l = __float_as_int(r.x);
-      atomicAdd(&acc[3 * l + 0], r.y);
-      atomicAdd(&acc[3 * l + 1], r.z);
-      atomicAdd(&acc[3 * l + 2], r.w);
+      atomicAdd(&acc[3 * l + 0], to_fixed(r.y, scale));
+      atomicAdd(&acc[3 * l + 1], to_fixed(r.z, scale));
+      atomicAdd(&acc[3 * l + 2], to_fixed(r.w, scale));
     }
     __syncthreads();
-    const DevJob& J = a.jobs[a.tile_job[t]];
     const int lt = t - J.tile0;
     const int tx = lt % J.tilesx, ty = lt / J.tilesx;
-    float* img = a.tech ? J.tech_images + (size_t)(a.tech - 1) * J.W * J.H * 3 : J.image;
     for (int l = threadIdx.x; l < tp; l += 256) {
       const int px = tx * a.ts + (l % a.ts), py = ty * a.ts + (l / a.ts);
       if (px < J.W && py < J.H) {
-        float* o = img + 3 * ((size_t)py * J.W + px);
+        unsigned long long* o = J.acc + 3 * ((size_t)py * J.W + px);
         if (shared) {
-          unsafeAtomicAdd(o + 0, acc[3 * l]);  // the hardware float add (device memory)
-          unsafeAtomicAdd(o + 1, acc[3 * l + 1]);
-          unsafeAtomicAdd(o + 2, acc[3 * l + 2]);
+          atomicAdd(o + 0, acc[3 * l]);
+          atomicAdd(o + 1, acc[3 * l + 1]);
+          atomicAdd(o + 2, acc[3 * l + 2]);
         } else {
           o[0] += acc[3 * l];
           o[1] += acc[3 * l + 1];
@@ -2122,15 +2137,27 @@ __global__ __launch_bounds__(256) void splat_tiles(SplatArgs a) {
   }
 }
 
-__global__ __launch_bounds__(256) void zero_images(const DevJob* jobs, int njobs, int images) {
+__global__ __launch_bounds__(256) void zero_images(const DevJob* jobs, int njobs) {
   for (int j = 0; j < njobs; ++j) {
     const int64_t n = (int64_t)jobs[j].W * jobs[j].H * 3;
-    float* p = jobs[j].image;
-    if (images)
-      for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0f;
+    unsigned long long* f = jobs[j].acc;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) f[i] = 0ull;
     float* q = jobs[j].tech_images;
     if (q)
       for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < kTechs * n; i += (int64_t)gridDim.x * 256) q[i] = 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(256) void flush_acc(const DevJob* jobs, int njobs, int tech, int accumulate) {
+  for (int j = 0; j < njobs; ++j) {
+    const DevJob& J = jobs[j];
+    const int64_t n = (int64_t)J.W * J.H * 3;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+      const float v = (float)((double)(long long)J.acc[i] * J.fx_unit);
+      J.acc[i] = 0ull;
+      if (tech) J.tech_images[(size_t)(tech - 1) * n + i] = v;
+      else J.image[i] = accumulate ? J.image[i] + v : v;
+    }
   }
 }
 
@@ -2320,8 +2347,11 @@ void launch_walk_tasks(const WalkArgs& A, int blocks, hipStream_t st) {
 void launch_sum_technique_images(const DevJob* jobs, int njobs, bool accumulate, hipStream_t st) {
   hipLaunchKernelGGL(sum_technique_images, dim3(1024), dim3(256), 0, st, jobs, njobs, accumulate ? 1 : 0);
 }
-void launch_zero_images(const DevJob* jobs, int njobs, bool images, hipStream_t st) {
-  hipLaunchKernelGGL(zero_images, dim3(1024), dim3(256), 0, st, jobs, njobs, images ? 1 : 0);
+void launch_flush_acc(const DevJob* jobs, int njobs, int tech, bool accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(flush_acc, dim3(1024), dim3(256), 0, st, jobs, njobs, tech, accumulate ? 1 : 0);
+}
+void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st) {
+  hipLaunchKernelGGL(zero_images, dim3(1024), dim3(256), 0, st, jobs, njobs);
 }
 void launch_t8_start(const WalkArgs& A, int blocks, hipStream_t st) {
   hipLaunchKernelGGL(t8_start_kernel, dim3(blocks), dim3(kTraceBlock), 0, st, A);
