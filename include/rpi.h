@@ -264,6 +264,40 @@ typedef struct {
 rpi_status rpi_render_residual_batch(const rpi_scene* scene, const rpi_job* jobs, int32_t num_jobs,
                                      const rpi_render_params* params, rpi_stats* stats, void* hip_stream);
 
+/* Residual-aware denoising (addition beyond the paper, which leaves the
+ * residual's noise around the edit to an external denoiser, Sec. 6,
+ * limitations).  d_a and d_b are two independent estimates of the residual
+ * (rpi_render_residual on the sample ranges [0, N/2) and [N/2, N) of every
+ * stream, each divided by the full N, so that R = a + b); d_out (H x W x 3
+ * float32, may alias neither input) receives R filtered by an
+ * edge-avoiding a-trous wavelet transform (Dammertz et al. 2010): 5x5
+ * B3-spline taps at strides 1, 2, 4, ..., weighted by the new frame's
+ * normals and hit distances (one camera ray per pixel centre) and by the
+ * luminance difference in units of the residual's standard deviation, which
+ * is estimated per pixel as (a - b)^2 and carried through the passes with
+ * squared weights (Schied et al. 2017).  Pixels no dynamic path reached
+ * (a = b = 0) have zero variance and keep their zero.  The filter trades
+ * bias for variance: its output is not an unbiased estimate.  Workspace
+ * (48 bytes per pixel) comes from the scene's allocator.  Asynchronous.
+ * Errors: INVALID_ARG (null pointers, iterations outside 0..10, negative or
+ * non-finite sigmas). */
+typedef struct {
+  int32_t iterations;  /* a-trous passes (strides 1, 2, 4, ...), 0: 5 */
+  float sigma_normal;  /* exponent of the normal weight max(0, n_p . n_q)^sigma, 0: 64 */
+  float sigma_depth;   /* hit-distance tolerance relative to the centre's distance, 0: 0.1 */
+  float sigma_value;   /* luminance tolerance in standard deviations of the centre's residual, 0: 4 */
+} rpi_denoise_params;
+
+rpi_status rpi_denoise_residual(const rpi_scene* scene, const rpi_edit* edit, const float* d_a, const float* d_b,
+                                const rpi_denoise_params* params, float* d_out, void* hip_stream);
+
+/* The guide of rpi_denoise_residual: per pixel (row-major, H x W x 4 float32)
+ * the geometric normal facing the camera and the hit distance of the ray
+ * through the pixel centre in frame `which` (0 old, 1 new); (0, 0, 0, -1)
+ * where the ray leaves the scene.  Asynchronous. */
+rpi_status rpi_render_gbuffer(const rpi_scene* scene, const rpi_edit* edit, int32_t which, float* d_gbuf,
+                              void* hip_stream);
+
 /* Launch configuration chosen by the autotuner. */
 typedef struct {
   int32_t queue_cap;              /* samples per round */

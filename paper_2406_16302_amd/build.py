@@ -16,7 +16,7 @@ ARCH = "gfx950"
 # kernels round like the scalar reference (the BVH slab test opts back in).
 HIP_FLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC", "-ffp-contract=off",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["rpi_kernels.hip", "rpi_train.hip", "rpi_host.cpp"]
+SOURCES = ["rpi_kernels.hip", "rpi_train.hip", "rpi_denoise.hip", "rpi_host.cpp"]
 
 
 def _run(cmd):

@@ -1437,6 +1437,51 @@ extern "C" rpi_status rpi_render_residual(const rpi_scene* s, const rpi_edit* e,
   return RPI_OK;
 }
 
+// ------------------------------------------------------------------ residual denoiser
+extern "C" rpi_status rpi_render_gbuffer(const rpi_scene* s, const rpi_edit* e, int32_t which, float* d_gbuf,
+                                         void* stream) {
+  if (!s || !d_gbuf) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  if (which != 0 && which != 1) return fail(RPI_ERR_INVALID_ARG, "which must be 0 (old frame) or 1 (new frame)");
+  const float* pose = (e && which == 1) ? e->pose_new : kIdentity;
+  const Material m = (e && which == 1) ? e->new_mat : s->obj_mat;
+  const DevFrame F = make_frame(s, pose, pose, m, false);
+  launch_gbuffer(s->dev, F, (float4*)d_gbuf, (hipStream_t)stream);
+  hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
+  return RPI_OK;
+}
+
+extern "C" rpi_status rpi_denoise_residual(const rpi_scene* s, const rpi_edit* e, const float* d_a, const float* d_b,
+                                           const rpi_denoise_params* dp, float* d_out, void* stream) {
+  if (!s || !e || !d_a || !d_b || !d_out) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  rpi_denoise_params q{5, 64.0f, 0.1f, 4.0f};
+  if (dp) {
+    if (dp->iterations) q.iterations = dp->iterations;
+    if (dp->sigma_normal > 0) q.sigma_normal = dp->sigma_normal;
+    if (dp->sigma_depth > 0) q.sigma_depth = dp->sigma_depth;
+    if (dp->sigma_value > 0) q.sigma_value = dp->sigma_value;
+    if (dp->iterations < 0 || dp->iterations > 10 || !std::isfinite(dp->sigma_normal) ||
+        !std::isfinite(dp->sigma_depth) || !std::isfinite(dp->sigma_value) || dp->sigma_normal < 0 ||
+        dp->sigma_depth < 0 || dp->sigma_value < 0)
+      return fail(RPI_ERR_INVALID_ARG, "bad denoise parameters");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int W = s->W, H = s->H;
+  const size_t px = (size_t)W * H;
+  void* mem = nullptr;
+  rpi_status rc = dev_alloc(s, 3 * px * sizeof(float4), st, true, &mem);
+  if (rc) return rc;
+  float4* g = (float4*)mem;
+  const DevFrame F = make_frame(s, e->pose_new, e->pose_new, e->new_mat, false);
+  launch_gbuffer(s->dev, F, g, st);
+  launch_denoise(d_a, d_b, g, g + px, g + 2 * px, W, H, q.iterations, q.sigma_normal, q.sigma_depth, q.sigma_value,
+                 d_out, st);
+  dev_free(s, mem, st, true);
+  hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return fail(RPI_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
+  return RPI_OK;
+}
+
 // ------------------------------------------------------------------ allocation-free variant
 // For callers that cannot allocate device memory (code under graph capture,
 // tight serving loops): the workspace of rpi_render_residual_noalloc lives in

@@ -295,6 +295,11 @@ void launch_frame(const FrameArgs& A, hipStream_t st);
 void launch_proposal_pdf(const WalkArgs& A, int blocks, hipStream_t st);
 void launch_t8_start(const WalkArgs& A, int blocks, hipStream_t st);
 
+// residual denoiser (rpi_denoise.hip)
+void launch_gbuffer(const DevScene& S, const DevFrame& F, float4* g, hipStream_t st);
+void launch_denoise(const float* a, const float* b, const float4* g, float4* buf0, float4* buf1, int W, int H,
+                    int iterations, float sigma_n, float sigma_z, float sigma_l, float* out, hipStream_t st);
+
 // learned proposal (rpi_train.hip)
 constexpr int kMlpNParam = 11368;
 constexpr int kMlpHalfElems = 64 * 16 + 64 * 64 + 64 * 64 + 48 * 64 + 64 * 64 + 64 * 64 + 64 * 48;  // BF16 block

@@ -130,6 +130,11 @@ def torch_allocator():
     return a
 
 
+class DenoiseParams(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("sigma_normal", C.c_float), ("sigma_depth", C.c_float),
+                ("sigma_value", C.c_float)]
+
+
 class Job(C.Structure):
     _fields_ = [("pose_old", C.c_float * 12), ("pose_new", C.c_float * 12), ("width", C.c_int32),
                 ("height", C.c_int32), ("d_out", C.c_void_p)]
@@ -161,6 +166,8 @@ def load_library():
         L.rpi_autotune.argtypes = [vp, vp, C.POINTER(Params), C.POINTER(Tuning), vp]
         L.rpi_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.rpi_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.rpi_denoise_residual.argtypes = [vp, vp, vp, vp, C.POINTER(DenoiseParams), vp, vp]
+        L.rpi_render_gbuffer.argtypes = [vp, vp, C.c_int32, vp, vp]
         L.rpi_proposal_create.argtypes = [vp, vp, C.c_uint64, C.POINTER(vp)]
         L.rpi_proposal_destroy.argtypes = [vp]
         L.rpi_proposal_set_weights.argtypes = [vp, vp]
@@ -170,7 +177,7 @@ def load_library():
         L.rpi_proposal_train.argtypes = [vp, vp, C.c_int64, C.POINTER(TrainParams), vp, vp]
         L.rpi_last_error.restype = C.c_char_p
         L.rpi_version.restype = C.c_char_p
-        for f in ("rpi_get_tuning", "rpi_render_residual_noalloc", "rpi_render_frame_difference", "rpi_sync_status", "rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
+        for f in ("rpi_denoise_residual", "rpi_render_gbuffer", "rpi_get_tuning", "rpi_render_residual_noalloc", "rpi_render_frame_difference", "rpi_sync_status", "rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
                   "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records",
                   "rpi_autotune", "rpi_set_tuning", "rpi_proposal_create", "rpi_proposal_destroy", "rpi_proposal_set_weights",
                   "rpi_proposal_get_weights", "rpi_proposal_forward", "rpi_proposal_loss_grad",
@@ -298,6 +305,22 @@ def render_frame_difference(scene: Scene, edit: Edit, correlated: bool, params: 
     L = load_library()
     _check(L.rpi_render_frame_difference(scene.h, edit.h, 1 if correlated else 0, C.byref(params),
                                          _devptr(out, scene.width * scene.height * 3), _stream(stream)))
+
+
+def denoise_residual(scene: Scene, edit: Edit, a, b, out, iterations=0, sigma_normal=0.0, sigma_depth=0.0,
+                     sigma_value=0.0, stream=None):
+    """rpi_denoise_residual: R = a + b (two independent half estimates)
+    filtered with the residual-aware a-trous filter into out."""
+    n = scene.width * scene.height * 3
+    dp = DenoiseParams(int(iterations), float(sigma_normal), float(sigma_depth), float(sigma_value))
+    _check(load_library().rpi_denoise_residual(scene.h, edit.h, _devptr(a, n), _devptr(b, n), C.byref(dp),
+                                               _devptr(out, n), _stream(stream)))
+
+
+def render_gbuffer(scene: Scene, edit: Edit | None, which: int, out, stream=None):
+    """rpi_render_gbuffer: normal (facing the camera) and hit distance per pixel centre."""
+    _check(load_library().rpi_render_gbuffer(scene.h, edit.h if edit is not None else None, int(which),
+                                             _devptr(out, scene.width * scene.height * 4), _stream(stream)))
 
 
 def sync_status(stream=None):
