@@ -21,7 +21,8 @@ learned proposal, all against a reference residual of 64 times the budget:
   cornell_sweep    Cornell box, displacement sweep with and without mapping
 Equal-time MSE: each method's MSE at its own budget, scaled by its device
 time to the estimator's (MSE x time is constant for an unbiased Monte Carlo
-estimator), so MSE_equal_time = MSE * t_method / t_estimator.
+estimator), so MSE_equal_time = MSE * t_method / t_estimator.  The denoised
+residual (biased) is listed at its own budget and time.
 
 The CPU oracle is timed on the host cores (all of them, and one) on bounded
 samples of the clutter workload.  Prints one JSON line.
@@ -300,6 +301,19 @@ def bench_single(name, args):
             methods["residual_no_mapping"] = (mse(out, ref), t_nm)
             spp_used["residual_no_mapping"] = ws.spp
         if name != "proposal":
+            # the residual-aware denoiser on the same budget: two half estimates, then the filter
+            N = ws.spp * sc.width * sc.height
+            ha, hb, dn = torch.zeros_like(out), torch.zeros_like(out), torch.zeros_like(out)
+            pa = native.Params.make(ws.spp, ws.depth, ws.seed, mask=mask, flags=base, sample_end=N // 2)
+            pb = native.Params.make(ws.spp, ws.depth, ws.seed, mask=mask, flags=base, sample_begin=N // 2)
+
+            def halves_and_filter():
+                native.render_residual(sc, ed, pa, ha)
+                native.render_residual(sc, ed, pb, hb)
+                native.denoise_residual(sc, ed, ha, hb, dn)
+            t_dn = device_ms(halves_and_filter, reps=2)
+            methods["residual_denoised"] = (mse(dn, ref), t_dn)
+            spp_used["residual_denoised"] = ws.spp
             for k, (m, t, s) in pt_baselines(native, sc, ed, 4, ws.depth, ref, t_res, 4242).items():
                 methods[k] = (m, t)
                 spp_used[k] = s

@@ -282,10 +282,10 @@ rpi_status rpi_render_residual_batch(const rpi_scene* scene, const rpi_job* jobs
  * Errors: INVALID_ARG (null pointers, iterations outside 0..10, negative or
  * non-finite sigmas). */
 typedef struct {
-  int32_t iterations;  /* a-trous passes (strides 1, 2, 4, ...), 0: 5 */
+  int32_t iterations;  /* a-trous passes (strides 1, 2, 4, ...), 0: 3 */
   float sigma_normal;  /* exponent of the normal weight max(0, n_p . n_q)^sigma, 0: 64 */
   float sigma_depth;   /* hit-distance tolerance relative to the centre's distance, 0: 0.1 */
-  float sigma_value;   /* luminance tolerance in standard deviations of the centre's residual, 0: 4 */
+  float sigma_value;   /* luminance tolerance in standard deviations of the centre's residual, 0: 2 */
 } rpi_denoise_params;
 
 rpi_status rpi_denoise_residual(const rpi_scene* scene, const rpi_edit* edit, const float* d_a, const float* d_b,

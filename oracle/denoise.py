@@ -70,7 +70,7 @@ def gbuffer(osc, scene, pose):
     return g.reshape(scene.height, scene.width, 4)
 
 
-def denoise(a, b, g, iterations=5, sigma_n=64.0, sigma_z=0.1, sigma_l=4.0):
+def denoise(a, b, g, iterations=3, sigma_n=64.0, sigma_z=0.1, sigma_l=2.0):
     """The filter as defined in the module docstring (float64, one tap at a time)."""
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void atrous_kernel(AtrousArgs A) {
         // the centre's estimate are edges (zero variance: only equal values)
         const float lq = (x.x + x.y + x.z) * (1.0f / 3.0f);
         const float dl = fabsf(lc - lq);
-        if (dl > 0.0f) w *= expf(-dl / (A.sigma_l * sd + 1e-30f));
+        if (dl > 0.0f) w = sd > 0.0f ? w * expf(-dl / (A.sigma_l * sd)) : 0.0f;
       }
       sw += w;
       sr += w * x.x;

@@ -1454,7 +1454,7 @@ extern "C" rpi_status rpi_render_gbuffer(const rpi_scene* s, const rpi_edit* e, 
 extern "C" rpi_status rpi_denoise_residual(const rpi_scene* s, const rpi_edit* e, const float* d_a, const float* d_b,
                                            const rpi_denoise_params* dp, float* d_out, void* stream) {
   if (!s || !e || !d_a || !d_b || !d_out) return fail(RPI_ERR_INVALID_ARG, "null argument");
-  rpi_denoise_params q{5, 64.0f, 0.1f, 4.0f};
+  rpi_denoise_params q{3, 64.0f, 0.1f, 2.0f};
   if (dp) {
     if (dp->iterations) q.iterations = dp->iterations;
     if (dp->sigma_normal > 0) q.sigma_normal = dp->sigma_normal;

@@ -74,26 +74,45 @@ def test_filter_matches_its_definition():
     assert rel_l2(out.cpu().numpy().astype(np.float64), ref3) < 1e-4
 
 
-def test_denoising_lowers_the_error_and_keeps_static_pixels_at_zero():
+@pytest.mark.parametrize("name,spp,ref_spp,gain", [("cornell_material", 4, 1024, 0.3),
+                                                    ("clutter_motion", 4, 256, 0.85)])
+def test_denoising_lowers_the_error_and_keeps_static_pixels_at_zero(name, spp, ref_spp, gain):
+    """MSE against a high-sample reference, raw and denoised (default
+    parameters).  The gain depends on the residual: smooth indirect changes
+    (the material edit) denoise well, the sharp shadow boundaries of a moving
+    object less so (filtering across them trades noise for bias)."""
     from paper_2406_16302_amd import native
-    ws = scenes.clutter_motion(width=128, height=128, depth=5)
+    if name == "cornell_material":
+        ws = scenes.cornell_material(width=96, height=96, depth=5)
+        mk = lambda s, spp_, **kw: native.Params.make(spp_, ws.depth, s, mask=0x07, flags=0, **kw)
+    else:
+        ws = scenes.clutter_motion(width=160, height=160, depth=4, n_spheres=60)
+        mk = lambda s, spp_, **kw: native.Params.make(spp_, ws.depth, s, **kw)
     sc = native.Scene(ws.scene)
     ed = native.Edit(sc, ws.edit)
-    ref = torch.zeros((128, 128, 3), dtype=torch.float64, device="cuda")
-    tmp = torch.zeros((128, 128, 3), dtype=torch.float32, device="cuda")
-    for k in range(16):
-        native.render_residual(sc, ed, native.Params.make(64, ws.depth, 70_000 + k), tmp)
+    H, W = sc.height, sc.width
+    ref = torch.zeros((H, W, 3), dtype=torch.float64, device="cuda")
+    tmp = torch.zeros((H, W, 3), dtype=torch.float32, device="cuda")
+    for k in range(8):
+        native.render_residual(sc, ed, mk(70_000 + k, ref_spp // 8), tmp)
         ref += tmp.double()
-    ref /= 16
+    ref /= 8
     raw, den = [], []
+    N = spp * W * H
     for k in range(4):
-        a, b = _halves(native, sc, ed, ws, 8, 100 + k)
+        a = torch.zeros((H, W, 3), dtype=torch.float32, device="cuda")
+        b = torch.zeros_like(a)
+        native.render_residual(sc, ed, mk(100 + k, spp, sample_end=N // 2), a)
+        native.render_residual(sc, ed, mk(100 + k, spp, sample_begin=N // 2), b)
         out = torch.zeros_like(a)
         native.denoise_residual(sc, ed, a, b, out)
         raw.append(((a + b).double() - ref).pow(2).mean().item())
         den.append((out.double() - ref).pow(2).mean().item())
-        zero = ((a == 0) & (b == 0)).all(-1)
-        # pixels far from any dynamic path stay exactly zero
-        assert (out[zero] == 0).float().mean().item() > 0.9
-    print("MSE raw %.4g, denoised %.4g" % (np.mean(raw), np.mean(den)))
-    assert np.mean(den) < 0.5 * np.mean(raw)
+        # pixels farther than the filter's reach (one pixel per pass) from
+        # every pixel a dynamic path reached stay exactly zero
+        reached = ((a != 0) | (b != 0)).any(-1).float()[None, None]
+        near = torch.nn.functional.max_pool2d(reached, 9, stride=1, padding=4)[0, 0] > 0
+        static = ~near
+        assert (out[static] == 0).all()
+    print("%s: MSE raw %.4g, denoised %.4g" % (name, np.mean(raw), np.mean(den)))
+    assert np.mean(den) < gain * np.mean(raw)
