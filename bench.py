@@ -289,6 +289,14 @@ def bench_single(name, args):
         native.render_residual(sc, ed, params(0), out)
         methods = {"residual": (mse(out, ref), t_res)}
         spp_used = {"residual": ws.spp}
+        # residual-aware allocation of the techniques' sample counts (pilot of spp/8)
+        counts = native.allocate_samples(sc, ed, params(0), pilot_spp=max(2, ws.spp // 8))
+        pal = native.Params.make(ws.spp, ws.depth, ws.seed, mask=mask, flags=base, proposal=prop,
+                                 technique_spp=counts)
+        t_al = device_ms(lambda: native.render_residual(sc, ed, pal, out), reps=3)
+        native.render_residual(sc, ed, pal, out)
+        methods["residual_allocated"] = (mse(out, ref), t_al)
+        spp_used["residual_allocated"] = counts
         if name == "proposal":
             t_plain = device_ms(lambda: native.render_residual(sc, ed, params(0, None, ref_mask), out), reps=3)
             native.render_residual(sc, ed, params(0, None, ref_mask), out)

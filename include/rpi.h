@@ -148,6 +148,14 @@ typedef struct {
    * need more than 16384 tiles).  The image does not depend on it beyond
    * float rounding. */
   int32_t tile;
+  /* Samples per pixel of technique t (index t-1); 0: spp.  Techniques then
+   * draw unequal sample counts n_t = technique_spp[t-1] * W * H, and every
+   * strategy density enters the MIS sums weighted by n_t / (spp * W * H):
+   * the balance heuristic over unequal counts (Veach 1997, Sec. 9.2), which
+   * keeps the estimator unbiased.  Needs the full sample range
+   * (sample_begin 0, sample_end < 0); not available for batches.  See
+   * rpi_allocate_samples. */
+  int32_t technique_spp[8];
 } rpi_render_params;
 
 typedef struct {
@@ -172,6 +180,8 @@ typedef struct {
   int64_t kernel_tris[32];
   int64_t kernel_bytes_written[32];
   int64_t train_records;  /* training records produced (may exceed train_capacity) */
+  double technique_ms[9];  /* with RPI_FLAG_TIME_KERNELS: device time of each technique's launches
+                              (start and walk phases, connect, splat of its rounds), index 1..8 */
 } rpi_stats;
 
 /* Copy, validate and upload a scene: the static geometry and the object
@@ -263,6 +273,22 @@ typedef struct {
  * tuned).  Errors as above; records and per-technique images are UNSUPPORTED. */
 rpi_status rpi_render_residual_batch(const rpi_scene* scene, const rpi_job* jobs, int32_t num_jobs,
                                      const rpi_render_params* params, rpi_stats* stats, void* hip_stream);
+
+/* Residual-aware sample allocation (addition beyond the paper, which
+ * gives every technique the same sample count).  A pilot of pilot_spp
+ * samples per pixel, in two independent halves with per-technique images,
+ * measures for each enabled technique t the variance V_t of its MIS-weighted
+ * share of the residual (the squared difference of the halves, summed over
+ * pixels) and its device time per sample c_t; technique_spp_out[t-1]
+ * receives n_t / (W*H) with n_t ~ sqrt(V_t / c_t) (Neyman allocation over
+ * the techniques taken as strata), scaled so that the total cost equals that
+ * of params->spp for every technique, rounded, and kept in [1, 64 spp]
+ * (0 for techniques that do not run).  Pass the result in
+ * params.technique_spp: the balance heuristic over the unequal counts keeps
+ * the estimator unbiased.  Synchronises hip_stream.  Errors as
+ * rpi_render_residual; INVALID_ARG for pilot_spp < 2. */
+rpi_status rpi_allocate_samples(const rpi_scene* scene, const rpi_edit* edit, const rpi_render_params* params,
+                                int32_t pilot_spp, int32_t* technique_spp_out, void* hip_stream);
 
 /* Residual-aware denoising (addition beyond the paper, which leaves the
  * residual's noise around the edit to an external denoiser, Sec. 6,

@@ -1026,6 +1026,10 @@ struct MisOpts {
   double p_dir;    // technique (6) direction pdf, uniform sphere
   const Proposal* prop;  // technique (8): learned lobes (null: off)
   const Frame* frame;
+  // samples of technique t relative to the base count N: the balance
+  // heuristic over unequal sample counts n_t weighs density p_t by n_t
+  // (Veach 1997, Sec. 9.2), and the image divides by N
+  double ratio[9];
 };
 
 // Forward pdf a_i (1 <= i <= k-3): x_i generated from x_{i+1} by BSDF
@@ -1137,7 +1141,7 @@ static MisTerms mis_terms(const Scene& S, const Frame& F, const Path& P, const M
       }
     }
   }
-  for (int t = 1; t <= 8; ++t) r.total += r.by_tech[t];
+  for (int t = 1; t <= 8; ++t) r.total += O.ratio[t] * r.by_tech[t];
   return r;
 }
 
@@ -1776,6 +1780,7 @@ struct Params {
   int threads;
   int material_mode;
   int no_mapping;  // the path-mapping ablation: every pair is rejected
+  int32_t tech_spp[8];  // samples per pixel of technique t (index t-1); 0: spp
 };
 
 struct Record {
@@ -1834,7 +1839,10 @@ static void train_record(const Scene& S, const Frame& F, const Proposal& Pr, con
 static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int dir, int tech, double sigma,
                            const Params& Pm, int64_t s0, int64_t s1, double N, double* img, double* tech_img,
                            Stats& st, std::vector<Record>* recs, const Proposal* prop) {
-  MisOpts O{Pm.mask, F.ghosts, 1.0 / (4.0 * PI), prop, &F};
+  MisOpts O{Pm.mask, F.ghosts, 1.0 / (4.0 * PI), prop, &F, {}};
+  for (int t = 0; t <= 8; ++t) O.ratio[t] = 1.0;
+  for (int t = 1; t <= 8; ++t)
+    if (Pm.tech_spp[t - 1] > 0) O.ratio[t] = (double)Pm.tech_spp[t - 1] / (double)Pm.spp;
   MapParams M{Pm.alpha_min, Pm.d_min, Pm.jac_max};
   double c = Pm.material_mode ? 1.0 : (double)Pm.c_weight;
   int P = S.cam.W * S.cam.H;
@@ -2226,7 +2234,9 @@ int orc_render_residual(void* sp, const float* pose_old, const float* pose_new, 
       if (!((pm->mask >> (t - 1)) & 1u)) continue;
       if (pm->material_mode && t >= 4 && t <= 6) continue;
       if (t == 8 && !mlp) continue;
-      parallel(pm->threads, s0, s1, P, img, tech_img, 8, st,
+      // technique t's own sample count (the full stream only): tech_spp x pixels
+      const int64_t s1t = pm->tech_spp[t - 1] > 0 ? (int64_t)pm->tech_spp[t - 1] * P : s1;
+      parallel(pm->threads, s0, s1t, P, img, tech_img, 8, st,
                [&](int64_t a, int64_t b, double* im, double* ti, Stats& s) {
                  residual_range(S, F, Fp, d, t, sigma, *pm, a, b, (double)N, im, ti, s, want ? &rv : nullptr,
                                 &prop);

@@ -843,6 +843,15 @@ static rpi_status check_params(const rpi_scene* s, const rpi_render_params* p) {
     return fail(RPI_ERR_INVALID_ARG, "RPI_FLAG_PER_TECHNIQUE needs d_technique_images");
   if ((p->flags & RPI_FLAG_NO_MAPPING) && !(p->flags & RPI_FLAG_TWO_WAY))
     return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING needs RPI_FLAG_TWO_WAY (a motion edit sampled in both frames)");
+  bool uneq = false;
+  for (int t = 0; t < kTechs; ++t) {
+    if (p->technique_spp[t] < 0) return fail(RPI_ERR_INVALID_ARG, "negative technique_spp");
+    if ((int64_t)p->technique_spp[t] * s->W * s->H > 0xffffffffLL)
+      return fail(RPI_ERR_UNSUPPORTED, "more than 2^32 samples per technique stream");
+    uneq |= p->technique_spp[t] > 0;
+  }
+  if (uneq && (p->sample_begin != 0 || p->sample_end >= 0))
+    return fail(RPI_ERR_INVALID_ARG, "technique_spp needs the full sample range");
   if (!(p->jac_max > 1.0f) || !(p->alpha_min >= 0.0f) || !(p->c_weight > 0.0f && p->c_weight < 1.0f))
     return fail(RPI_ERR_INVALID_ARG, "bad rejection / weight parameters");
   const int64_t N = (int64_t)p->spp * s->W * s->H;
@@ -1097,6 +1106,8 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
     J.tech_images = q.tech;
     J.fx_scale = (float)(1099511627776.0 / (double)s->lmax);  // 2^40 / largest emission
     J.fx_unit = (double)s->lmax / 1099511627776.0;
+    for (int t = 0; t < kTechs; ++t)
+      J.tech_ratio[t] = p->technique_spp[t] > 0 ? (float)((double)p->technique_spp[t] / (double)p->spp) : 1.0f;
     const int64_t N = (int64_t)p->spp * q.W * q.H;
     if (N > 0xffffffffLL) return fail(RPI_ERR_UNSUPPORTED, "more than 2^32 samples per technique stream");
     J.s0 = p->sample_begin;
@@ -1124,14 +1135,19 @@ static rpi_status make_plan(const rpi_scene* s, const std::vector<JobSpec>& js, 
     for (int j = 0; j < nj; ++j)
       for (int d = 0; d < 2; ++d) {
         pre[2 * j + d] = run;
-        if (on && (d == 0 || two_way)) run += (pl.jobs[j].s1 - pl.jobs[j].s0 + kItem - 1) / kItem;
+        const int64_t n = p->technique_spp[t - 1] > 0 ? (int64_t)p->technique_spp[t - 1] * js[j].W * js[j].H
+                                                       : pl.jobs[j].s1 - pl.jobs[j].s0;
+        if (on && (d == 0 || two_way)) run += (n + kItem - 1) / kItem;
       }
     pre[2 * nj] = run;
   }
   int maxp = 0;
   for (int t = 1; t <= kTechs; ++t) maxp = std::max(maxp, max_pairs_per_sample(t, p->max_depth));
   int64_t total = 0;
-  for (int j = 0; j < nj; ++j) total = std::max(total, pl.jobs[j].s1 - pl.jobs[j].s0);
+  for (int j = 0; j < nj; ++j) {
+    total = std::max(total, pl.jobs[j].s1 - pl.jobs[j].s0);
+    for (int t = 0; t < kTechs; ++t) total = std::max(total, (int64_t)p->technique_spp[t] * js[j].W * js[j].H);
+  }
   int64_t Q = std::min<int64_t>(tu.Q, std::max<int64_t>(total * nj * 2, kItem));
   Q = (Q + kItem - 1) / kItem * kItem;
   Q = std::min<int64_t>(Q, kMaxRound);
@@ -1149,6 +1165,7 @@ struct RunOpts {
 
 struct Timed {
   int kid;
+  int tech;  // the technique whose round launched it
   hipEvent_t a, b;
 };
 
@@ -1175,6 +1192,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
   A.d_min = p->d_min;
   A.jac_max = p->jac_max;
   A.no_mapping = (p->flags & RPI_FLAG_NO_MAPPING) ? 1 : 0;
+  A.tech_spp = 0;
   A.count_work = o.count_work ? 1 : 0;
   A.keep_records = o.keep ? 1 : 0;
   const bool t8 = (p->strategy_mask & 0x80u) && p->proposal;
@@ -1217,7 +1235,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       launch();
       return RPI_OK;
     }
-    Timed t{kid, nullptr, nullptr};
+    Timed t{kid, A.tech, nullptr, nullptr};
     HIP_OK(hipEventCreate(&t.a));
     HIP_OK(hipEventCreate(&t.b));
     HIP_OK(hipEventRecord(t.a, st));
@@ -1231,6 +1249,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
     const int64_t T = pre_h[2 * nj];
     if (T == 0) continue;
     A.tech = t;
+    A.tech_spp = p->technique_spp[t - 1];
     A.item_prefix = w.prefix + (size_t)(t - 1) * (2 * nj + 1);
     for (int64_t i0 = 0; i0 < T; i0 += R) {
       A.item0 = i0;
@@ -1330,9 +1349,11 @@ static void fill_stats(rpi_stats* stats, const DevStats& ds, const Plan& pl, con
     const int64_t* pre = pl.prefix.data() + (size_t)(t - 1) * (2 * nj + 1);
     for (int j = 0; j < nj; ++j)
       for (int d = 0; d < 2; ++d)
-        if (pre[2 * j + d + 1] > pre[2 * j + d]) stats->samples += pl.jobs[j].s1 - pl.jobs[j].s0;
+        if (pre[2 * j + d + 1] > pre[2 * j + d])
+          stats->samples += p->technique_spp[t - 1] > 0
+                                ? (int64_t)p->technique_spp[t - 1] * pl.jobs[j].W * pl.jobs[j].H
+                                : pl.jobs[j].s1 - pl.jobs[j].s0;
   }
-  (void)p;
 }
 
 // Direct (non-graph) execution of a batch of jobs with optional statistics.
@@ -1393,6 +1414,7 @@ static rpi_status run_jobs(const rpi_scene* s, const std::vector<JobSpec>& js, b
         HIP_OK(hipEventElapsedTime(&kms, t.a, t.b));
         stats->kernel_ms[t.kid] += kms;
         stats->kernel_launches[t.kid] += 1;
+        stats->technique_ms[t.tech] += kms;
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
       }
@@ -1433,6 +1455,81 @@ extern "C" rpi_status rpi_render_residual(const rpi_scene* s, const rpi_edit* e,
   if (p->flags & RPI_FLAG_RECORDS) {
     std::lock_guard<std::mutex> lk(const_cast<rpi_scene*>(s)->mu);
     const_cast<rpi_scene*>(s)->rec_host.swap(recs);
+  }
+  return RPI_OK;
+}
+
+// ------------------------------------------------------------------ residual-aware sample allocation
+extern "C" rpi_status rpi_allocate_samples(const rpi_scene* s, const rpi_edit* e, const rpi_render_params* p,
+                                           int32_t pilot_spp, int32_t* out, void* stream) {
+  if (!s || !e || !out) return fail(RPI_ERR_INVALID_ARG, "null argument");
+  rpi_status rc = check_params(s, p);
+  if (rc) return rc;
+  if (pilot_spp < 2) return fail(RPI_ERR_INVALID_ARG, "pilot_spp must be at least 2");
+  if (p->d_train_records) return fail(RPI_ERR_INVALID_ARG, "no training records in an allocation pilot");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t P = (int64_t)s->W * s->H;
+  const int64_t N = (int64_t)pilot_spp * P;
+  if (N > 0xffffffffLL) return fail(RPI_ERR_UNSUPPORTED, "pilot of more than 2^32 samples per stream");
+  // two independent halves of the pilot, each with its per-technique images
+  void* mem = nullptr;
+  const size_t img = (size_t)P * 3;
+  rc = dev_alloc(s, (2 * kTechs + 1) * img * sizeof(float), st, true, &mem);
+  if (rc) return rc;
+  float* ta = (float*)mem;
+  float* tb = ta + kTechs * img;
+  float* tot = tb + kTechs * img;
+  rpi_render_params q = *p;
+  q.spp = pilot_spp;
+  for (int t = 0; t < kTechs; ++t) q.technique_spp[t] = 0;
+  q.flags &= ~(uint32_t)(RPI_FLAG_ACCUMULATE | RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK);
+  q.flags |= RPI_FLAG_PER_TECHNIQUE | RPI_FLAG_TIME_KERNELS;
+  double ms[kTechs + 1] = {0};
+  for (int h = 0; h < 2; ++h) {
+    q.sample_begin = h ? N / 2 : 0;
+    q.sample_end = h ? N : N / 2;
+    q.d_technique_images = h ? tb : ta;
+    rpi_stats stt;
+    rc = rpi_render_residual(s, e, &q, tot, &stt, stream);
+    if (rc) {
+      dev_free(s, mem, st, true);
+      return rc;
+    }
+    for (int t = 1; t <= kTechs; ++t) ms[t] += stt.technique_ms[t];
+  }
+  std::vector<float> ha(kTechs * img), hb(kTechs * img);
+  hipError_t e1 = hipMemcpyAsync(ha.data(), ta, ha.size() * sizeof(float), hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipMemcpyAsync(hb.data(), tb, hb.size() * sizeof(float), hipMemcpyDeviceToHost, st);
+  hipError_t e3 = hipStreamSynchronize(st);
+  dev_free(s, mem, st, true);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+    return fail(RPI_ERR_DEVICE, "copying the pilot's technique images failed");
+  // Var of technique t's share of the pilot ~ sum over pixels of (a_t - b_t)^2;
+  // its cost per sample from its launches' device time.  Treating the
+  // techniques as strata, the variance with n_t samples is V_t N / n_t at a
+  // cost c_t n_t, minimised for a fixed cost by n_t ~ sqrt(V_t / c_t)
+  // (Neyman allocation); the total cost is kept at that of equal counts.
+  double x[kTechs + 1] = {0}, c[kTechs + 1] = {0};
+  double sc = 0.0, scx = 0.0;
+  for (int t = 1; t <= kTechs; ++t) {
+    if (!(ms[t] > 0.0)) continue;
+    double v = 0.0;
+    const float* a = ha.data() + (size_t)(t - 1) * img;
+    const float* b = hb.data() + (size_t)(t - 1) * img;
+    for (size_t i = 0; i < img; ++i) v += ((double)a[i] - b[i]) * ((double)a[i] - b[i]);
+    c[t] = ms[t] / (double)N;
+    x[t] = std::sqrt(v / c[t]);
+    sc += c[t];
+    scx += c[t] * x[t];
+  }
+  for (int t = 1; t <= kTechs; ++t) {
+    if (!(c[t] > 0.0)) {
+      out[t - 1] = 0;
+      continue;
+    }
+    const double n = scx > 0.0 ? (double)p->spp * P * sc / scx * x[t] : (double)p->spp * P;
+    const double spp_t = std::round(n / (double)P);
+    out[t - 1] = (int32_t)std::min<double>(std::max<double>(spp_t, 1.0), 64.0 * p->spp);
   }
   return RPI_OK;
 }
@@ -1651,8 +1748,9 @@ static Tuning scene_tuning(const rpi_scene* s, const rpi_render_params* p) {
 static rpi_status autotune_job(rpi_scene* s, const JobSpec& j, bool material_mode, const rpi_render_params* p,
                                hipStream_t st, rpi_tuning* out) {
   rpi_render_params q = *p;
-  q.flags &= ~(uint32_t)(RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_ACCUMULATE);
+  q.flags &= ~(uint32_t)(RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_ACCUMULATE | RPI_FLAG_PER_TECHNIQUE);
   q.flags |= RPI_FLAG_ACCUMULATE;
+  for (int t = 0; t < kTechs; ++t) q.technique_spp[t] = 0;
   const int64_t N = (int64_t)p->spp * j.W * j.H;
   q.sample_begin = 0;
   // up to 2^24 samples per stream: the largest round holds that many samples
@@ -1775,6 +1873,8 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
       ((p->strategy_mask & 0x80u) && !p->proposal))
     return fail(RPI_ERR_INVALID_ARG, "bad params");
   if (p->d_train_records) return fail(RPI_ERR_UNSUPPORTED, "training-record collection is not available for batches");
+  for (int t = 0; t < kTechs; ++t)
+    if (p->technique_spp[t] != 0) return fail(RPI_ERR_UNSUPPORTED, "technique_spp is not available for batches");
   if (p->flags & (RPI_FLAG_RECORDS | RPI_FLAG_PER_TECHNIQUE))
     return fail(RPI_ERR_UNSUPPORTED, "records and per-technique images are not available for batches");
   if (p->tile != 0 && p->tile != 16 && p->tile != 32) return fail(RPI_ERR_INVALID_ARG, "tile must be 0, 16 or 32");

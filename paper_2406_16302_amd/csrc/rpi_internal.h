@@ -169,6 +169,10 @@ struct DevJob {
   unsigned long long* acc;
   float fx_scale;   // fixed-point units per unit of radiance: 2^40 / (largest emission of the scene)
   double fx_unit;   // 1 / fx_scale
+  // samples of technique t (index t-1) relative to the base count N: the
+  // weight of its density in the MIS sums (balance heuristic over unequal
+  // sample counts; all 1 by default)
+  float tech_ratio[8];
   int64_t s0, s1;
   float inv_n;      // 1 / (spp * W * H)
   int32_t tile0;    // first tile of this job in the batch-wide tile index space
@@ -235,6 +239,7 @@ struct WalkArgs {
   float cweight;
   float alpha_min, d_min, jac_max;
   int32_t no_mapping;          // every path rejected (the path-mapping ablation)
+  int32_t tech_spp;            // this technique's samples per pixel (0: the job's sample range)
   int32_t count_work;
   int32_t keep_records;
   MlpDev mlp;                  // technique (8) and its MIS term (mask bit 7)

@@ -732,7 +732,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_START_OCCUPANCY void walk_kernel(W
     const int dir = jd & 1;
     const int64_t smp = J.s0 + (g - A.item_prefix[jd]) * kItem + threadIdx.x;
     const int s = (int)it * kItem + threadIdx.x;
-    const bool active = smp < J.s1;
+    const bool active = smp < (A.tech_spp ? (int64_t)A.tech_spp * J.W * J.H : J.s1);
     const Ctx C{J.S, J.F[dir], A.W, A.depth};
     Lane L{C, Rng{A.k0, A.k1, (uint32_t)smp, ((uint32_t)TECH << 24) | ((uint32_t)dir << 23), A.job_base + (uint32_t)(jd >> 1)},
            s, stk, WorkCount{}, 0, 0, 0u, 0u, 0u, 0, smp, 0u};
@@ -1342,7 +1342,7 @@ __global__ __launch_bounds__(kTraceBlock) void t8_start_kernel(WalkArgs A) {
     const DevFrame& F = J.F[dir];
     const int64_t smp = J.s0 + (g - A.item_prefix[jd]) * kItem + threadIdx.x;
     const int s = (int)it * kItem + threadIdx.x;
-    const bool active = smp < J.s1;
+    const bool active = smp < (A.tech_spp ? (int64_t)A.tech_spp * J.W * J.H : J.s1);
     const Rng rng{A.k0, A.k1, (uint32_t)smp, (8u << 24) | ((uint32_t)dir << 23), A.job_base + (uint32_t)(jd >> 1)};
     float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     vec3 p = v3(0.f, 0.f, 0.f), n = v3(0.f, 0.f, 1.f);
@@ -1419,6 +1419,7 @@ struct CCtx {
   const MlpDev* mlp;  // training-record input normalisation (collection on), else null
   int train_weighting;
   int no_mapping;     // the path-mapping ablation: every pair rejected
+  const float* ratio; // [8]: samples of technique t / the base count (balance heuristic over unequal counts)
 };
 
 // q8a, q8b: the proposal's densities at x_1..x_4 and x_5 (technique (8) in the mask).
@@ -1620,21 +1621,24 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
 #pragma unroll
   for (int q = kMaxK - 2; q >= 2; --q) Bsuf[q] = (q <= k - 2) ? Bsuf[q + 1] * gen(q - 1, q, q - 2) : 1.0f;
   auto on = [&](int t) { return (A.mask >> (t - 1)) & 1u; };
+  // each strategy's density weighs by its sample count relative to the base
+  // count (the balance heuristic over unequal counts; 1 when they are equal)
+  const float* rt = A.ratio;
   float sum = 0.0f;
   float pgen = 0.0f;  // techniques (2), (3): density of the generating strategy
-  if (on(7)) sum += k == 2 ? pcam : pcam * Bsuf[2] * pL;
+  if (on(7)) sum += rt[6] * (k == 2 ? pcam : pcam * Bsuf[2] * pL);
 #pragma unroll
   for (int m = 1; m < kMaxK - 1; ++m) {
     if (m > k - 2 || !(v[m].md & kDynBit)) continue;
     if (m == k - 2) {
-      if (on(1)) sum += pL * pD * Apre[m - 1];
+      if (on(1)) sum += rt[0] * (pL * pD * Apre[m - 1]);
     } else if (m == 1) {
       if (on(2) && k >= 4) {
         const float t2 = pD * Bsuf[2] * pL;
-        sum += t2;
+        sum += rt[1] * t2;
         if (T == 2) pgen = t2;
       }
-      if (on(8)) sum += pD * q8a.x * to_area(1, 2, origin(1, 2)) * Bsuf[3] * pL;
+      if (on(8)) sum += rt[7] * (pD * q8a.x * to_area(1, 2, origin(1, 2)) * Bsuf[3] * pL);
     } else if (on(3) || on(8)) {
       const vec3 o = origin(m, m + 1);
       const vec3 w = unit(v[m + 1].p - o);
@@ -1642,10 +1646,10 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
       const float c = dot(v[m].n, w);
       if (on(3) && c > 0.0f) {
         const float t3 = pD * (c / kPi) * rest3;
-        sum += t3;
+        sum += rt[2] * t3;
         if (T == 3 && m == i + 2) pgen = t3;
       }
-      if (on(8)) sum += pD * (m == 2 ? q8a.y : m == 3 ? q8a.z : m == 4 ? q8a.w : q8b.x) * rest3;
+      if (on(8)) sum += rt[7] * (pD * (m == 2 ? q8a.y : m == 3 ? q8a.z : m == 4 ? q8a.w : q8b.x) * rest3);
     }
   }
   if (motion && k >= 3) {
@@ -1662,18 +1666,18 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
 #pragma unroll
           for (int q = 1; q < kMaxK; ++q)
             if (q == k - 3) ak = Apre[q];
-          sum += pL * pG * exw[a] * fabsf(dot(vl.n, unit(d))) / len2(d) * ak;
+          sum += rt[3] * (pL * pG * exw[a] * fabsf(dot(vl.n, unit(d))) / len2(d) * ak);
         }
       } else if (a == 0) {
         if (on(5)) {
           const vec3 d = v[1].p - C.eye;
-          sum += pG * exw[a] * fabsf(dot(v[1].n, unit(d))) / len2(d) * Bsuf[2] * pL;
+          sum += rt[4] * (pG * exw[a] * fabsf(dot(v[1].n, unit(d))) / len2(d) * Bsuf[2] * pL);
         }
       } else if (on(6)) {
         const vec3 d = v[a + 1].p - v[a].p;
         const vec3 w = unit(d);
         const float G = fabsf(dot(v[a].n, w)) * fabsf(dot(v[a + 1].n, w)) / len2(d);
-        sum += pG * pdir * G * exw[a] * Apre[a > 0 ? a - 1 : 0] * Bsuf[a + 2] * pL;
+        sum += rt[5] * (pG * pdir * G * exw[a] * Apre[a > 0 ? a - 1 : 0] * Bsuf[a + 2] * pL);
       }
     }
   }
@@ -1855,7 +1859,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_ker
       const int dir = jd & 1;
       const CCtx C{J.S, J.F[dir], J.F[1 - dir], A.W, A.tech, A.material_mode, A.mask, dir ? -1.0f : 1.0f,
                    A.cweight, J.inv_n, A.alpha_min, A.d_min, A.jac_max, jd >> 1, A.train ? &A.mlp : nullptr,
-                   A.train_weighting, A.no_mapping};
+                   A.train_weighting, A.no_mapping, J.tech_ratio};
       const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
       const float4 q8a = A.W.t8q ? A.W.t8q[2 * (size_t)idx] : z4, q8b = A.W.t8q ? A.W.t8q[2 * (size_t)idx + 1] : z4;
       float4 rec;

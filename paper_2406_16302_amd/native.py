@@ -47,19 +47,23 @@ class Params(C.Structure):
                 ("sample_begin", C.c_int64), ("sample_end", C.c_int64), ("queue_cap", C.c_int32),
                 ("job", C.c_uint32), ("proposal", C.c_void_p), ("d_train_records", C.c_void_p),
                 ("train_capacity", C.c_int64), ("train_weighting", C.c_int32),
-                ("d_technique_images", C.c_void_p), ("tile", C.c_int32)]
+                ("d_technique_images", C.c_void_p), ("tile", C.c_int32), ("technique_spp", C.c_int32 * 8)]
 
     @staticmethod
     def make(spp, depth, seed, mask=0x7F, flags=FLAG_TWO_WAY, alpha_min=0.2, d_min=-1.0, jac_max=10.0,
              c_weight=0.5, sample_begin=0, sample_end=-1, queue_cap=0, job=0, proposal=None, train_records=None,
-             train_weighting=0, technique_images=None, tile=0):
+             train_weighting=0, technique_images=None, tile=0, technique_spp=None):
         """proposal: a Proposal (technique 8 with mask bit 7); train_records: a
         float32 device tensor [cap, 10] receiving technique-3 training records;
         technique_images: a float32 device tensor [8, H, W, 3] (sets
-        FLAG_PER_TECHNIQUE)."""
+        FLAG_PER_TECHNIQUE); technique_spp: 8 per-technique samples per pixel
+        (0 = spp)."""
         p = Params(spp, depth, seed, mask, flags, alpha_min, d_min, jac_max, c_weight, sample_begin,
                    sample_end, queue_cap, job)
         p.tile = int(tile)
+        if technique_spp is not None:
+            for i, v in enumerate(technique_spp):
+                p.technique_spp[i] = int(v)
         if technique_images is not None:
             p.d_technique_images = _devptr(technique_images, technique_images.numel()).value
             p._technique_ref = technique_images
@@ -81,7 +85,8 @@ class Stats(C.Structure):
                 ("nodes_visited", C.c_int64), ("tris_tested", C.c_int64), ("milliseconds", C.c_double),
                 ("kernel_ms", C.c_double * 32), ("kernel_launches", C.c_int64 * 32),
                 ("kernel_nodes", C.c_int64 * 32), ("kernel_tris", C.c_int64 * 32),
-                ("kernel_bytes_written", C.c_int64 * 32), ("train_records", C.c_int64)]
+                ("kernel_bytes_written", C.c_int64 * 32), ("train_records", C.c_int64),
+                ("technique_ms", C.c_double * 9)]
 
     def as_dict(self):
         return {"samples": self.samples, "paths": self.paths, "accepted": self.accepted,
@@ -90,7 +95,7 @@ class Stats(C.Structure):
                 "milliseconds": self.milliseconds, "kernel_ms": list(self.kernel_ms),
                 "kernel_launches": list(self.kernel_launches), "kernel_nodes": list(self.kernel_nodes),
                 "kernel_tris": list(self.kernel_tris), "kernel_bytes_written": list(self.kernel_bytes_written),
-                "train_records": self.train_records}
+                "train_records": self.train_records, "technique_ms": list(self.technique_ms)}
 
 
 class Tuning(C.Structure):
@@ -166,6 +171,7 @@ def load_library():
         L.rpi_autotune.argtypes = [vp, vp, C.POINTER(Params), C.POINTER(Tuning), vp]
         L.rpi_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.rpi_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.rpi_allocate_samples.argtypes = [vp, vp, C.POINTER(Params), C.c_int32, C.POINTER(C.c_int32), vp]
         L.rpi_denoise_residual.argtypes = [vp, vp, vp, vp, C.POINTER(DenoiseParams), vp, vp]
         L.rpi_render_gbuffer.argtypes = [vp, vp, C.c_int32, vp, vp]
         L.rpi_proposal_create.argtypes = [vp, vp, C.c_uint64, C.POINTER(vp)]
@@ -177,7 +183,7 @@ def load_library():
         L.rpi_proposal_train.argtypes = [vp, vp, C.c_int64, C.POINTER(TrainParams), vp, vp]
         L.rpi_last_error.restype = C.c_char_p
         L.rpi_version.restype = C.c_char_p
-        for f in ("rpi_denoise_residual", "rpi_render_gbuffer", "rpi_get_tuning", "rpi_render_residual_noalloc", "rpi_render_frame_difference", "rpi_sync_status", "rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
+        for f in ("rpi_allocate_samples", "rpi_denoise_residual", "rpi_render_gbuffer", "rpi_get_tuning", "rpi_render_residual_noalloc", "rpi_render_frame_difference", "rpi_sync_status", "rpi_build_scene", "rpi_destroy_scene", "rpi_apply_edit", "rpi_destroy_edit",
                   "rpi_render_residual", "rpi_render_frame", "rpi_render_residual_batch", "rpi_get_records",
                   "rpi_autotune", "rpi_set_tuning", "rpi_proposal_create", "rpi_proposal_destroy", "rpi_proposal_set_weights",
                   "rpi_proposal_get_weights", "rpi_proposal_forward", "rpi_proposal_loss_grad",
@@ -305,6 +311,14 @@ def render_frame_difference(scene: Scene, edit: Edit, correlated: bool, params: 
     L = load_library()
     _check(L.rpi_render_frame_difference(scene.h, edit.h, 1 if correlated else 0, C.byref(params),
                                          _devptr(out, scene.width * scene.height * 3), _stream(stream)))
+
+
+def allocate_samples(scene: Scene, edit: Edit, params: Params, pilot_spp=4, stream=None):
+    """rpi_allocate_samples: per-technique samples per pixel from a pilot."""
+    out = (C.c_int32 * 8)()
+    _check(load_library().rpi_allocate_samples(scene.h, edit.h, C.byref(params), int(pilot_spp), out,
+                                               _stream(stream)))
+    return [int(x) for x in out]
 
 
 def denoise_residual(scene: Scene, edit: Edit, a, b, out, iterations=0, sigma_normal=0.0, sigma_depth=0.0,

@@ -156,3 +156,61 @@ def test_sync_status_reports_ok():
     native.sync_status()
     s = torch.cuda.Stream()
     native.sync_status(s)
+
+
+@pytest.mark.parametrize("name", ["cornell_motion", "cornell_material"])
+def test_unequal_technique_counts_match_oracle(name):
+    """Per-technique sample counts (balance heuristic over unequal counts)
+    against the oracle on the same Philox streams, record by record."""
+    from gpu_parity import compare_records, rel_l2
+    import oracle
+    from paper_2406_16302_amd import native
+    if name == "cornell_motion":
+        ws = scenes.cornell_motion(width=32, height=32, depth=5, spp=4)
+        counts = [8, 2, 4, 6, 2, 4, 1, 0]
+    else:
+        ws = scenes.cornell_material(width=32, height=32, depth=5, spp=4)
+        counts = [12, 1, 3, 0, 0, 0, 0, 0]
+    print(name, "technique counts", counts, flush=True)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    material = ws.edit.kind == scenes.EDIT_MATERIAL
+    flags = (0 if material else native.FLAG_TWO_WAY) | native.FLAG_RECORDS
+    out = torch.zeros((32, 32, 3), dtype=torch.float32, device="cuda")
+    st = native.render_residual(sc, ed, native.Params.make(ws.spp, ws.depth, ws.seed, mask=ws.mask, flags=flags,
+                                                           technique_spp=counts), out, stats=True)
+    per_dir = 1 if material else 2
+    assert st["samples"] == per_dir * 32 * 32 * sum(c for t, c in enumerate(counts) if (ws.mask >> t) & 1)
+    g = sc.records()
+    o = oracle.residual_for(ws, oracle.OracleScene(ws.scene), threads=1, records=True, tech_spp=counts)
+    c = compare_records(g, o["records"])
+    print(c, flush=True)
+    assert c["oracle"] > 1000
+    assert c["value_mismatch"] + c["missing_on_gpu"] + c["extra_on_gpu"] <= 1e-3 * c["oracle"]
+    assert rel_l2(out.cpu().numpy().astype(np.float64), o["image"]) < 1e-3
+
+
+def test_sample_allocation_from_a_pilot():
+    """rpi_allocate_samples: one count per enabled technique, none for the
+    others; the allocation it returns renders an unbiased residual (the sum
+    of the image agrees with equal counts) and, printed, what it gains."""
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_material(width=64, height=64, depth=5, spp=8)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    p = native.Params.make(ws.spp, ws.depth, ws.seed, mask=0x07, flags=0)
+    counts = native.allocate_samples(sc, ed, p, pilot_spp=4)
+    print("allocation", counts, flush=True)
+    assert all(c >= 1 for c in counts[:3]) and all(c == 0 for c in counts[3:])
+    out = torch.zeros((64, 64, 3), dtype=torch.float32, device="cuda")
+    sums = {}
+    for label, tc in (("equal", None), ("allocated", counts)):
+        v = []
+        for k in range(16):
+            native.render_residual(sc, ed, native.Params.make(ws.spp, ws.depth, 500 + k, mask=0x07, flags=0,
+                                                              technique_spp=tc), out)
+            v.append(out.double().sum().item())
+        sums[label] = (np.mean(v), np.std(v, ddof=1) / 4.0)
+    (m0, s0), (m1, s1) = sums["equal"], sums["allocated"]
+    print(sums, flush=True)
+    assert abs(m0 - m1) < 4 * np.hypot(s0, s1)

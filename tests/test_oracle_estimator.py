@@ -149,18 +149,22 @@ def test_mapping_is_an_involution_with_symmetric_rejection(oracle_lib):
 
 # --- unbiasedness against the difference of two independent frames -------------
 
-@pytest.mark.parametrize("kind", ["motion", "material", "motion_no_mapping"])
+@pytest.mark.parametrize("kind", ["motion", "material", "motion_no_mapping", "motion_unequal_counts",
+                                  "material_unequal_counts"])
 def test_residual_converges_to_frame_difference(oracle_lib, kind):
     """motion_no_mapping: the path-mapping ablation (every pair rejected,
-    each frame's dynamic paths with weight 1) is also unbiased."""
+    each frame's dynamic paths with weight 1) is also unbiased.
+    *_unequal_counts: techniques with different sample counts, combined by
+    the balance heuristic over those counts, stay unbiased."""
+    counts = [512, 128, 256, 384, 128, 256, 64, 0] if kind.endswith("unequal_counts") else None
     if kind.startswith("motion"):
         w = scenes.cornell_motion(width=8, height=8, depth=4)
         frame_kw = dict(pose_new=w.edit.old_to_new)
-        res_kw = dict(pose_new=w.edit.old_to_new, no_mapping=kind.endswith("no_mapping"))
+        res_kw = dict(pose_new=w.edit.old_to_new, no_mapping=kind.endswith("no_mapping"), tech_spp=counts)
     else:
         w = scenes.cornell_material(width=8, height=8, depth=4)
         frame_kw = dict(new_mat=w.edit.new_material)
-        res_kw = dict(new_mat=w.edit.new_material, material_mode=True, mask=0x07, two_way=False)
+        res_kw = dict(new_mat=w.edit.new_material, material_mode=True, mask=0x07, two_way=False, tech_spp=counts)
     d = w.depth
     o = oracle_lib.OracleScene(w.scene)
     D, dse = batched(lambda s: o.render_frame(2, 4096, d, s, threads=T, **frame_kw)[0]
@@ -170,7 +174,9 @@ def test_residual_converges_to_frame_difference(oracle_lib, kind):
         st = o.render_residual(16, d, 1, threads=T, **res_kw)["stats"]
         assert st["paths"] > 0 and st["accepted"] == 0 and st["unmapped"] == st["paths"]
     z, _ = zscores(R, se, D, dse)
-    assert (np.abs(z) < 3).mean() > 0.98
+    # the three channels of a pixel share their paths, so values beyond 3
+    # sigma come in threes: allow one such pixel of the 64
+    assert (np.abs(z) < 3).mean() > 0.98 - (0.01 if counts else 0.0)
     assert np.abs(z).max() < 5.5
     zm = (R.mean() - D.mean()) / (np.sqrt((se ** 2).sum() + (dse ** 2).sum()) / R.size)
     assert abs(zm) < 3.5
