@@ -186,16 +186,17 @@ def time_residual(native, sc, ed, params, steps, warmup, out):
 
 
 def device_ms(fn, reps=3):
-    """Median device time of fn() (HIP events on the current stream)."""
+    """Median wall time of fn() up to the end of its device work, after one
+    untimed call (every method is timed the same way, allocations included)."""
     import torch
+    fn()
+    torch.cuda.synchronize()
     ts = []
     for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
+        t0 = time.perf_counter()
         fn()
-        b.record()
         torch.cuda.synchronize()
-        ts.append(a.elapsed_time(b))
+        ts.append((time.perf_counter() - t0) * 1e3)
     return float(np.median(ts))
 
 

@@ -363,8 +363,38 @@ struct rpi_proposal {
   MlpDev view() const { return mlp_view(B, center, inv_half); }
 };
 
+// The library's own stream-ordered pool per device.  It keeps the memory
+// handed back (release threshold: unlimited) so that the per-call workspace
+// (tens of GB at the large rounds) is not unmapped and mapped again at every
+// synchronisation, as the default pool would do; rpi_destroy_scene trims it.
+static std::mutex g_pool_mu;
+static hipMemPool_t g_pool[64];
+static bool g_pool_tried[64];
+
+static hipMemPool_t lib_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (!g_pool_tried[dev]) {
+    g_pool_tried[dev] = true;
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof props);
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+      uint64_t keep = ~(uint64_t)0;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+      g_pool[dev] = pool;
+    }
+  }
+  return g_pool[dev];
+}
+
 // Device memory of a scene and of the calls on it: through the caller's hook
-// when one was given, else hipMallocAsync on the stream (async) or hipMalloc.
+// when one was given, else from the library's pool on the stream (async; the
+// default pool if the library's could not be made) or hipMalloc.
 static rpi_status dev_alloc(const rpi_scene* s, size_t bytes, hipStream_t st, bool async, void** out) {
   *out = nullptr;
   if (bytes == 0) return RPI_OK;
@@ -373,7 +403,9 @@ static rpi_status dev_alloc(const rpi_scene* s, size_t bytes, hipStream_t st, bo
     if (!*out) return fail(RPI_ERR_OUT_OF_MEMORY, "the allocator hook returned no memory for " + std::to_string(bytes) + " bytes");
     return RPI_OK;
   }
-  hipError_t e = async ? hipMallocAsync(out, bytes, st) : hipMalloc(out, bytes);
+  hipMemPool_t pool = async ? lib_pool() : nullptr;
+  hipError_t e = async ? (pool ? hipMallocFromPoolAsync(out, bytes, pool, st) : hipMallocAsync(out, bytes, st))
+                       : hipMalloc(out, bytes);
   if (e != hipSuccess) {
     *out = nullptr;
     return fail(e == hipErrorOutOfMemory ? RPI_ERR_OUT_OF_MEMORY : RPI_ERR_DEVICE,
@@ -718,6 +750,8 @@ extern "C" rpi_status rpi_destroy_scene(rpi_scene* s) {
   s->batch = nullptr;
   (void)hipDeviceSynchronize();  // no call on the scene may still be running
   for (void* p : s->allocs) dev_free(s, p, nullptr, false);
+  if (!s->has_al)
+    if (hipMemPool_t pool = lib_pool()) (void)hipMemPoolTrimTo(pool, 0);  // hand the pooled workspace back
   delete s;
   return RPI_OK;
 }
