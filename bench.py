@@ -399,6 +399,11 @@ def cornell_sweep(args):
         t_res = device_ms(lambda: native.render_residual(sc, ed, p0, out), reps=3)
         native.render_residual(sc, ed, p0, out)
         methods = {"residual": (mse(out, ref), t_res)}
+        counts = native.allocate_samples(sc, ed, p0, pilot_spp=4)
+        pa = native.Params.make(ws.spp, ws.depth, ws.seed, flags=native.FLAG_TWO_WAY, technique_spp=counts)
+        t_al = device_ms(lambda: native.render_residual(sc, ed, pa, out), reps=3)
+        native.render_residual(sc, ed, pa, out)
+        methods["residual_allocated"] = (mse(out, ref), t_al)
         pn = mk(ws.seed, native.FLAG_NO_MAPPING)
         t_nm = device_ms(lambda: native.render_residual(sc, ed, pn, out), reps=3)
         native.render_residual(sc, ed, pn, out)
