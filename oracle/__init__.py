@@ -34,7 +34,8 @@ class Params(C.Structure):
                 ("seed", C.c_uint64), ("job", C.c_uint32), ("alpha_min", C.c_float),
                 ("d_min", C.c_float), ("jac_max", C.c_float), ("c_weight", C.c_float),
                 ("s0", C.c_int64), ("s1", C.c_int64), ("threads", C.c_int),
-                ("material_mode", C.c_int), ("no_mapping", C.c_int), ("tech_spp", C.c_int32 * 8)]
+                ("material_mode", C.c_int), ("no_mapping", C.c_int), ("tech_spp", C.c_int32 * 8),
+                ("balance", C.c_int)]
 
 
 RECORD_DTYPE = np.dtype([("dir", "<i4"), ("tech", "<i4"), ("sample", "<u4"), ("k", "<i4"),
@@ -193,12 +194,12 @@ class OracleScene:
         return t, ids
 
     def _params(self, spp, depth, mask, two_way, seed, job, alpha_min, d_min, jac_max, c_weight, s0, s1,
-                threads, material_mode, no_mapping=False, tech_spp=None):
+                threads, material_mode, no_mapping=False, tech_spp=None, balance=False):
         if d_min is None:
             d_min = np.float32(0.01 * scene_diag(self.scene))
         ts = (C.c_int32 * 8)(*([int(x) for x in tech_spp] if tech_spp is not None else [0] * 8))
         return Params(spp, depth, mask, int(two_way), seed, job, alpha_min, float(d_min), jac_max, c_weight,
-                      s0, s1, threads, int(material_mode), int(no_mapping), ts)
+                      s0, s1, threads, int(material_mode), int(no_mapping), ts, int(balance))
 
     def render_frame(self, which, spp, depth, seed, pose_old=IDENTITY, pose_new=IDENTITY, new_mat=None,
                      s0=0, s1=-1, threads=1, job=0, stream_dir=None):
@@ -219,13 +220,14 @@ class OracleScene:
     def render_residual(self, spp, depth, seed, pose_old=IDENTITY, pose_new=IDENTITY, new_mat=None,
                         material_mode=False, mask=TECH_MASK_ALL, two_way=True, alpha_min=0.2, d_min=None,
                         jac_max=10.0, c_weight=0.5, s0=0, s1=-1, threads=1, job=0, per_tech=False,
-                        records=False, rec_cap=4_000_000, mlp=None, no_mapping=False, tech_spp=None):
+                        records=False, rec_cap=4_000_000, mlp=None, no_mapping=False, tech_spp=None,
+                        balance=False):
         """tech_spp: per-technique samples per pixel (8 values, 0 = spp; the
         full sample range only): unequal counts in the balance heuristic."""
         if tech_spp is not None and any(tech_spp) and (s0 != 0 or s1 != -1):
             raise ValueError("per-technique sample counts need the full sample range")
         pm = self._params(spp, depth, mask, two_way, seed, job, alpha_min, d_min, jac_max, c_weight, s0, s1,
-                          threads, material_mode, no_mapping, tech_spp)
+                          threads, material_mode, no_mapping, tech_spp, balance)
         img = np.zeros((self.H, self.W, 3), np.float64)
         timg = np.zeros((8, self.H, self.W, 3), np.float64) if per_tech else None
         st = np.zeros(32, np.int64)

@@ -1781,6 +1781,7 @@ struct Params {
   int material_mode;
   int no_mapping;  // the path-mapping ablation: every pair is rejected
   int32_t tech_spp[8];  // samples per pixel of technique t (index t-1); 0: spp
+  int balance;          // accepted pairs weighted by the balance heuristic over both directions
 };
 
 struct Record {
@@ -1878,16 +1879,31 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
       // rejected: it keeps its own frame's term with weight 1.
       int reason = Pm.material_mode ? ACCEPT : (Pm.no_mapping ? REJECT_UNMAPPED : map_path(S, F, Fp, X, Y, M));
       D3 val;
+      double total = mt.total;
       if (reason == ACCEPT) {
         D3 fy = contribution_rest(S, Fp, Y) * cf;
-        val = (fx - fy) * c;
+        if (Pm.balance && !Pm.material_mode) {
+          // The other direction samples the same pair through Y = T(X), with
+          // the strategy densities of its own frame; in X's measure their sum
+          // is Sigma_f'(Y) |T'|, and the balance heuristic over the strategies
+          // of both directions divides the pair's value by both sums.
+          MisOpts Oy = O;
+          Oy.ghosts = Fp.ghosts;
+          Oy.frame = &Fp;
+          MisTerms my = mis_terms(S, Fp, Y, Oy);
+          const double jac = cam_pdf(S, X) / cam_pdf(S, Y);  // 1 unless x_1 was re-traced
+          total = mt.total + my.total * jac;
+          val = fx - fy;
+        } else {
+          val = (fx - fy) * c;
+        }
         st.accepted++;
       } else {
         val = fx;
         st.rejected[reason == REJECT_UNMAPPED ? 0 : reason]++;
       }
       const D3 unweighted = val;
-      val = val * (sigma / mt.total / N);
+      val = val * (sigma / total / N);
       st.paths++;
       st.by_tech[tech]++;
       img[3 * pix + 0] += val.x;
@@ -1913,7 +1929,7 @@ static void residual_range(const Scene& S, const Frame& F, const Frame& Fp, int 
         r.val[0] = val.x;
         r.val[1] = val.y;
         r.val[2] = val.z;
-        r.mis_total = mt.total;
+        r.mis_total = total;
         r.mis_tech = mt.by_tech[tech];
         for (int t = 0; t < 9; ++t) r.mis_by_tech[t] = mt.by_tech[t];
         r.p_gen = X.p_gen;

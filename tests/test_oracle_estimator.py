@@ -150,17 +150,20 @@ def test_mapping_is_an_involution_with_symmetric_rejection(oracle_lib):
 # --- unbiasedness against the difference of two independent frames -------------
 
 @pytest.mark.parametrize("kind", ["motion", "material", "motion_no_mapping", "motion_unequal_counts",
-                                  "material_unequal_counts"])
+                                  "material_unequal_counts", "motion_balance"])
 def test_residual_converges_to_frame_difference(oracle_lib, kind):
     """motion_no_mapping: the path-mapping ablation (every pair rejected,
     each frame's dynamic paths with weight 1) is also unbiased.
     *_unequal_counts: techniques with different sample counts, combined by
-    the balance heuristic over those counts, stay unbiased."""
+    the balance heuristic over those counts, stay unbiased.
+    motion_balance: accepted pairs weighted by the balance heuristic over the
+    strategies of both directions instead of c = 1/2."""
     counts = [512, 128, 256, 384, 128, 256, 64, 0] if kind.endswith("unequal_counts") else None
     if kind.startswith("motion"):
         w = scenes.cornell_motion(width=8, height=8, depth=4)
         frame_kw = dict(pose_new=w.edit.old_to_new)
-        res_kw = dict(pose_new=w.edit.old_to_new, no_mapping=kind.endswith("no_mapping"), tech_spp=counts)
+        res_kw = dict(pose_new=w.edit.old_to_new, no_mapping=kind.endswith("no_mapping"), tech_spp=counts,
+                      balance=kind.endswith("balance"))
     else:
         w = scenes.cornell_material(width=8, height=8, depth=4)
         frame_kw = dict(new_mat=w.edit.new_material)
