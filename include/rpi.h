@@ -60,6 +60,18 @@ typedef int32_t rpi_status;
  * RPI_FLAG_ACCUMULATE, else onto zero).  The technique images are always
  * overwritten (zero for techniques that did not run). */
 #define RPI_FLAG_PER_TECHNIQUE 64u
+/* Balance heuristic across the two directions of the two-way mapping
+ * (Sec. 5, two-way path mapping; Sec. 4.3, technique combination).  An
+ * accepted pair (x, y = T(x)) is weighted by the balance heuristic over the
+ * strategies of both frames instead of the fixed weight c_weight: its value
+ * f(x) - f'(y)|T'| is divided by Sigma_f(x) + Sigma_f'(y)|T'|, the sums of
+ * the strategy densities that generate x in its own frame and y in the
+ * other (|T'| = 1 except for a re-traced x_1, where it is the ratio of the
+ * two camera densities).  Rejected paths keep their own frame's sum.  Still
+ * unbiased: the two directions' weights of a pair sum to one.  Motion edits
+ * with RPI_FLAG_TWO_WAY, without technique 8; anything else is UNSUPPORTED.
+ * c_weight is then unused. */
+#define RPI_FLAG_BALANCE 128u
 
 typedef struct rpi_scene rpi_scene;
 typedef struct rpi_edit rpi_edit;

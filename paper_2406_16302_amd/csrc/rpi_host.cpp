@@ -864,6 +864,14 @@ static DevFrame make_frame(const rpi_scene* s, const float* pose, const float* g
   return F;
 }
 
+// Flags that apply to motion edits only.
+static rpi_status check_edit_flags(const rpi_edit* e, const rpi_render_params* p) {
+  if (e->kind != RPI_EDIT_MATERIAL) return RPI_OK;
+  if (p->flags & RPI_FLAG_NO_MAPPING) return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING applies to motion edits only");
+  if (p->flags & RPI_FLAG_BALANCE) return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_BALANCE applies to motion edits only");
+  return RPI_OK;
+}
+
 static rpi_status check_params(const rpi_scene* s, const rpi_render_params* p) {
   if (!p) return fail(RPI_ERR_INVALID_ARG, "null params");
   if (p->spp <= 0) return fail(RPI_ERR_INVALID_ARG, "spp must be positive");
@@ -877,6 +885,10 @@ static rpi_status check_params(const rpi_scene* s, const rpi_render_params* p) {
     return fail(RPI_ERR_INVALID_ARG, "RPI_FLAG_PER_TECHNIQUE needs d_technique_images");
   if ((p->flags & RPI_FLAG_NO_MAPPING) && !(p->flags & RPI_FLAG_TWO_WAY))
     return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING needs RPI_FLAG_TWO_WAY (a motion edit sampled in both frames)");
+  if ((p->flags & RPI_FLAG_BALANCE) && !(p->flags & RPI_FLAG_TWO_WAY))
+    return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_BALANCE needs RPI_FLAG_TWO_WAY (a motion edit sampled in both frames)");
+  if ((p->flags & RPI_FLAG_BALANCE) && (p->strategy_mask & 0x80u))
+    return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_BALANCE does not combine with technique 8");
   bool uneq = false;
   for (int t = 0; t < kTechs; ++t) {
     if (p->technique_spp[t] < 0) return fail(RPI_ERR_INVALID_ARG, "negative technique_spp");
@@ -1226,6 +1238,7 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
   A.d_min = p->d_min;
   A.jac_max = p->jac_max;
   A.no_mapping = (p->flags & RPI_FLAG_NO_MAPPING) ? 1 : 0;
+  A.balance = (p->flags & RPI_FLAG_BALANCE) ? 1 : 0;
   A.tech_spp = 0;
   A.count_work = o.count_work ? 1 : 0;
   A.keep_records = o.keep ? 1 : 0;
@@ -1468,8 +1481,8 @@ extern "C" rpi_status rpi_render_residual(const rpi_scene* s, const rpi_edit* e,
   rpi_status rc = check_params(s, p);
   if (rc) return rc;
   if (p->d_train_records && !stats) return fail(RPI_ERR_INVALID_ARG, "training-record collection needs stats");
-  if ((p->flags & RPI_FLAG_NO_MAPPING) && e->kind == RPI_EDIT_MATERIAL)
-    return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING applies to motion edits only");
+  rc = check_edit_flags(e, p);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   JobSpec j;
   std::memcpy(j.pose_old, e->pose_old, sizeof j.pose_old);
@@ -1649,8 +1662,8 @@ extern "C" rpi_status rpi_render_residual_noalloc(const rpi_scene* s, const rpi_
   if (p->d_train_records || (p->flags & (RPI_FLAG_RECORDS | RPI_FLAG_COUNT_WORK | RPI_FLAG_TIME_KERNELS)))
     return fail(RPI_ERR_UNSUPPORTED, "records, work counting, kernel timing and training records need "
                                      "rpi_render_residual");
-  if ((p->flags & RPI_FLAG_NO_MAPPING) && e->kind == RPI_EDIT_MATERIAL)
-    return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING applies to motion edits only");
+  rc = check_edit_flags(e, p);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   JobSpec j;
   std::memcpy(j.pose_old, e->pose_old, sizeof j.pose_old);
@@ -1914,6 +1927,8 @@ extern "C" rpi_status rpi_render_residual_batch(const rpi_scene* cs, const rpi_j
   if (p->tile != 0 && p->tile != 16 && p->tile != 32) return fail(RPI_ERR_INVALID_ARG, "tile must be 0, 16 or 32");
   if ((p->flags & RPI_FLAG_NO_MAPPING) && !(p->flags & RPI_FLAG_TWO_WAY))
     return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_NO_MAPPING needs RPI_FLAG_TWO_WAY");
+  if ((p->flags & RPI_FLAG_BALANCE) && (!(p->flags & RPI_FLAG_TWO_WAY) || (p->strategy_mask & 0x80u)))
+    return fail(RPI_ERR_UNSUPPORTED, "RPI_FLAG_BALANCE needs RPI_FLAG_TWO_WAY and no technique 8");
   hipStream_t st = (hipStream_t)stream;
   rpi_render_params q = *p;
   if (q.d_min < 0) q.d_min = (float)(0.01 * (double)s->diag);

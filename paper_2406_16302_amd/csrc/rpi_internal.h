@@ -239,6 +239,7 @@ struct WalkArgs {
   float cweight;
   float alpha_min, d_min, jac_max;
   int32_t no_mapping;          // every path rejected (the path-mapping ablation)
+  int32_t balance;             // accepted pairs: balance heuristic over both directions' strategies
   int32_t tech_spp;            // this technique's samples per pixel (0: the job's sample range)
   int32_t count_work;
   int32_t keep_records;

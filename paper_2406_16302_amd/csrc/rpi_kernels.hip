@@ -1423,7 +1423,10 @@ struct CCtx {
 };
 
 // q8a, q8b: the proposal's densities at x_1..x_4 and x_5 (technique (8) in the mask).
-template <bool CW>
+// BAL: accepted pairs weighted by the balance heuristic over the strategies of
+// both directions (the mapped path's strategy sum in the other frame) instead
+// of the fixed two-way weight.
+template <bool CW, bool BAL>
 DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* stk, WorkCount& wc, float4& rec,
                      int& reason, TrainRec& tr) {
   const DevScene& S = A.S;
@@ -1609,78 +1612,85 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
     const vec3 wo = (q == k - 1 && E.env) ? E.n : unit(pick(q == k - 1, E.p, v[q].p) - og);
     return bsdf_pdf(m, v[r].n, dir_from(r, inc), wo) * to_area(r, q, og);
   };
-  float Apre[kMaxK], Bsuf[kMaxK + 1];
-  Apre[0] = 1.0f;
-#pragma unroll
-  for (int q = 1; q < kMaxK; ++q) Apre[q] = Apre[q - 1];
-#pragma unroll
-  for (int q = 1; q <= kMaxK - 3; ++q)
-    if (q <= k - 3) Apre[q] = Apre[q - 1] * gen(q + 1, q, q + 2);
-#pragma unroll
-  for (int q = kMaxK; q >= 0; --q) Bsuf[q] = 1.0f;
-#pragma unroll
-  for (int q = kMaxK - 2; q >= 2; --q) Bsuf[q] = (q <= k - 2) ? Bsuf[q + 1] * gen(q - 1, q, q - 2) : 1.0f;
-  auto on = [&](int t) { return (A.mask >> (t - 1)) & 1u; };
-  // each strategy's density weighs by its sample count relative to the base
-  // count (the balance heuristic over unequal counts; 1 when they are equal)
-  const float* rt = A.ratio;
-  float sum = 0.0f;
+  // The strategy densities of the path in v[] (crossing records exm/exw,
+  // camera density pcam): the forward/backward tables and the MIS sum.
   float pgen = 0.0f;  // techniques (2), (3): density of the generating strategy
-  if (on(7)) sum += rt[6] * (k == 2 ? pcam : pcam * Bsuf[2] * pL);
-#pragma unroll
-  for (int m = 1; m < kMaxK - 1; ++m) {
-    if (m > k - 2 || !(v[m].md & kDynBit)) continue;
-    if (m == k - 2) {
-      if (on(1)) sum += rt[0] * (pL * pD * Apre[m - 1]);
-    } else if (m == 1) {
-      if (on(2) && k >= 4) {
-        const float t2 = pD * Bsuf[2] * pL;
-        sum += rt[1] * t2;
-        if (T == 2) pgen = t2;
-      }
-      if (on(8)) sum += rt[7] * (pD * q8a.x * to_area(1, 2, origin(1, 2)) * Bsuf[3] * pL);
-    } else if (on(3) || on(8)) {
-      const vec3 o = origin(m, m + 1);
-      const vec3 w = unit(v[m + 1].p - o);
-      const float rest3 = to_area(m, m + 1, o) * Apre[m - 1] * Bsuf[m + 2] * pL;
-      const float c = dot(v[m].n, w);
-      if (on(3) && c > 0.0f) {
-        const float t3 = pD * (c / kPi) * rest3;
-        sum += rt[2] * t3;
-        if (T == 3 && m == i + 2) pgen = t3;
-      }
-      if (on(8)) sum += rt[7] * (pD * (m == 2 ? q8a.y : m == 3 ? q8a.z : m == 4 ? q8a.w : q8b.x) * rest3);
-    }
-  }
-  if (motion && k >= 3) {
-    const float pG = pD;
-    const float pdir = 1.0f / (4.0f * kPi);
-#pragma unroll
-    for (int a = 0; a < kMaxK - 1; ++a) {
-      if (a > k - 2 || !((exm >> a) & 1u)) continue;
-      if (a == k - 2) {
-        if (on(4) && !E.env) {
-          const vec3 o = spawn(S, E.p, E.n, vl.p);  // the offset light point generating x_{k-2}
-          const vec3 d = vl.p - o;
-          float ak = Apre[0];
-#pragma unroll
-          for (int q = 1; q < kMaxK; ++q)
-            if (q == k - 3) ak = Apre[q];
-          sum += rt[3] * (pL * pG * exw[a] * fabsf(dot(vl.n, unit(d))) / len2(d) * ak);
+  auto mis_sum = [&](bool first) -> float {
+    float Apre[kMaxK], Bsuf[kMaxK + 1];
+    Apre[0] = 1.0f;
+  #pragma unroll
+    for (int q = 1; q < kMaxK; ++q) Apre[q] = Apre[q - 1];
+  #pragma unroll
+    for (int q = 1; q <= kMaxK - 3; ++q)
+      if (q <= k - 3) Apre[q] = Apre[q - 1] * gen(q + 1, q, q + 2);
+  #pragma unroll
+    for (int q = kMaxK; q >= 0; --q) Bsuf[q] = 1.0f;
+  #pragma unroll
+    for (int q = kMaxK - 2; q >= 2; --q) Bsuf[q] = (q <= k - 2) ? Bsuf[q + 1] * gen(q - 1, q, q - 2) : 1.0f;
+    auto on = [&](int t) { return (A.mask >> (t - 1)) & 1u; };
+    // each strategy's density weighs by its sample count relative to the base
+    // count (the balance heuristic over unequal counts; 1 when they are equal)
+    const float* rt = A.ratio;
+    float sum = 0.0f;
+    if (on(7)) sum += rt[6] * (k == 2 ? pcam : pcam * Bsuf[2] * pL);
+  #pragma unroll
+    for (int m = 1; m < kMaxK - 1; ++m) {
+      if (m > k - 2 || !(v[m].md & kDynBit)) continue;
+      if (m == k - 2) {
+        if (on(1)) sum += rt[0] * (pL * pD * Apre[m - 1]);
+      } else if (m == 1) {
+        if (on(2) && k >= 4) {
+          const float t2 = pD * Bsuf[2] * pL;
+          sum += rt[1] * t2;
+          if (first && T == 2) pgen = t2;
         }
-      } else if (a == 0) {
-        if (on(5)) {
-          const vec3 d = v[1].p - C.eye;
-          sum += rt[4] * (pG * exw[a] * fabsf(dot(v[1].n, unit(d))) / len2(d) * Bsuf[2] * pL);
+        if (on(8)) sum += rt[7] * (pD * q8a.x * to_area(1, 2, origin(1, 2)) * Bsuf[3] * pL);
+      } else if (on(3) || on(8)) {
+        const vec3 o = origin(m, m + 1);
+        const vec3 w = unit(v[m + 1].p - o);
+        const float rest3 = to_area(m, m + 1, o) * Apre[m - 1] * Bsuf[m + 2] * pL;
+        const float c = dot(v[m].n, w);
+        if (on(3) && c > 0.0f) {
+          const float t3 = pD * (c / kPi) * rest3;
+          sum += rt[2] * t3;
+          if (first && T == 3 && m == i + 2) pgen = t3;
         }
-      } else if (on(6)) {
-        const vec3 d = v[a + 1].p - v[a].p;
-        const vec3 w = unit(d);
-        const float G = fabsf(dot(v[a].n, w)) * fabsf(dot(v[a + 1].n, w)) / len2(d);
-        sum += rt[5] * (pG * pdir * G * exw[a] * Apre[a > 0 ? a - 1 : 0] * Bsuf[a + 2] * pL);
+        if (on(8)) sum += rt[7] * (pD * (m == 2 ? q8a.y : m == 3 ? q8a.z : m == 4 ? q8a.w : q8b.x) * rest3);
       }
     }
-  }
+    if (motion && k >= 3) {
+      const float pG = pD;
+      const float pdir = 1.0f / (4.0f * kPi);
+  #pragma unroll
+      for (int a = 0; a < kMaxK - 1; ++a) {
+        if (a > k - 2 || !((exm >> a) & 1u)) continue;
+        if (a == k - 2) {
+          if (on(4) && !E.env) {
+            const vec3 o = spawn(S, E.p, E.n, vl.p);  // the offset light point generating x_{k-2}
+            const vec3 d = vl.p - o;
+            float ak = Apre[0];
+  #pragma unroll
+            for (int q = 1; q < kMaxK; ++q)
+              if (q == k - 3) ak = Apre[q];
+            sum += rt[3] * (pL * pG * exw[a] * fabsf(dot(vl.n, unit(d))) / len2(d) * ak);
+          }
+        } else if (a == 0) {
+          if (on(5)) {
+            const vec3 d = v[1].p - C.eye;
+            sum += rt[4] * (pG * exw[a] * fabsf(dot(v[1].n, unit(d))) / len2(d) * Bsuf[2] * pL);
+          }
+        } else if (on(6)) {
+          const vec3 d = v[a + 1].p - v[a].p;
+          const vec3 w = unit(d);
+          const float G = fabsf(dot(v[a].n, w)) * fabsf(dot(v[a + 1].n, w)) / len2(d);
+          sum += rt[5] * (pG * pdir * G * exw[a] * Apre[a > 0 ? a - 1 : 0] * Bsuf[a + 2] * pL);
+        }
+      }
+    }
+    return sum;
+  };
+  const float sum = mis_sum(true);
+  float denom = sum;  // the balance heuristic's denominator of this path's value
   if (!(sum > 0.0f)) {
     reason = 8;
     return;
@@ -1804,13 +1814,70 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
     }
     if (!rej) {
       const vec3 fy = rest(Fp, istar, y) * camf;
-      val = (fx - fy) * A.cweight;
+      if constexpr (BAL) {
+        // The other direction samples this pair through y = T(x) with its own
+        // frame's strategies.  Their densities: the tables of the mapped path
+        // (x with vertex istar replaced by y), its dynamic vertex y, and its
+        // ghost crossings in f' (the object at this frame's pose): only the
+        // two edges at y can cross it, since x's other edges are unoccluded in
+        // this frame.  In x's measure the sum carries |T'| = pcam_x / pcam_y
+        // (1 unless x_1 was re-traced).  With no vertex moved (the frames
+        // coincide, or x has no dynamic vertex and no crossing) the mapped
+        // path is x and its strategies are x's.
+        float sum_y = sum;
+        if (istar > 0) {
+          PV ym = v[0], yp = v[0];  // the neighbours of the moved vertex
+#pragma unroll
+          for (int q = 0; q < kMaxK - 1; ++q) {
+            if (q == istar - 1) ym = v[q];
+            if (q == istar + 1) yp = v[q];
+          }
+          const End ey = end_surf(y.p, y.n);
+          const Cross c1 = edge_cross<CW>(S, Fp, istar == 1 ? end_eye(S) : end_surf(ym.p, ym.n), ey, stk, wc);
+          const bool last = istar + 1 == k - 1;
+          const Cross c2 = edge_cross<CW>(S, Fp, ey, last ? end_light(E) : end_surf(yp.p, yp.n), stk, wc);
+          const float w1 = istar == 1 ? c1.sa : c1.s0, w2 = last ? c2.sb : c2.s0;
+          // swap the mapped path in, take its sum, swap x back
+          float exw_x[kMaxK];
+#pragma unroll
+          for (int q = 0; q < kMaxK; ++q) {
+            exw_x[q] = exw[q];
+            exw[q] = q == istar - 1 ? w1 : (q == istar ? w2 : 0.0f);
+          }
+          const uint32_t exm_x = exm;
+          exm = ((c1.n > 0.0f ? 1u : 0u) << (istar - 1)) | ((c2.n > 0.0f ? 1u : 0u) << istar);
+          PV xs = v[0];
+#pragma unroll
+          for (int q = 1; q < kMaxK - 1; ++q)
+            if (q == istar) {
+              xs = v[q];
+              v[q] = y;
+            }
+          const PV vl_x = vl;
+          if (istar == k - 2) vl = y;
+          const float pcam_x = pcam;
+          if (istar == 1) pcam = camera_geo(C, y.p, y.n);
+          sum_y = mis_sum(false) * (pcam_x / pcam);
+#pragma unroll
+          for (int q = 1; q < kMaxK - 1; ++q)
+            if (q == istar) v[q] = xs;
+          vl = vl_x;
+          pcam = pcam_x;
+          exm = exm_x;
+#pragma unroll
+          for (int q = 0; q < kMaxK; ++q) exw[q] = exw_x[q];
+        }
+        val = fx - fy;
+        denom = sum + sum_y;
+      } else {
+        val = (fx - fy) * A.cweight;
+      }
     } else {
       val = fx;
     }
     reason = rej;
   }
-  const float sc = A.sigma / sum * A.inv_n;
+  const float sc = A.sigma / denom * A.inv_n;
   rec = make_float4(__int_as_float(pixel | (A.job << 24)), val.x * sc, val.y * sc, val.z * sc);
   if (A.mlp && (T == 2 || T == 3) && pgen > 0.0f) {
     // x_m = x_D (m = i + 2) and its light-side neighbour, by constant indices
@@ -1833,7 +1900,7 @@ DEV void connect_one(const CCtx& A, uint32_t code, float4 q8a, float4 q8b, int* 
   }
 }
 
-template <bool CW>
+template <bool CW, bool BAL>
 __global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
   __shared__ unsigned long long cnt[16];
@@ -1864,7 +1931,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_ker
       const float4 q8a = A.W.t8q ? A.W.t8q[2 * (size_t)idx] : z4, q8b = A.W.t8q ? A.W.t8q[2 * (size_t)idx + 1] : z4;
       float4 rec;
       int reason;
-      connect_one<CW>(C, code, q8a, q8b, stk, wc, rec, reason, tr);
+      connect_one<CW, BAL>(C, code, q8a, q8b, stk, wc, rec, reason, tr);
       A.W.records[idx] = rec;
       if (CW) wc.bytes += 16u;
       if (A.keep_records) {
@@ -2409,10 +2476,14 @@ void launch_sort_pairs(const WalkArgs& A, hipStream_t st) {
 }
 
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st) {
-  if (A.count_work)
-    hipLaunchKernelGGL((connect_kernel<true>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
+  if (A.count_work && A.balance)
+    hipLaunchKernelGGL((connect_kernel<true, true>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
+  else if (A.count_work)
+    hipLaunchKernelGGL((connect_kernel<true, false>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
+  else if (A.balance)
+    hipLaunchKernelGGL((connect_kernel<false, true>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
   else
-    hipLaunchKernelGGL((connect_kernel<false>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
+    hipLaunchKernelGGL((connect_kernel<false, false>), dim3(blocks), dim3(kTraceBlock), 0, st, A);
 }
 void launch_splat(const SplatArgs& a, hipStream_t st) {
   const size_t lds = (size_t)a.ntiles * sizeof(uint32_t);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "librpi.so")
 RPI_OK = 0
 EDIT_RIGID, EDIT_MATERIAL = 0, 1
 FLAG_TWO_WAY, FLAG_ACCUMULATE, FLAG_COUNT_WORK, FLAG_RECORDS, FLAG_TIME_KERNELS = 1, 2, 4, 8, 16
-FLAG_NO_MAPPING, FLAG_PER_TECHNIQUE = 32, 64
+FLAG_NO_MAPPING, FLAG_PER_TECHNIQUE, FLAG_BALANCE = 32, 64, 128
 FRAME_OLD, FRAME_NEW = 0, 1
 PROPOSAL_NPARAM, TRAIN_RECORD_FLOATS = 11368, 10
 

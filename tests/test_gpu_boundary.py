@@ -214,3 +214,52 @@ def test_sample_allocation_from_a_pilot():
     (m0, s0), (m1, s1) = sums["equal"], sums["allocated"]
     print(sums, flush=True)
     assert abs(m0 - m1) < 4 * np.hypot(s0, s1)
+
+
+@pytest.mark.parametrize("name", ["cornell", "clutter"])
+def test_balance_across_directions_matches_oracle(name):
+    """RPI_FLAG_BALANCE: accepted pairs divided by the strategy sums of both
+    frames (the mapped path's sum in the other frame, its ghost crossings on
+    the two edges at the moved vertex, |T'| for a re-traced x_1) against the
+    oracle on the same Philox streams, record by record."""
+    from gpu_parity import compare_records, rel_l2
+    import oracle
+    from paper_2406_16302_amd import native
+    if name == "cornell":
+        ws = scenes.cornell_motion(width=32, height=32, depth=5, spp=8)
+    else:
+        ws = scenes.clutter_motion(width=48, height=48, depth=4, spp=4, n_spheres=60)
+    print(name, "balance across directions", flush=True)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    flags = native.FLAG_TWO_WAY | native.FLAG_BALANCE | native.FLAG_RECORDS
+    out, st = _render(sc, ed, native.Params.make(ws.spp, ws.depth, ws.seed, flags=flags))
+    assert st["accepted"] > 100
+    g = sc.records()
+    o = oracle.residual_for(ws, oracle.OracleScene(ws.scene), threads=1, records=True, balance=True)
+    c = compare_records(g, o["records"])
+    print(c, flush=True)
+    assert c["oracle"] > 1000
+    assert c["value_mismatch"] + c["missing_on_gpu"] + c["extra_on_gpu"] <= 1e-3 * c["oracle"]
+    assert rel_l2(out.cpu().numpy().astype(np.float64), o["image"]) < 1e-3
+    # the weighting changes the image (it is not c = 1/2 in disguise)
+    half, _ = _render(sc, ed, native.Params.make(ws.spp, ws.depth, ws.seed))
+    assert rel_l2(half.cpu().numpy().astype(np.float64), out.cpu().numpy().astype(np.float64)) > 1e-3
+
+
+def test_balance_is_rejected_where_it_does_not_apply():
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_material(width=16, height=16, depth=4, spp=2)
+    sc = native.Scene(ws.scene)
+    ed = native.Edit(sc, ws.edit)
+    out = torch.zeros((16, 16, 3), dtype=torch.float32, device="cuda")
+    for flags in (native.FLAG_BALANCE, native.FLAG_BALANCE | native.FLAG_TWO_WAY):
+        with pytest.raises(native.RpiError) as e:
+            native.render_residual(sc, ed, native.Params.make(2, 4, 1, mask=0x07, flags=flags), out)
+        assert e.value.code == -2
+    wm = scenes.cornell_motion(width=16, height=16, depth=4, spp=2)
+    scm = native.Scene(wm.scene)
+    edm = native.Edit(scm, wm.edit)
+    with pytest.raises(native.RpiError) as e:
+        native.render_residual(scm, edm, native.Params.make(2, 4, 1, flags=native.FLAG_BALANCE), out)
+    assert e.value.code == -2

@@ -30,7 +30,7 @@ def test_header_flags_match_the_binding():
     assert flags == {"TWO_WAY": native.FLAG_TWO_WAY, "ACCUMULATE": native.FLAG_ACCUMULATE,
                      "COUNT_WORK": native.FLAG_COUNT_WORK, "RECORDS": native.FLAG_RECORDS,
                      "TIME_KERNELS": native.FLAG_TIME_KERNELS, "NO_MAPPING": native.FLAG_NO_MAPPING,
-                     "PER_TECHNIQUE": native.FLAG_PER_TECHNIQUE}
+                     "PER_TECHNIQUE": native.FLAG_PER_TECHNIQUE, "BALANCE": native.FLAG_BALANCE}
 
 
 def test_null_arguments_are_rejected_without_device_work():
