@@ -309,6 +309,13 @@ def bench_single(name, args):
             native.render_residual(sc, ed, pnm, out)
             methods["residual_no_mapping"] = (mse(out, ref), t_nm)
             spp_used["residual_no_mapping"] = ws.spp
+        if not material and name != "proposal":
+            # accepted pairs weighted by the balance heuristic over both frames' strategies
+            pbl = native.Params.make(ws.spp, ws.depth, ws.seed, mask=mask, flags=base | native.FLAG_BALANCE)
+            t_bl = device_ms(lambda: native.render_residual(sc, ed, pbl, out), reps=2)
+            native.render_residual(sc, ed, pbl, out)
+            methods["residual_balance"] = (mse(out, ref), t_bl)
+            spp_used["residual_balance"] = ws.spp
         if name != "proposal":
             # the residual-aware denoiser on the same budget: two half estimates, then the filter
             N = ws.spp * sc.width * sc.height
@@ -408,6 +415,10 @@ def cornell_sweep(args):
         t_nm = device_ms(lambda: native.render_residual(sc, ed, pn, out), reps=3)
         native.render_residual(sc, ed, pn, out)
         methods["residual_no_mapping"] = (mse(out, ref), t_nm)
+        pb = mk(ws.seed, native.FLAG_BALANCE)
+        t_bl = device_ms(lambda: native.render_residual(sc, ed, pb, out), reps=3)
+        native.render_residual(sc, ed, pb, out)
+        methods["residual_balance"] = (mse(out, ref), t_bl)
         for k, (m, t, s) in pt_baselines(native, sc, ed, 16, ws.depth, ref, t_res, 4243).items():
             methods[k] = (m, t)
         et = equal_time(methods, t_res)
