@@ -41,7 +41,7 @@ import numpy as np
 
 METRIC = "residual paths/s & Mrays/s at 1 GPU; equal-time residual MSE vs plain GPU path"
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES, TRI_BYTES = 64, 48
+NODE_BYTES, TRI_BYTES = 112, 48  # 4-wide node: six box planes and the links (its padding is not read)
 KERNEL_NAMES = {t: "walk_kernel<%d>" % t for t in range(1, 9)}          # start phase of technique t
 KERNEL_NAMES.update({16 + t: "walk_task_kernel<%d>" % t for t in range(1, 9)})  # its walk phase
 KERNEL_NAMES.update({9: "connect_kernel", 10: "splat", 12: "proposal_pdf_kernel", 13: "t8_start_kernel"})

@@ -291,6 +291,59 @@ DEV bool slab(float lx, float ly, float lz, float hx, float hy, float hz, vec3 i
   return t0 <= t1;
 }
 
+// One visit of a 4-wide node: test(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, tnear)
+// says whether the ray meets a child's box.  ORDER: the nearest child met is
+// returned and the others go on the lane's stack, the farthest first
+// (deepest), so the next nearest is popped first (closest-hit and any-hit
+// queries find their hit sooner); without ORDER (all-hit queries, which
+// visit every box met anyway) the children are taken in slot order.  With
+// no child met the next entry is popped (kDone once the stack is empty).
+// At most (children - 1) entries are pushed.
+constexpr int kDone = 0x7fffffff;  // no node left (inner node indices stay below it)
+template <bool ORDER = true, class Test>
+DEV int visit4(const float4* __restrict__ N, int node, int* __restrict__ stk, int& sp, Test&& test) {
+  const size_t b = (size_t)kNodeF4 * (size_t)node;
+  const float4 lx = gld(N, b), hx = gld(N, b + 1), ly = gld(N, b + 2), hy = gld(N, b + 3), lz = gld(N, b + 4),
+               hz = gld(N, b + 5);
+  const int4 e = gld(reinterpret_cast<const int4*>(N), b + 6);
+  const int lane = threadIdx.x;
+  const float inf = __builtin_inff();
+  // entry distance of each child met, +inf for the others (a box met has a
+  // finite entry distance); no branch per child
+  auto key = [&](float lox, float loy, float loz, float hix, float hiy, float hiz, int link) {
+    float t;
+    const bool h = test(lox, loy, loz, hix, hiy, hiz, t) & (link != kEmptyLink);
+    return h ? t : inf;
+  };
+  float d0 = key(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, e.x);
+  float d1 = key(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, e.y);
+  float d2 = key(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, e.z);
+  float d3 = key(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, e.w);
+  int c0 = e.x, c1 = e.y, c2 = e.z, c3 = e.w;
+  if constexpr (ORDER) {
+    // sorting network on (distance, link): 0-1, 2-3, 0-2, 1-3, 1-2
+    auto cas = [](float& da, int& ca, float& db, int& cb) {
+      const bool sw = db < da;
+      const float td = sw ? db : da;
+      db = sw ? da : db;
+      da = td;
+      const int tc = sw ? cb : ca;
+      cb = sw ? ca : cb;
+      ca = tc;
+    };
+    cas(d0, c0, d1, c1);
+    cas(d2, c2, d3, c3);
+    cas(d0, c0, d2, c2);
+    cas(d1, c1, d3, c3);
+    cas(d1, c1, d2, c2);
+  }
+  if (d3 < inf) stk[sp++ * kTraceBlock + lane] = c3;
+  if (d2 < inf) stk[sp++ * kTraceBlock + lane] = c2;
+  if (d1 < inf) stk[sp++ * kTraceBlock + lane] = c1;
+  if (d0 < inf) return c0;
+  return sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
+}
+
 // Visit every leaf whose box the ray (o, d) meets before tlim (read through
 // a reference, so closest-hit leaves tighten it).  leaf(code) returns true to
 // stop.  The stack lives in LDS: entry k of lane l at stk[k * kTraceBlock + l];
@@ -302,37 +355,24 @@ DEV bool slab(float lx, float ly, float lz, float hx, float hy, float hz, vec3 i
 // with the lanes of all leaves instead of one branch per node visit, and
 // lanes that found a leaf early do useful node work meanwhile.  A
 // closest-hit query may visit a few nodes that the postponed leaf's hit
-// would have culled; the hit found is the same.
-template <bool CW, class Leaf>
+// would have culled; the hit found is the same.  ORDER: nearest child first
+// (false for all-hit queries).
+template <bool CW, bool ORDER = true, class Leaf>
 DEV void bvh_walk(const float4* __restrict__ N, vec3 o, vec3 d, const float& tlim, int* __restrict__ stk,
                      WorkCount& wc, Leaf&& leaf) {
   const vec3 inv = v3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
   const vec3 oi = v3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
   const int lane = threadIdx.x;
-  constexpr int kDone = 0x7fffffff;  // no node left (inner node indices stay below it)
   int sp = 0;
   int node = 0;  // >= 0: inner node to visit next; < 0: a leaf code; kDone
   int pl = 0;    // postponed leaf code, 0: none
+  auto test = [&](float lx, float ly, float lz, float hx, float hy, float hz, float& tn) {
+    return slab(lx, ly, lz, hx, hy, hz, inv, oi, tlim, tn);
+  };
   while (node != kDone) {
     while ((uint32_t)node < (uint32_t)kDone) {
-      const float4 a = gld(N, 4 * (size_t)node), b = gld(N, 4 * (size_t)node + 1), c = gld(N, 4 * (size_t)node + 2);
-      const int4 e = gld(reinterpret_cast<const int4*>(N), 4 * (size_t)node + 3);
       if (CW) wc.nodes++;
-      float n0, n1;
-      const bool h0 = slab(a.x, a.y, a.z, a.w, b.x, b.y, inv, oi, tlim, n0);
-      const bool h1 = slab(b.z, b.w, c.x, c.y, c.z, c.w, inv, oi, tlim, n1);
-      const bool first0 = n0 <= n1;
-      if (h0 && h1) {
-        stk[sp * kTraceBlock + lane] = first0 ? e.y : e.x;
-        ++sp;
-        node = first0 ? e.x : e.y;
-      } else if (h0) {
-        node = e.x;
-      } else if (h1) {
-        node = e.y;
-      } else {
-        node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
-      }
+      node = visit4<ORDER>(N, node, stk, sp, test);
       if (node < 0 && pl == 0) {  // postpone the first leaf and go on with the stack
         pl = node;
         node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
@@ -469,30 +509,16 @@ DEV void bvh_walk_line(const float4* __restrict__ N, vec3 o, vec3 d, const float
   const vec3 inv = v3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
   const vec3 oi = v3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
   const int lane = threadIdx.x;
-  constexpr int kDone = 0x7fffffff;
   int sp = 0;
   int node = 0;
   int pl = 0;
+  auto test = [&](float lx, float ly, float lz, float hx, float hy, float hz, float& tn) {
+    return slab_line(lx, ly, lz, hx, hy, hz, inv, oi, tf, tb, tn);
+  };
   while (node != kDone) {
     while ((uint32_t)node < (uint32_t)kDone) {
-      const float4 a = gld(N, 4 * (size_t)node), b = gld(N, 4 * (size_t)node + 1), c = gld(N, 4 * (size_t)node + 2);
-      const int4 e = gld(reinterpret_cast<const int4*>(N), 4 * (size_t)node + 3);
       if (CW) wc.nodes++;
-      float n0, n1;
-      const bool h0 = slab_line(a.x, a.y, a.z, a.w, b.x, b.y, inv, oi, tf, tb, n0);
-      const bool h1 = slab_line(b.z, b.w, c.x, c.y, c.z, c.w, inv, oi, tf, tb, n1);
-      const bool first0 = n0 <= n1;
-      if (h0 && h1) {
-        stk[sp * kTraceBlock + lane] = first0 ? e.y : e.x;
-        ++sp;
-        node = first0 ? e.x : e.y;
-      } else if (h0) {
-        node = e.x;
-      } else if (h1) {
-        node = e.y;
-      } else {
-        node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
-      }
+      node = visit4(N, node, stk, sp, test);
       if (node < 0 && pl == 0) {
         pl = node;
         node = sp > 0 ? stk[--sp * kTraceBlock + lane] : kDone;
@@ -656,7 +682,7 @@ DEV Cross edge_cross(const DevScene& S, const DevFrame& F, const End& A, const E
   const vec3 la = pose_inv_apply(F.ghost, a), ld = pose_inv_rot(F.ghost, b - a);
   const vec3 u = env ? unit(s.d) : unit(b - a);
   const float tmax = s.tmax;
-  bvh_walk<CW>(S.obj.nodes, go, gd, tmax, stk, wc, [&](int code) {
+  bvh_walk<CW, false>(S.obj.nodes, go, gd, tmax, stk, wc, [&](int code) {
     const int f = leaf_first(code), n = leaf_count(code);
     for (int i = f; i < f + n; ++i) {
       vec3 v0, e1, e2;
@@ -699,6 +725,22 @@ struct LightEnd {
   uint32_t mat; // emitter material index
   int env;
 };
+// The first CDF entry strictly above u (clamped to n - 1): a binary search
+// over the range the guide table gives for u (g[j] .. g[j + 1], j = the
+// table slot of u), which returns the same index as a search over the whole
+// CDF with one or two loads instead of log2(n) dependent ones.
+DEV int cdf_find(const float* __restrict__ cdf, const int32_t* __restrict__ g, int bits, int n, float u) {
+  const int M = 1 << bits;
+  const int j = min((int)(u * (float)M), M - 1);  // u * 2^bits is exact
+  int lo = g[max(j, 0)], hi = g[max(j, 0) + 1];
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (cdf[mid] <= u) lo = mid + 1;
+    else hi = mid;
+  }
+  return min(lo, n - 1);
+}
+
 DEV bool sample_light(const DevScene& S, const float u[4], LightEnd& L) {
   // every branch writes the fields in the same order, which lets the
   // compiler keep a LightEnd in registers
@@ -710,14 +752,7 @@ DEV bool sample_light(const DevScene& S, const float u[4], LightEnd& L) {
     return true;
   }
   if (S.nlights == 0) return false;
-  // first CDF entry strictly above u
-  int lo = 0, hi = S.nlights;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (S.light_cdf[mid] <= u[1]) lo = mid + 1;
-    else hi = mid;
-  }
-  const int k = min(lo, S.nlights - 1);
+  const int k = cdf_find(S.light_cdf, S.light_guide, S.light_gbits, S.nlights, u[1]);
   vec3 v0, e1, e2;
   int id, mat;
   load_tri(S.light_tris, k, v0, e1, e2, id, mat);
@@ -741,13 +776,7 @@ DEV End end_light(const LightEnd& L) { return End{L.p, L.n, L.env ? END_ENV : EN
 // Uniform-by-area point on the object at `pose`.
 DEV void object_point(const DevScene& S, const Pose& pose, const float u[4], vec3& p, vec3& n, uint32_t& md,
                       int& tri) {
-  int lo = 0, hi = S.nobj;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (S.obj_cdf[mid] <= u[0]) lo = mid + 1;
-    else hi = mid;
-  }
-  const int k = min(lo, S.nobj - 1);
+  const int k = cdf_find(S.obj_cdf, S.obj_guide, S.obj_gbits, S.nobj, u[0]);
   vec3 v0, e1, e2;
   int id, mat;
   load_tri(S.obj_tris, k, v0, e1, e2, id, mat);

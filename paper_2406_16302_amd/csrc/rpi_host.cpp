@@ -71,17 +71,20 @@ struct HostTri {
 };
 
 struct BuiltBvh {
-  std::vector<float4> nodes;
+  std::vector<float4> nodes;  // binary while building, 4-wide after collapse4
   std::vector<float4> tris;
   int max_depth = 0;
+  int max_stack = 0;          // traversal stack entries a ray can need (4-wide)
 };
 
 constexpr int kLeafMax = 2;  // leaves of 2 triangles traced faster than 1, 3, 4 or 8 (measured)
 constexpr int kBins = 16;
 constexpr int kMedianDepth = 24;  // from this depth on splits are object medians (bounded stack use)
 
-// Binned SAH (16 bins per axis) with object-median splits from depth 24 on;
-// children's boxes are stored in their parent (64-byte nodes).
+// Binned SAH (16 bins per axis) with object-median splits from depth 24 on.
+// The binary tree it builds keeps both children's boxes and links in their
+// parent (4 float4: c0.lo.xyz, c0.hi.xyz, c1.lo.xyz, c1.hi.xyz, then the two
+// links); collapse4 turns it into the device's 4-wide nodes.
 class Builder {
  public:
   explicit Builder(const std::vector<HostTri>& t) : tris_(t) {
@@ -298,6 +301,149 @@ class Builder {
   int median_depth_ = kMedianDepth;
 };
 
+// Collapse the binary BVH into 4-wide nodes (kNodeF4 float4 per node: the
+// children's lo.x, hi.x, lo.y, hi.y, lo.z, hi.z planes, then their links;
+// unused slots hold kEmptyLink).  A 4-wide visit tests up to four boxes
+// with one dependent fetch, and the traversal of a ray takes about half as
+// many dependent steps.  A node visit pushes up to (children - 1) entries,
+// so wider nodes need more stack: each binary subtree v gets a budget b(v)
+// of entries, a node widens (replacing its largest-area inner child by that
+// child's two children) only while every resulting child c keeps
+// h(c) <= b - (children - 1), where h is the binary height (the entries a
+// binary traversal below c can push), and its children inherit
+// b - (children - 1).  With b(root) = kStackDepth - 1 >= h(root) (the binary
+// builder's guarantee) no path can push more than kStackDepth - 1 entries.
+bool collapse4(BuiltBvh& bvh, std::string& err) {
+  const std::vector<float4>& in = bvh.nodes;
+  const int n2 = (int)in.size() / 4;
+  struct Child {
+    float lo[3], hi[3];
+    int32_t link;
+  };
+  auto child = [&](int node, int slot) {
+    const float* f = reinterpret_cast<const float*>(&in[4 * (size_t)node]);
+    const int32_t* iv = reinterpret_cast<const int32_t*>(&in[4 * (size_t)node + 3]);
+    Child c;
+    for (int a = 0; a < 3; ++a) {
+      c.lo[a] = f[6 * slot + a];
+      c.hi[a] = f[6 * slot + 3 + a];
+    }
+    c.link = iv[slot];
+    return c;
+  };
+  // binary heights, children after their parent in the array
+  std::vector<int> h(n2, 0);
+  for (int i = n2 - 1; i >= 0; --i) {
+    int m = 0;
+    for (int slot = 0; slot < 2; ++slot) {
+      const int32_t l = child(i, slot).link;
+      if (l >= 0) {
+        if (l <= i || l >= n2) {
+          err = "binary BVH link out of order";
+          return false;
+        }
+        m = std::max(m, h[l]);
+      }
+    }
+    h[i] = 1 + m;
+  }
+  auto hc = [&](const Child& c) { return c.link >= 0 ? h[c.link] : 0; };
+  auto area = [](const Child& c) {
+    const float dx = c.hi[0] - c.lo[0], dy = c.hi[1] - c.lo[1], dz = c.hi[2] - c.lo[2];
+    return dx * dy + dy * dz + dz * dx;
+  };
+  const int root_budget = kStackDepth - 1;
+  if (h[0] > root_budget) {
+    err = "BVH deeper than the traversal stack";
+    return false;
+  }
+  std::vector<float4> out;
+  struct Job {
+    int bin, budget, wide, depth;  // binary node, its budget, its 4-wide node, stack entries above it
+  };
+  std::vector<Job> st;
+  out.resize(kNodeF4);
+  st.push_back({0, root_budget, 0, 0});
+  int max_stack = 0;
+  while (!st.empty()) {
+    const Job j = st.back();
+    st.pop_back();
+    std::vector<Child> C = {child(j.bin, 0), child(j.bin, 1)};
+    while (C.size() < 4) {
+      int best = -1;
+      float best_area = -1.0f;
+      for (int k = 0; k < (int)C.size(); ++k) {
+        if (C[k].link < 0) continue;
+        // children after expanding C[k]: all must fit the budget left to them
+        const int cost = (int)C.size();  // (size + 1) children -> size entries
+        bool ok = true;
+        for (int q = 0; q < (int)C.size() && ok; ++q)
+          if (q != k) ok = hc(C[q]) <= j.budget - cost;
+        for (int slot = 0; slot < 2 && ok; ++slot) ok = hc(child(C[k].link, slot)) <= j.budget - cost;
+        if (ok && area(C[k]) > best_area) {
+          best_area = area(C[k]);
+          best = k;
+        }
+      }
+      if (best < 0) break;
+      const int b = C[best].link;
+      C[best] = child(b, 0);
+      C.push_back(child(b, 1));
+    }
+    const int pushes = (int)C.size() - 1;
+    max_stack = std::max(max_stack, j.depth + pushes);
+    float* f = reinterpret_cast<float*>(&out[(size_t)kNodeF4 * j.wide]);
+    int32_t* links = reinterpret_cast<int32_t*>(&out[(size_t)kNodeF4 * j.wide + 6]);
+    for (int k = 0; k < 4; ++k) {
+      if (k < (int)C.size()) {
+        for (int a = 0; a < 3; ++a) {
+          f[8 * a + k] = C[k].lo[a];
+          f[8 * a + 4 + k] = C[k].hi[a];
+        }
+        if (C[k].link < 0) {
+          links[k] = C[k].link;
+        } else {
+          const int w = (int)(out.size() / kNodeF4);
+          out.resize(out.size() + kNodeF4);
+          f = reinterpret_cast<float*>(&out[(size_t)kNodeF4 * j.wide]);  // the resize moved the array
+          links = reinterpret_cast<int32_t*>(&out[(size_t)kNodeF4 * j.wide + 6]);
+          links[k] = w;
+          st.push_back({C[k].link, j.budget - pushes, w, j.depth + pushes});
+        }
+      } else {
+        for (int a = 0; a < 3; ++a) {
+          f[8 * a + k] = 0.0f;
+          f[8 * a + 4 + k] = 0.0f;
+        }
+        links[k] = kEmptyLink;
+      }
+    }
+    float* pad = reinterpret_cast<float*>(&out[(size_t)kNodeF4 * j.wide + 7]);
+    for (int k = 0; k < 4; ++k) pad[k] = 0.0f;
+  }
+  if (max_stack > kStackDepth) {
+    err = "4-wide BVH exceeds the traversal stack";
+    return false;
+  }
+  // every link inside the arrays
+  const int n4 = (int)(out.size() / kNodeF4);
+  const int ntri = (int)(bvh.tris.size() / 3);
+  for (int i = 0; i < n4; ++i) {
+    const int32_t* links = reinterpret_cast<const int32_t*>(&out[(size_t)kNodeF4 * i + 6]);
+    for (int k = 0; k < 4; ++k) {
+      const int32_t l = links[k];
+      if (l >= 0 ? (l <= i || l >= n4)
+                 : (int)(((uint32_t)l & 0x7fffffffu) >> 4) + (int)(l & 15) > ntri) {
+        err = "4-wide BVH link out of range";
+        return false;
+      }
+    }
+  }
+  bvh.nodes.swap(out);
+  bvh.max_stack = max_stack;
+  return true;
+}
+
 Pose pose_of(const float* m) {
   Pose P;
   for (int i = 0; i < 3; ++i) {
@@ -418,6 +564,26 @@ static void dev_free(const rpi_scene* s, void* p, hipStream_t st, bool async) {
   if (s->has_al) s->al.deallocate(s->al.ctx, p, (void*)st);
   else if (async) (void)hipFreeAsync(p, st);
   else (void)hipFree(p);
+}
+
+// Guide table of a CDF (the cutpoint method of Chen and Asau 1974): with
+// M = 2^bits (the power of two >= n, at most 2^22), g[j] is the first index
+// whose CDF value exceeds j / M (j = 0..M; j / M is exact in float).  The
+// first index above any u in [j / M, (j + 1) / M) lies in [g[j], g[j + 1]],
+// so a search over that range returns what a search over the whole CDF
+// returns.
+static void cdf_guide(const std::vector<float>& cdf, std::vector<int32_t>& g, int& bits) {
+  const int n = (int)cdf.size();
+  bits = 0;
+  while ((1 << bits) < n && bits < 22) ++bits;
+  const int M = 1 << bits;
+  g.assign(M + 1, 0);
+  int i = 0;
+  for (int j = 0; j <= M; ++j) {
+    const float x = (float)j / (float)M;
+    while (i < n && cdf[i] <= x) ++i;
+    g[j] = i;
+  }
 }
 
 template <class T>
@@ -622,11 +788,11 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, const rpi_allocat
   std::string err;
   {
     Builder b(stat);
-    if (!b.build(bs, err)) return fail(RPI_ERR_UNSUPPORTED, "static BVH: " + err);
+    if (!b.build(bs, err) || !collapse4(bs, err)) return fail(RPI_ERR_UNSUPPORTED, "static BVH: " + err);
   }
   {
     Builder b(obj);
-    if (!b.build(bo, err)) return fail(RPI_ERR_UNSUPPORTED, "object BVH: " + err);
+    if (!b.build(bo, err) || !collapse4(bo, err)) return fail(RPI_ERR_UNSUPPORTED, "object BVH: " + err);
   }
   S->bvh_depth_static = bs.max_depth;
   S->bvh_depth_obj = bo.max_depth;
@@ -679,11 +845,16 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, const rpi_allocat
     if (*p) S->allocs.push_back((void*)*p);
     return r;
   };
+  std::vector<int32_t> ogd, lgd;
+  int ogb, lgb;
+  cdf_guide(ocdf, ogd, ogb);
+  cdf_guide(lcdf, lgd, lgb);
   float4 *sn, *stt, *on, *ot, *of, *lf;
   float *oc, *lc, *mt;
+  int32_t *og, *lg;
   if ((rc = up(bs.nodes, &sn)) || (rc = up(bs.tris, &stt)) || (rc = up(bo.nodes, &on)) || (rc = up(bo.tris, &ot)) ||
       (rc = up(obj_flat, &of)) || (rc = up(light_flat, &lf)) || (rc = up(ocdf, &oc)) || (rc = up(lcdf, &lc)) ||
-      (rc = up(mats, &mt))) {
+      (rc = up(mats, &mt)) || (rc = up(ogd, &og)) || (rc = up(lgd, &lg))) {
     for (void* p : S->allocs) dev_free(S.get(), p, nullptr, false);
     return rc;
   }
@@ -692,9 +863,13 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, const rpi_allocat
   D.obj_tris = of;
   D.obj_cdf = oc;
   D.nobj = (int)obj.size();
+  D.obj_guide = og;
+  D.obj_gbits = ogb;
   D.light_tris = lf;
   D.light_cdf = lc;
   D.nlights = (int)la.size();
+  D.light_guide = lg;
+  D.light_gbits = lgb;
   D.mats = mt;
   D.nmats = d->num_materials;
   D.inv_obj_area = (float)(1.0 / otot);

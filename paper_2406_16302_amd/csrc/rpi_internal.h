@@ -54,12 +54,16 @@ RPI_HD vec3 pose_inv_apply(const Pose& P, vec3 p) {
 // ------------------------------------------------------------------ scene on the device
 enum { MAT_DIFFUSE = 0, MAT_GGX = 1, MAT_EMITTER = 2 };
 
-// BVH2 node (64 B): both children's boxes and links.
-//   f4[0] = c0.lo.xyz, c0.hi.x   f4[1] = c0.hi.yz, c1.lo.xy
-//   f4[2] = c1.lo.z, c1.hi.xyz   f4[3] = child0, child1 (int bits), 0, 0
+// 4-wide BVH node (128 B, kNodeF4 float4): the boxes of children 0..3 as
+// planes, then their links:
+//   f4[0] = lo.x of c0..c3   f4[1] = hi.x   f4[2] = lo.y   f4[3] = hi.y
+//   f4[4] = lo.z             f4[5] = hi.z   f4[6] = links (int bits)   f4[7] = 0
 // A child link >= 0 is an inner node; a negative link is a leaf
-// 0x80000000 | first << 4 | count (count <= 15) into the triangle array.
+// 0x80000000 | first << 4 | count (count <= 15) into the triangle array;
+// unused slots hold kEmptyLink and are never entered.  The root is node 0.
 // Triangle (48 B): f4[0] = v0.xyz, id; f4[1] = e1.xyz, material; f4[2] = e2.xyz, 0.
+constexpr int kNodeF4 = 8;
+constexpr int32_t kEmptyLink = (int32_t)0x80000000;  // a leaf of no triangles
 struct DevBvh {
   const float4* nodes;
   const float4* tris;
@@ -68,7 +72,7 @@ struct DevBvh {
 
 // Traversal stack entries per lane (LDS: kStackDepth * 256 B per wave).  At
 // 40 a compute unit holds 16 waves of the trace kernels, four per SIMD; the
-// builder keeps every leaf at depth < kStackDepth.
+// builder bounds the entries any ray can push by kStackDepth - 1.
 #ifndef RPI_STACK_DEPTH
 #define RPI_STACK_DEPTH 40
 #endif
@@ -86,9 +90,13 @@ struct DevScene {
   const float4* obj_tris;  // object triangles in input order (area sampling), 3 float4 each
   const float* obj_cdf;
   int32_t nobj;
+  const int32_t* obj_guide;  // guide table of obj_cdf: 2^obj_gbits + 1 entries
+  int32_t obj_gbits;
   const float4* light_tris;  // emitter triangles in input order
   const float* light_cdf;
   int32_t nlights;
+  const int32_t* light_guide;
+  int32_t light_gbits;
   const float* mats;  // 8 floats per material
   int32_t nmats;
   float inv_obj_area;   // p_D = p_G

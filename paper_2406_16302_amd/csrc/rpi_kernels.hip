@@ -649,21 +649,12 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 // Persistent walk kernel: each wave pulls 64-sample work items (job,
 // direction, sample range) from a round counter until the round is drained,
 // which balances jobs of uneven image size and uneven per-sample cost.
-// Occupancy target of the trace-heavy kernels (waves per SIMD; 0 leaves the
+// Occupancy targets of the trace-heavy kernels (waves per SIMD; 0 leaves the
 // register allocation to the compiler).  The 10 KB LDS stack per wave lets a
-// compute unit hold 16 waves, four per SIMD; at four the walk-phase and
-// connect kernels spill a few registers, and still run faster than at three
-// (measured: -8% time per step for the start kernels, -4% for the others).
-#ifndef RPI_TRACE_WAVES_PER_EU
-#define RPI_TRACE_WAVES_PER_EU 4
-#endif
-#if RPI_TRACE_WAVES_PER_EU > 0
-#define RPI_TRACE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_TRACE_WAVES_PER_EU)))
-#else
-#define RPI_TRACE_OCCUPANCY
-#endif
+// compute unit hold 16 waves, four per SIMD.  The start kernels fit four
+// without spills.
 #ifndef RPI_START_WAVES_PER_EU
-#define RPI_START_WAVES_PER_EU RPI_TRACE_WAVES_PER_EU
+#define RPI_START_WAVES_PER_EU 4
 #endif
 #if RPI_START_WAVES_PER_EU > 0
 #define RPI_START_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_START_WAVES_PER_EU)))
@@ -688,11 +679,6 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
 #define RPI_CONNECT_WAVES_PER_EU 3
 #endif
 #define RPI_CONNECT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_CONNECT_WAVES_PER_EU)))
-#if RPI_START_WAVES_PER_EU > 0
-#define RPI_START_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RPI_START_WAVES_PER_EU)))
-#else
-#define RPI_START_OCCUPANCY
-#endif
 
 // ------------------------------------------------------------------ walk tasks
 
@@ -1218,7 +1204,6 @@ DEV void sm_step(const WalkArgs& A, SmLane& L, SmQuery& q, uint32_t t, WorkCount
 template <int TECH, bool CW>
 __global__ __launch_bounds__(kTraceBlock) RPI_WALK_OCCUPANCY(TECH) void walk_task_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
-  constexpr int kDone = 0x7fffffff;  // no node left in the stage
   const int lane = threadIdx.x;
   const uint32_t n = min(*A.W.ntasks, (uint32_t)A.W.Q);
   WorkCount wc{};
@@ -1276,25 +1261,11 @@ __global__ __launch_bounds__(kTraceBlock) RPI_WALK_OCCUPANCY(TECH) void walk_tas
       // can take their next queries (all of them once the queue is drained)
       if (__popcll(__ballot(q.stage != QS_NONE)) <= (drained ? 0 : RPI_SM_REFILL)) break;
       while (q.stage != QS_NONE && (uint32_t)q.node < (uint32_t)kDone) {
-        const float4 a = gld(q.nodes, 4 * (size_t)q.node), b = gld(q.nodes, 4 * (size_t)q.node + 1),
-                     c = gld(q.nodes, 4 * (size_t)q.node + 2);
-        const int4 e = gld(reinterpret_cast<const int4*>(q.nodes), 4 * (size_t)q.node + 3);
         if (CW) wc.nodes++;
-        float n0, n1;
-        const bool h0 = slab(a.x, a.y, a.z, a.w, b.x, b.y, q.inv, q.oi, q.tmax, n0);
-        const bool h1 = slab(b.z, b.w, c.x, c.y, c.z, c.w, q.inv, q.oi, q.tmax, n1);
-        const bool first0 = n0 <= n1;
-        if (h0 && h1) {
-          stk[q.sp * kTraceBlock + lane] = first0 ? e.y : e.x;
-          ++q.sp;
-          q.node = first0 ? e.x : e.y;
-        } else if (h0) {
-          q.node = e.x;
-        } else if (h1) {
-          q.node = e.y;
-        } else {
-          q.node = q.sp > 0 ? stk[--q.sp * kTraceBlock + lane] : kDone;
-        }
+        q.node = visit4(q.nodes, q.node, stk, q.sp, [&](float lx, float ly, float lz, float hx, float hy, float hz,
+                                                        float& tn) {
+          return slab(lx, ly, lz, hx, hy, hz, q.inv, q.oi, q.tmax, tn);
+        });
         if (q.node < 0 && q.pl == 0) {  // postpone the first leaf and go on with the stack
           q.pl = q.node;
           q.node = q.sp > 0 ? stk[--q.sp * kTraceBlock + lane] : kDone;
