@@ -107,6 +107,23 @@ def measured_traffic(kernel, workload, queue_cap):
     return rec.get("traffic_bytes_per_launch")
 
 
+def measured_valu(workload, queue_cap):
+    """VALU utilisation per kernel group from the committed rocprofv3 counter
+    summary (SQ_INSTS_VALU over the dispatch time against the chip's wave64
+    issue rate; SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU) for the
+    lanes), if it was taken on the current kernel sources with the same round
+    size (else {})."""
+    try:
+        with open(os.path.join(HERE, "profiles", "valu_utilisation_%s.md" % workload)) as fh:
+            m = re.search(r"```json\n(.*?)\n```", fh.read(), re.S)
+        rec = json.loads(m.group(1))
+    except (OSError, AttributeError, ValueError):
+        return {}
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("queue_cap") != queue_cap:
+        return {}
+    return rec.get("groups", {})
+
+
 def copy_only():
     import torch
     n = 1 << 28  # float32 elements: 1 GiB
@@ -127,8 +144,10 @@ def kernel_bytes(cw, k):
 def rooflines(cw, kms, klaunch, steps, workload, queue_cap):
     """The dominant kernel's roofline and the walk phase's (all start- and
     walk-phase kernels together): algorithmic bytes per launch (BVH nodes x
-    64 B + triangles x 48 B + record bytes written, counted by the
-    instrumented pass) / the HIP-event-timed launch duration."""
+    112 B + triangles x 48 B + record bytes written, counted by the
+    instrumented pass) / the HIP-event-timed launch duration; with each, the
+    VALU utilisation of the committed counter summary (null once the kernel
+    sources or the round size differ)."""
     kid = max(KIDS, key=lambda k: kms[k])
     launches = max(klaunch[kid] / steps, 1)
     avg_ms = kms[kid] / max(klaunch[kid], 1)
@@ -140,13 +159,16 @@ def rooflines(cw, kms, klaunch, steps, workload, queue_cap):
            "kernel": KERNEL_NAMES[kid], "avg_launch_ms": round(avg_ms, 4),
            "algorithmic_bytes_per_launch": int(kb / launches),
            "device_time_share": round(float(kms[kid] / kms[KIDS].sum()), 3)}
+    valu = measured_valu(workload, queue_cap)
+    top["valu"] = valu.get(KERNEL_NAMES[kid])
     wb = sum(kernel_bytes(cw, k) for k in WALK_KIDS)
     wms = float(sum(kms[k] for k in WALK_KIDS)) / steps
     wach = wb / (wms / 1e3) / 1e9 if wms > 0 else 0.0
     walk = {"bound": "hbm", "achieved": round(wach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(wach / HBM_PEAK_GBS, 4), "kernels": "walk_kernel<t> + walk_task_kernel<t>",
             "ms_per_step": round(wms, 2), "algorithmic_bytes_per_step": int(wb),
-            "device_time_share": round(float(sum(kms[k] for k in WALK_KIDS) / kms[KIDS].sum()), 3)}
+            "device_time_share": round(float(sum(kms[k] for k in WALK_KIDS) / kms[KIDS].sum()), 3),
+            "valu": valu.get("walk_phase")}
     return top, walk
 
 
