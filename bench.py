@@ -137,6 +137,32 @@ def copy_only():
 
 
 # ----------------------------------------------------------------- rooflines
+_ACHIEVABLE = []
+
+
+def achievable_hbm_gbs():
+    """HBM bandwidth a plain device copy reaches here: 1 GiB copied five
+    times, (bytes read + bytes written) / the median HIP-event time."""
+    if not _ACHIEVABLE:
+        import torch
+        n = 1 << 28  # float32 elements: 1 GiB
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        del a, b
+        torch.cuda.empty_cache()
+        _ACHIEVABLE.append(2.0 * 4 * n / (float(np.median(ts)) / 1e3) / 1e9)
+    return _ACHIEVABLE[0]
+
+
 def kernel_bytes(cw, k):
     return cw["kernel_nodes"][k] * NODE_BYTES + cw["kernel_tris"][k] * TRI_BYTES + cw["kernel_bytes_written"][k]
 
@@ -145,7 +171,8 @@ def rooflines(cw, kms, klaunch, steps, workload, queue_cap):
     """The dominant kernel's roofline and the walk phase's (all start- and
     walk-phase kernels together): algorithmic bytes per launch (BVH nodes x
     112 B + triangles x 48 B + record bytes written, counted by the
-    instrumented pass) / the HIP-event-timed launch duration; with each, the
+    instrumented pass) / the HIP-event-timed launch duration, against the
+    published peak and against what a device copy reaches; with each, the
     VALU utilisation of the committed counter summary (null once the kernel
     sources or the round size differ)."""
     kid = max(KIDS, key=lambda k: kms[k])
@@ -155,6 +182,8 @@ def rooflines(cw, kms, klaunch, steps, workload, queue_cap):
     achieved = (kb / launches) / (avg_ms / 1e3) / 1e9
     top = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "achievable": round(achievable_hbm_gbs(), 1),
+           "frac_of_achievable": round(achieved / achievable_hbm_gbs(), 4),
            "traffic": measured_traffic(KERNEL_NAMES[kid], workload, queue_cap),
            "kernel": KERNEL_NAMES[kid], "avg_launch_ms": round(avg_ms, 4),
            "algorithmic_bytes_per_launch": int(kb / launches),
@@ -165,7 +194,9 @@ def rooflines(cw, kms, klaunch, steps, workload, queue_cap):
     wms = float(sum(kms[k] for k in WALK_KIDS)) / steps
     wach = wb / (wms / 1e3) / 1e9 if wms > 0 else 0.0
     walk = {"bound": "hbm", "achieved": round(wach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(wach / HBM_PEAK_GBS, 4), "kernels": "walk_kernel<t> + walk_task_kernel<t>",
+            "frac": round(wach / HBM_PEAK_GBS, 4), "achievable": round(achievable_hbm_gbs(), 1),
+            "frac_of_achievable": round(wach / achievable_hbm_gbs(), 4),
+            "kernels": "walk_kernel<t> + walk_task_kernel<t>",
             "ms_per_step": round(wms, 2), "algorithmic_bytes_per_step": int(wb),
             "device_time_share": round(float(sum(kms[k] for k in WALK_KIDS) / kms[KIDS].sum()), 3),
             "valu": valu.get("walk_phase")}
