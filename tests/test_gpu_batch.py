@@ -93,3 +93,24 @@ def test_autotune_returns_a_configuration():
     t = native.autotune(sc, ed, native.Params.make(16, 3, 1))
     assert t["queue_cap"] in (1 << 23, 1 << 24, 1 << 25) and t["walk_blocks_per_cu"] in (16, 32)
     assert t["ms_per_msample"] > 0
+
+
+def test_batch_with_balance_across_directions_matches_oracle():
+    """RPI_FLAG_BALANCE in the batched launch: each job against the oracle's
+    cross-direction balance heuristic with its own poses and job index."""
+    import oracle
+    from gpu_parity import rel_l2
+    from paper_2406_16302_amd import native
+    ws = scenes.cornell_motion(width=24, height=24, depth=4)
+    sc = native.Scene(ws.scene)
+    sizes = [(24, 24), (32, 16)]
+    offs = [(0.1, 0, 0.05), (-0.06, 0.0, 0.07)]
+    jobs = _jobs(sizes, offs)
+    p = native.Params.make(4, 4, 71, job=3, flags=native.FLAG_TWO_WAY | native.FLAG_BALANCE)
+    native.render_residual_batch(sc, jobs, p)
+    torch.cuda.synchronize()
+    for j, ((w, h), off) in enumerate(zip(sizes, offs)):
+        o = oracle.OracleScene(ws.scene.with_resolution(w, h))
+        ref = o.render_residual(4, 4, 71, pose_new=scenes.translation(off), job=3 + j, threads=8, balance=True)
+        assert np.abs(ref["image"]).sum() > 0
+        assert rel_l2(jobs[j]["out"].cpu().numpy().astype(np.float64), ref["image"]) < 1e-3, j
