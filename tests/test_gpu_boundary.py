@@ -158,14 +158,17 @@ def test_sync_status_reports_ok():
     native.sync_status(s)
 
 
-@pytest.mark.parametrize("name", ["cornell_motion", "cornell_material"])
+@pytest.mark.parametrize("name", ["cornell_motion", "cornell_material", "cornell_motion_balance"])
 def test_unequal_technique_counts_match_oracle(name):
     """Per-technique sample counts (balance heuristic over unequal counts)
-    against the oracle on the same Philox streams, record by record."""
+    against the oracle on the same Philox streams, record by record; with
+    RPI_FLAG_BALANCE the mapped path's strategy sum carries the same count
+    ratios."""
     from gpu_parity import compare_records, rel_l2
     import oracle
     from paper_2406_16302_amd import native
-    if name == "cornell_motion":
+    balance = name.endswith("_balance")
+    if name.startswith("cornell_motion"):
         ws = scenes.cornell_motion(width=32, height=32, depth=5, spp=4)
         counts = [8, 2, 4, 6, 2, 4, 1, 0]
     else:
@@ -175,14 +178,15 @@ def test_unequal_technique_counts_match_oracle(name):
     sc = native.Scene(ws.scene)
     ed = native.Edit(sc, ws.edit)
     material = ws.edit.kind == scenes.EDIT_MATERIAL
-    flags = (0 if material else native.FLAG_TWO_WAY) | native.FLAG_RECORDS
+    flags = (0 if material else native.FLAG_TWO_WAY) | native.FLAG_RECORDS | (native.FLAG_BALANCE if balance else 0)
     out = torch.zeros((32, 32, 3), dtype=torch.float32, device="cuda")
     st = native.render_residual(sc, ed, native.Params.make(ws.spp, ws.depth, ws.seed, mask=ws.mask, flags=flags,
                                                            technique_spp=counts), out, stats=True)
     per_dir = 1 if material else 2
     assert st["samples"] == per_dir * 32 * 32 * sum(c for t, c in enumerate(counts) if (ws.mask >> t) & 1)
     g = sc.records()
-    o = oracle.residual_for(ws, oracle.OracleScene(ws.scene), threads=1, records=True, tech_spp=counts)
+    o = oracle.residual_for(ws, oracle.OracleScene(ws.scene), threads=1, records=True, tech_spp=counts,
+                            balance=balance)
     c = compare_records(g, o["records"])
     print(c, flush=True)
     assert c["oracle"] > 1000

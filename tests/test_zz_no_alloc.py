@@ -17,12 +17,12 @@ def need_gpu():
         pytest.skip("no HIP device")
 
 
-def _pair(ws, **kw):
+def _pair(ws, extra_flags=0, **kw):
     from paper_2406_16302_amd import native
     sc = native.Scene(ws.scene)
     ed = native.Edit(sc, ws.edit)
     material = ws.edit.kind == scenes.EDIT_MATERIAL
-    flags = 0 if material else native.FLAG_TWO_WAY
+    flags = (0 if material else native.FLAG_TWO_WAY) | extra_flags
     p = native.Params.make(ws.spp, ws.depth, ws.seed, mask=ws.mask, flags=flags, **kw)
     ref = torch.zeros((sc.height, sc.width, 3), dtype=torch.float32, device="cuda")
     st = native.render_residual(sc, ed, p, ref, stats=True)
@@ -52,6 +52,16 @@ def test_noalloc_matches_render_residual_on_two_calls():
     assert st2["paths"] > 100
     print("rel L2 %.3g" % rel_l2(got2, ref2), flush=True)
     assert rel_l2(got2, ref2) <= 1e-3
+
+
+def test_noalloc_balance_across_directions():
+    from gpu_parity import rel_l2
+    from paper_2406_16302_amd import native
+    ws = scenes.clutter_motion(width=64, height=48, depth=5, spp=8, n_spheres=60)
+    print("noalloc balance: clutter 64x48 d5 spp8", flush=True)
+    ref, got, st = _pair(ws, extra_flags=native.FLAG_BALANCE)
+    assert st["accepted"] > 100
+    assert rel_l2(got, ref) <= 1e-3
 
 
 def test_noalloc_material_edit_and_technique_images():
