@@ -44,9 +44,10 @@ HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES = 112, 48  # 4-wide node: six box planes and the links (its padding is not read)
 KERNEL_NAMES = {t: "walk_kernel<%d>" % t for t in range(1, 9)}          # start phase of technique t
 KERNEL_NAMES.update({16 + t: "walk_task_kernel<%d>" % t for t in range(1, 9)})  # its walk phase
-KERNEL_NAMES.update({9: "connect_kernel", 10: "splat", 12: "proposal_pdf_kernel", 13: "t8_start_kernel"})
+KERNEL_NAMES.update({9: "connect_kernel", 10: "splat", 12: "proposal_pdf_kernel", 13: "t8_start_kernel",
+                     14: "start_order_kernel"})
 KIDS = sorted(KERNEL_NAMES)
-WALK_KIDS = [k for k in KIDS if k <= 8 or k >= 17]
+WALK_KIDS = [k for k in KIDS if k <= 8 or k >= 14]
 RAY_TYPES = ["closest", "shadow", "camera", "ghost", "map_retrace", "map_visibility"]
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["rpi_kernels.hip", "rpi_device.h", "rpi_internal.h", "rpi_mlp.h"]

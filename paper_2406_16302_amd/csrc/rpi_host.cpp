@@ -1147,7 +1147,7 @@ struct Ws {
 // Byte offsets of the workspace parts for rounds of Q samples.
 struct WsLayout {
   size_t eye, light, start, counts, pairs, pairs2, np, rec, keys, ks, t8, stats, tc, to, cp, hist, bin, jobs, pre, tj,
-      ic, tc2, task, nt, acc, bytes;
+      ic, tc2, task, nt, acc, order, okey, bytes;
 };
 
 static WsLayout ws_layout(int Q, int depth, int64_t pair_cap, int ntiles, int njobs, bool keep, bool t8,
@@ -1185,6 +1185,8 @@ static WsLayout ws_layout(int Q, int depth, int64_t pair_cap, int ntiles, int nj
   L.task = take((size_t)kTaskFields * Q * sizeof(float4));
   L.nt = take(256);
   L.acc = take((size_t)acc_elems * 8);
+  L.order = take((size_t)Q * 4);
+  L.okey = take((size_t)Q * 2);
   L.bytes = off;
   return L;
 }
@@ -1200,6 +1202,8 @@ static void ws_bind(Ws& w, const WsLayout& L, void* mem, int Q, int depth, int64
   w.W.counts = (uint32_t*)(b + L.counts);
   w.W.pairs = (uint32_t*)(b + L.pairs);
   w.W.pairs2 = (uint32_t*)(b + L.pairs2);
+  w.W.order = (uint32_t*)(b + L.order);
+  w.W.okey = (uint16_t*)(b + L.okey);
   w.W.npairs = (uint32_t*)(b + L.np);
   w.W.records = (float4*)(b + L.rec);
   w.W.rec_keys = keep ? (uint32_t*)(b + L.keys) : nullptr;
@@ -1481,6 +1485,11 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
       launch_zero_u32(w.W.ntasks, 64, st);  // the task count, the fetch counters, the length bins
       const int blocks = std::min<int64_t>(wblocks, A.nitems);
       rpi_status r;
+      // samples ordered by where they start (on the object or the ghost;
+      // path tracing: pixel tiles)
+      A.W.order = w.W.order;
+      r = timed(kKidStartOrder, [&] { launch_start_order(A, st); });
+      if (r) return r;
       if (t == 8) {
         r = timed(kKidT8Start, [&] { launch_t8_start(A, std::min<int64_t>(cblocks, A.nitems), st); });
         if (r) return r;

@@ -154,6 +154,8 @@ struct Workspace {
   uint32_t* fetch;     // [2] work counters of the walk phase (tasks) and the connect kernel (paths)
   uint32_t* kbins;     // [32] paths per length k, then the sort's cursors per k
   uint32_t* pairs2;    // [pair_cap] the path queue sorted by path length
+  uint32_t* order;     // [Q] or null: slot s of the round holds the sample of item-order slot order[s]
+  uint16_t* okey;      // [Q] the ordering pass's keys
   float4* t8q;         // technique (8) on: per queued path (2 float4), the proposal's
                        // solid-angle density at vertices x_1 .. x_5 (0 where not used)
   int32_t Q;           // samples per chunk
@@ -195,7 +197,8 @@ constexpr int kMaxRound = 1 << 25;  // samples per round: the path code holds sl
 // t, 17..24 its walk phase, then connect, splat, frame, the proposal's
 // densities and technique 8's MLP starts.
 constexpr int kKernelSlots = 32;
-constexpr int kKidConnect = 9, kKidSplat = 10, kKidFrame = 11, kKidProposalPdf = 12, kKidT8Start = 13;
+constexpr int kKidConnect = 9, kKidSplat = 10, kKidFrame = 11, kKidProposalPdf = 12, kKidT8Start = 13,
+              kKidStartOrder = 14;
 RPI_HD constexpr int kid_start(int t) { return t; }
 RPI_HD constexpr int kid_walk(int t) { return 16 + t; }
 // Techniques whose walks run in a separate phase over the compacted task
@@ -294,6 +297,7 @@ void launch_walk(const WalkArgs& A, int blocks, hipStream_t st);        // start
 void launch_walk_tasks(const WalkArgs& A, int blocks, hipStream_t st);  // walk phase (over the task queue)
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st);
 void launch_sort_pairs(const WalkArgs& A, hipStream_t st);
+void launch_start_order(const WalkArgs& A, hipStream_t st);  // fills A.W.order for the round
 // zero the jobs' technique images (if any) and fixed-point accumulation images
 void launch_zero_images(const DevJob* jobs, int njobs, hipStream_t st);
 // fixed-point accumulation -> float: tech = 0: into the job's image (added to

@@ -646,6 +646,128 @@ DEV int find_jd(const int64_t* pre, int n, int64_t g) {
   return lo;
 }
 
+// The sample a slot of the round holds.  Slots are in item order (item it,
+// lane l -> slot it * 64 + l, the sample's index following from the item's
+// place in its stream) unless start_order_kernel permuted the round; its
+// permutation stays within one (job, direction) stream, so a slot and the
+// slot whose sample it holds belong to the same stream.
+DEV int64_t slot_sample(const WalkArgs& A, const DevJob& J, int jd, int s) {
+  const int so = A.W.order ? (int)A.W.order[s] : s;
+  return J.s0 + (A.item0 + so / kItem - A.item_prefix[jd]) * kItem + so % kItem;
+}
+
+// Start order: within windows of order_items<t>() items of one (job,
+// direction) stream, the round's samples are counting-sorted by a key of
+// where they start, so that the lanes of a wave start close together and
+// their first rays take similar paths through the BVH.
+//   techniques 1-6 and 8: the cell of the start point (x_D on the object, x_G on
+//     the ghost, from the sample's first draw as its technique takes it) in a
+//     16 x 16 x 16 grid over that object's bounds, cells in Morton order
+//     (technique 3: an 8 x 8 x 8 grid under the octant of its first ray's
+//     direction);
+//   path tracing (7): the pixel, in 8-pixel column groups by row within the
+//     window, so that a wave covers an 8 x 8 tile.
+// Only the assignment of samples to slots changes: every sample keeps its
+// random numbers, and slot_sample follows the permutation.  Windows that
+// hold more than one stream keep the item order.  Samples past their
+// stream's end go last.  Pass 1 counts the keys (LDS) and keeps them in
+// W.okey, then the counts become each key's first place in the window, and
+// pass 2 places the slots.
+#ifndef RPI_ORDER_ITEMS
+#define RPI_ORDER_ITEMS 1024
+#endif
+constexpr int kOrderBins = 4096;
+template <int TECH>
+constexpr int order_items() { return TECH == 7 ? 64 : RPI_ORDER_ITEMS; }
+DEV uint32_t spread4(uint32_t c) { return (c & 1u) | ((c & 2u) << 2) | ((c & 4u) << 4) | ((c & 8u) << 6); }
+DEV uint32_t grid_cell16(float v, float a, float b) {
+  const float t = (v - a) / fmaxf(b - a, 1e-30f) * 16.0f;
+  return (uint32_t)min(15, max(0, (int)t));
+}
+template <int TECH>
+__global__ __launch_bounds__(256) void start_order_kernel(WalkArgs A) {
+  __shared__ uint32_t cnt[kOrderBins], part[256];
+  constexpr int kPerThread = kOrderBins / 256;
+  constexpr int kOrderItems = order_items<TECH>();
+  const int nwin = (A.nitems + kOrderItems - 1) / kOrderItems;
+  for (int w = blockIdx.x; w < nwin; w += gridDim.x) {
+    const int i0 = w * kOrderItems, i1 = min(i0 + kOrderItems, A.nitems);
+    const int p0 = i0 * kItem, p1 = i1 * kItem;
+    const int jd = find_jd(A.item_prefix, 2 * A.njobs, A.item0 + i0);
+    if (find_jd(A.item_prefix, 2 * A.njobs, A.item0 + i1 - 1) != jd) {
+      for (int p = p0 + (int)threadIdx.x; p < p1; p += 256) A.W.order[p] = (uint32_t)p;
+      continue;  // the same for the whole workgroup
+    }
+    for (int b = threadIdx.x; b < kOrderBins; b += 256) cnt[b] = 0u;
+    __syncthreads();
+    const DevJob& J = A.jobs[jd >> 1];
+    const int dir = jd & 1;
+    const DevFrame& F = J.F[dir];
+    const bool ghost = TECH >= 4 && TECH <= 6;
+    const vec3 lo = ghost ? F.glo : F.olo, hi = ghost ? F.ghi : F.ohi;
+    const int64_t lim = A.tech_spp ? (int64_t)A.tech_spp * J.W * J.H : J.s1;
+    const uint32_t P = (uint32_t)(J.W * J.H);
+    const int64_t smp0 = J.s0 + (A.item0 + i0 - A.item_prefix[jd]) * kItem;
+    const int y0 = (int)(((uint32_t)smp0 % P) / (uint32_t)J.W);
+    const int rows = (kOrderItems * kItem + J.W - 1) / J.W + 1;
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += 256) {
+      const int64_t smp = J.s0 + (A.item0 + p / kItem - A.item_prefix[jd]) * kItem + p % kItem;
+      uint32_t kk = kOrderBins - 1;
+      if (smp < lim && TECH == 7) {
+        const uint32_t pixel = (uint32_t)smp % P;
+        const int x = (int)(pixel % (uint32_t)J.W), y = (int)(pixel / (uint32_t)J.W);
+        kk = (uint32_t)min((x >> 3) * rows + (y - y0 + J.H) % J.H, kOrderBins - 2);
+      } else if (smp < lim) {
+        const Rng g{A.k0, A.k1, (uint32_t)smp, ((uint32_t)TECH << 24) | ((uint32_t)dir << 23),
+                    A.job_base + (uint32_t)(jd >> 1)};
+        float u[4];
+        draw(g, 0, 0, 0, u);
+        vec3 x, n;
+        uint32_t md;
+        int tri;
+        object_point(J.S, ghost ? F.ghost : F.pose, u, x, n, md, tri);
+        kk = spread4(grid_cell16(x.x, lo.x, hi.x)) | (spread4(grid_cell16(x.y, lo.y, hi.y)) << 1) |
+             (spread4(grid_cell16(x.z, lo.z, hi.z)) << 2);
+        if (TECH == 3) {
+          // technique 3's first ray leaves x_D in a cosine-lobe direction:
+          // its octant above an 8 x 8 x 8 grid
+          draw(g, 0, 0, 2, u);
+          const vec3 wd = cosine_dir(n, u[0], u[1]);
+          const uint32_t oct = (wd.x < 0.0f ? 1u : 0u) | (wd.y < 0.0f ? 2u : 0u) | (wd.z < 0.0f ? 4u : 0u);
+          kk = (oct << 9) | spread4(grid_cell16(x.x, lo.x, hi.x) >> 1) |
+               (spread4(grid_cell16(x.y, lo.y, hi.y) >> 1) << 1) | (spread4(grid_cell16(x.z, lo.z, hi.z) >> 1) << 2);
+        }
+      }
+      atomicAdd(&cnt[kk], 1u);
+      A.W.okey[p] = (uint16_t)kk;
+    }
+    __syncthreads();
+    {  // exclusive prefix sums: each key's first place in the window (kPerThread keys per thread)
+      const int t = threadIdx.x;
+      uint32_t sum = 0u;
+      for (int q = 0; q < kPerThread; ++q) sum += cnt[kPerThread * t + q];
+      part[t] = sum;
+      __syncthreads();
+      for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+      }
+      uint32_t run = part[t] - sum;
+      for (int q = 0; q < kPerThread; ++q) {
+        const uint32_t c = cnt[kPerThread * t + q];
+        cnt[kPerThread * t + q] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += 256)
+      A.W.order[p0 + atomicAdd(&cnt[A.W.okey[p]], 1u)] = (uint32_t)p;
+    __syncthreads();
+  }
+}
+
 // Persistent walk kernel: each wave pulls 64-sample work items (job,
 // direction, sample range) from a round counter until the round is drained,
 // which balances jobs of uneven image size and uneven per-sample cost.
@@ -716,8 +838,8 @@ __global__ __launch_bounds__(kTraceBlock) RPI_START_OCCUPANCY void walk_kernel(W
     const int jd = __builtin_amdgcn_readfirstlane(find_jd(A.item_prefix, 2 * A.njobs, g));
     const DevJob& J = A.jobs[jd >> 1];
     const int dir = jd & 1;
-    const int64_t smp = J.s0 + (g - A.item_prefix[jd]) * kItem + threadIdx.x;
     const int s = (int)it * kItem + threadIdx.x;
+    const int64_t smp = slot_sample(A, J, jd, s);
     const bool active = smp < (A.tech_spp ? (int64_t)A.tech_spp * J.W * J.H : J.s1);
     const Ctx C{J.S, J.F[dir], A.W, A.depth};
     Lane L{C, Rng{A.k0, A.k1, (uint32_t)smp, ((uint32_t)TECH << 24) | ((uint32_t)dir << 23), A.job_base + (uint32_t)(jd >> 1)},
@@ -1010,7 +1132,7 @@ DEV void sm_begin(const WalkArgs& A, SmLane& L, uint32_t t) {
   L.k2 = (int)__float_as_uint(h.z);
   const int64_t g = A.item0 + L.s / kItem;
   L.jd = find_jd(A.item_prefix, 2 * A.njobs, g);
-  L.smp = (uint32_t)(A.jobs[L.jd >> 1].s0 + (g - A.item_prefix[L.jd]) * kItem + L.s % kItem);
+  L.smp = (uint32_t)slot_sample(A, A.jobs[L.jd >> 1], L.jd, (int)L.s);
   L.nE = L.nL = 0;
   L.camok = L.neeok = L.dynpre = 0u;
   L.ph = PH_ESTART;
@@ -1302,7 +1424,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_WALK_OCCUPANCY(TECH) void walk_tas
 // per wave on the matrix cores) and the light-side direction drawn from its
 // vMF mixture (made defensive by a uniform-sphere component), into start records 0 (x_D, material), 1 (normal) and 3 (the
 // direction) of the sample's slot; walk_kernel<8> continues from there.
-// Items map to slots as in the walk kernel: item it, lane l -> it * 64 + l.
+// Slots hold the samples slot_sample gives them, as in the walk kernel.
 __global__ __launch_bounds__(kTraceBlock) void t8_start_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) float lds[kMlpLdsBytes / 4];
   for (uint32_t it = blockIdx.x; it < (uint32_t)A.nitems; it += gridDim.x) {
@@ -1311,8 +1433,8 @@ __global__ __launch_bounds__(kTraceBlock) void t8_start_kernel(WalkArgs A) {
     const DevJob& J = A.jobs[jd >> 1];
     const int dir = jd & 1;
     const DevFrame& F = J.F[dir];
-    const int64_t smp = J.s0 + (g - A.item_prefix[jd]) * kItem + threadIdx.x;
     const int s = (int)it * kItem + threadIdx.x;
+    const int64_t smp = slot_sample(A, J, jd, s);
     const bool active = smp < (A.tech_spp ? (int64_t)A.tech_spp * J.W * J.H : J.s1);
     const Rng rng{A.k0, A.k1, (uint32_t)smp, (8u << 24) | ((uint32_t)dir << 23), A.job_base + (uint32_t)(jd >> 1)};
     float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1909,7 +2031,7 @@ __global__ __launch_bounds__(kTraceBlock) RPI_CONNECT_OCCUPANCY void connect_ker
         // debug key: the pair as (i + 1) << 4 | (j + 1)
         const uint32_t pr = ((uint32_t)(code_i(code) + 1) << 4) | (uint32_t)(code_j(code) + 1);
         A.W.rec_keys[idx] = (uint32_t)dir | ((uint32_t)A.tech << 1) | (pr << 8);
-        A.W.rec_sample[idx] = (uint32_t)(J.s0 + (g - A.item_prefix[jd]) * kItem + s % kItem);
+        A.W.rec_sample[idx] = (uint32_t)slot_sample(A, J, jd, s);
       }
       if (A.stats && (reason <= 6 || reason == 9)) atomicAdd(&cnt[reason == 9 ? 7 : reason], 1ull);
     }
@@ -2439,6 +2561,20 @@ __global__ __launch_bounds__(256) void pair_sort_kernel(WalkArgs A) {
     const uint32_t code = A.W.pairs[i];
     const int k = path_len(code, A.tech);
     A.W.pairs2[base[k] + atomicAdd(&h[k], 1u)] = code;
+  }
+}
+void launch_start_order(const WalkArgs& A, hipStream_t st) {
+  const int items = A.tech == 7 ? order_items<7>() : order_items<1>();
+  const dim3 grid((unsigned)std::min((A.nitems + items - 1) / items, 2048));
+  switch (A.tech) {
+    case 1: hipLaunchKernelGGL(start_order_kernel<1>, grid, dim3(256), 0, st, A); break;
+    case 2: hipLaunchKernelGGL(start_order_kernel<2>, grid, dim3(256), 0, st, A); break;
+    case 3: hipLaunchKernelGGL(start_order_kernel<3>, grid, dim3(256), 0, st, A); break;
+    case 4: hipLaunchKernelGGL(start_order_kernel<4>, grid, dim3(256), 0, st, A); break;
+    case 5: hipLaunchKernelGGL(start_order_kernel<5>, grid, dim3(256), 0, st, A); break;
+    case 6: hipLaunchKernelGGL(start_order_kernel<6>, grid, dim3(256), 0, st, A); break;
+    case 7: hipLaunchKernelGGL(start_order_kernel<7>, grid, dim3(256), 0, st, A); break;
+    default: hipLaunchKernelGGL(start_order_kernel<8>, grid, dim3(256), 0, st, A); break;
   }
 }
 void launch_sort_pairs(const WalkArgs& A, hipStream_t st) {
