@@ -677,6 +677,7 @@ DEV int64_t slot_sample(const WalkArgs& A, const DevJob& J, int jd, int s) {
 #define RPI_ORDER_ITEMS 1024
 #endif
 constexpr int kOrderBins = 4096;
+constexpr int kOrderThreads = 1024;  // one workgroup per window
 template <int TECH>
 constexpr int order_items() { return TECH == 7 ? 64 : RPI_ORDER_ITEMS; }
 DEV uint32_t spread4(uint32_t c) { return (c & 1u) | ((c & 2u) << 2) | ((c & 4u) << 4) | ((c & 8u) << 6); }
@@ -685,9 +686,9 @@ DEV uint32_t grid_cell16(float v, float a, float b) {
   return (uint32_t)min(15, max(0, (int)t));
 }
 template <int TECH>
-__global__ __launch_bounds__(256) void start_order_kernel(WalkArgs A) {
-  __shared__ uint32_t cnt[kOrderBins], part[256];
-  constexpr int kPerThread = kOrderBins / 256;
+__global__ __launch_bounds__(kOrderThreads) void start_order_kernel(WalkArgs A) {
+  __shared__ uint32_t cnt[kOrderBins], part[kOrderThreads];
+  constexpr int kPerThread = kOrderBins / kOrderThreads;
   constexpr int kOrderItems = order_items<TECH>();
   const int nwin = (A.nitems + kOrderItems - 1) / kOrderItems;
   for (int w = blockIdx.x; w < nwin; w += gridDim.x) {
@@ -695,10 +696,10 @@ __global__ __launch_bounds__(256) void start_order_kernel(WalkArgs A) {
     const int p0 = i0 * kItem, p1 = i1 * kItem;
     const int jd = find_jd(A.item_prefix, 2 * A.njobs, A.item0 + i0);
     if (find_jd(A.item_prefix, 2 * A.njobs, A.item0 + i1 - 1) != jd) {
-      for (int p = p0 + (int)threadIdx.x; p < p1; p += 256) A.W.order[p] = (uint32_t)p;
+      for (int p = p0 + (int)threadIdx.x; p < p1; p += kOrderThreads) A.W.order[p] = (uint32_t)p;
       continue;  // the same for the whole workgroup
     }
-    for (int b = threadIdx.x; b < kOrderBins; b += 256) cnt[b] = 0u;
+    for (int b = threadIdx.x; b < kOrderBins; b += kOrderThreads) cnt[b] = 0u;
     __syncthreads();
     const DevJob& J = A.jobs[jd >> 1];
     const int dir = jd & 1;
@@ -710,7 +711,7 @@ __global__ __launch_bounds__(256) void start_order_kernel(WalkArgs A) {
     const int64_t smp0 = J.s0 + (A.item0 + i0 - A.item_prefix[jd]) * kItem;
     const int y0 = (int)(((uint32_t)smp0 % P) / (uint32_t)J.W);
     const int rows = (kOrderItems * kItem + J.W - 1) / J.W + 1;
-    for (int p = p0 + (int)threadIdx.x; p < p1; p += 256) {
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += kOrderThreads) {
       const int64_t smp = J.s0 + (A.item0 + p / kItem - A.item_prefix[jd]) * kItem + p % kItem;
       uint32_t kk = kOrderBins - 1;
       if (smp < lim && TECH == 7) {
@@ -748,7 +749,7 @@ __global__ __launch_bounds__(256) void start_order_kernel(WalkArgs A) {
       for (int q = 0; q < kPerThread; ++q) sum += cnt[kPerThread * t + q];
       part[t] = sum;
       __syncthreads();
-      for (int off = 1; off < 256; off <<= 1) {
+      for (int off = 1; off < kOrderThreads; off <<= 1) {
         const uint32_t v = t >= off ? part[t - off] : 0u;
         __syncthreads();
         part[t] += v;
@@ -762,7 +763,7 @@ __global__ __launch_bounds__(256) void start_order_kernel(WalkArgs A) {
       }
     }
     __syncthreads();
-    for (int p = p0 + (int)threadIdx.x; p < p1; p += 256)
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += kOrderThreads)
       A.W.order[p0 + atomicAdd(&cnt[A.W.okey[p]], 1u)] = (uint32_t)p;
     __syncthreads();
   }
@@ -2567,14 +2568,14 @@ void launch_start_order(const WalkArgs& A, hipStream_t st) {
   const int items = A.tech == 7 ? order_items<7>() : order_items<1>();
   const dim3 grid((unsigned)std::min((A.nitems + items - 1) / items, 2048));
   switch (A.tech) {
-    case 1: hipLaunchKernelGGL(start_order_kernel<1>, grid, dim3(256), 0, st, A); break;
-    case 2: hipLaunchKernelGGL(start_order_kernel<2>, grid, dim3(256), 0, st, A); break;
-    case 3: hipLaunchKernelGGL(start_order_kernel<3>, grid, dim3(256), 0, st, A); break;
-    case 4: hipLaunchKernelGGL(start_order_kernel<4>, grid, dim3(256), 0, st, A); break;
-    case 5: hipLaunchKernelGGL(start_order_kernel<5>, grid, dim3(256), 0, st, A); break;
-    case 6: hipLaunchKernelGGL(start_order_kernel<6>, grid, dim3(256), 0, st, A); break;
-    case 7: hipLaunchKernelGGL(start_order_kernel<7>, grid, dim3(256), 0, st, A); break;
-    default: hipLaunchKernelGGL(start_order_kernel<8>, grid, dim3(256), 0, st, A); break;
+    case 1: hipLaunchKernelGGL(start_order_kernel<1>, grid, dim3(kOrderThreads), 0, st, A); break;
+    case 2: hipLaunchKernelGGL(start_order_kernel<2>, grid, dim3(kOrderThreads), 0, st, A); break;
+    case 3: hipLaunchKernelGGL(start_order_kernel<3>, grid, dim3(kOrderThreads), 0, st, A); break;
+    case 4: hipLaunchKernelGGL(start_order_kernel<4>, grid, dim3(kOrderThreads), 0, st, A); break;
+    case 5: hipLaunchKernelGGL(start_order_kernel<5>, grid, dim3(kOrderThreads), 0, st, A); break;
+    case 6: hipLaunchKernelGGL(start_order_kernel<6>, grid, dim3(kOrderThreads), 0, st, A); break;
+    case 7: hipLaunchKernelGGL(start_order_kernel<7>, grid, dim3(kOrderThreads), 0, st, A); break;
+    default: hipLaunchKernelGGL(start_order_kernel<8>, grid, dim3(kOrderThreads), 0, st, A); break;
   }
 }
 void launch_sort_pairs(const WalkArgs& A, hipStream_t st) {
