@@ -885,7 +885,10 @@ static V3 vmf_sample(const Lobes& L, float u0, float u1, float u2) {
     if (u0 < run) break;
   }
   const float k = L.kappa[l];
-  const float c = 1.0f + std::log(u1 + (1.0f - u1) * std::exp(-2.0f * k)) / k;
+  // u1 = 0 with e^{-2 kappa} below the float range makes the argument 0:
+  // the formula's limit there is c = -1, the antipode of the mean
+  const float a = u1 + (1.0f - u1) * std::exp(-2.0f * k);
+  const float c = a > 0.0f ? 1.0f + std::log(a) / k : -1.0f;
   const float s = std::sqrt(std::max(0.0f, 1.0f - c * c));
   const float ph = 2.0f * PIf * u2;
   V3 mu = mk(L.mu[l][0], L.mu[l][1], L.mu[l][2]);

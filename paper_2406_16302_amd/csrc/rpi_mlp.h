@@ -165,7 +165,10 @@ DEV vec3 vmf_mix_sample(const float* raw, float u0, float u1, float u2) {
   vec3 mu;
   float k;
   lobe(raw, l, mu, k);
-  const float c = 1.0f + logf(u1 + (1.0f - u1) * expf(-2.0f * k)) / k;
+  // u1 = 0 with e^{-2 kappa} below the float range makes the argument 0:
+  // the formula's limit there is c = -1, the antipode of the mean
+  const float a = u1 + (1.0f - u1) * expf(-2.0f * k);
+  const float c = a > 0.0f ? 1.0f + logf(a) / k : -1.0f;
   const float s = sqrtf(fmaxf(0.0f, 1.0f - c * c));
   float sp, cp;
   sincosf(2.0f * kPi * u2, &sp, &cp);

@@ -56,6 +56,24 @@ def test_vmf_sampling_matches_pdf(oracle_lib):
     assert chi2 < 45.0, chi2
 
 
+def test_vmf_sampling_at_the_end_of_the_unit_interval(oracle_lib):
+    """u1 = 0 on a lobe so sharp that e^{-2 kappa} is below the float range:
+    the inversion's argument is 0 and its limit is c = -1, the antipode of
+    the mean (not a NaN direction); u1 near 1 gives the mean itself."""
+    raw = np.zeros(40)
+    raw[0:3] = [0.3, -0.2, 0.9]
+    raw[3] = 1e4  # kappa clamped at 1e4
+    for l in range(1, 8):
+        raw[5 * l + 4] = -30.0
+    mu = raw[0:3] / np.linalg.norm(raw[0:3])
+    for u2 in (0.0, 0.37):
+        w = np.asarray(oracle_lib.vmf_sample(raw, 0.1, 0.0, u2))
+        assert np.all(np.isfinite(w)), w
+        assert abs(w @ mu + 1.0) < 1e-5, w @ mu
+        w = np.asarray(oracle_lib.vmf_sample(raw, 0.1, np.float32(1.0 - 2 ** -24), u2))
+        assert w @ mu > 1.0 - 1e-5
+
+
 def test_backprop_matches_finite_differences(oracle_lib):
     rng = np.random.default_rng(2)
     P = oracle_lib.mlp_init(3)
