@@ -291,6 +291,15 @@ DEV bool slab(float lx, float ly, float lz, float hx, float hy, float hz, vec3 i
   return t0 <= t1;
 }
 
+// A ray with a NaN in its origin or direction meets no triangle (every
+// comparison of its hit tests is false) but every box (the slab test's
+// min/max drop the NaNs), so its traversal would visit the whole BVH to find
+// nothing: the traversals end it before the first node, with the same
+// result.
+DEV bool ray_ok(vec3 o, vec3 d) {
+  return (o.x == o.x) & (o.y == o.y) & (o.z == o.z) & (d.x == d.x) & (d.y == d.y) & (d.z == d.z);
+}
+
 // One visit of a 4-wide node: test(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, tnear)
 // says whether the ray meets a child's box.  ORDER: the nearest child met is
 // returned and the others go on the lane's stack, the farthest first
@@ -364,7 +373,7 @@ DEV void bvh_walk(const float4* __restrict__ N, vec3 o, vec3 d, const float& tli
   const vec3 oi = v3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
   const int lane = threadIdx.x;
   int sp = 0;
-  int node = 0;  // >= 0: inner node to visit next; < 0: a leaf code; kDone
+  int node = ray_ok(o, d) ? 0 : kDone;  // >= 0: inner node to visit next; < 0: a leaf code; kDone
   int pl = 0;    // postponed leaf code, 0: none
   auto test = [&](float lx, float ly, float lz, float hx, float hy, float hz, float& tn) {
     return slab(lx, ly, lz, hx, hy, hz, inv, oi, tlim, tn);
@@ -510,7 +519,7 @@ DEV void bvh_walk_line(const float4* __restrict__ N, vec3 o, vec3 d, const float
   const vec3 oi = v3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
   const int lane = threadIdx.x;
   int sp = 0;
-  int node = 0;
+  int node = ray_ok(o, d) ? 0 : kDone;
   int pl = 0;
   auto test = [&](float lx, float ly, float lz, float hx, float hy, float hz, float& tn) {
     return slab_line(lx, ly, lz, hx, hy, hz, inv, oi, tf, tb, tn);

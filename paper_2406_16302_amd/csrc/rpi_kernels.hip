@@ -962,7 +962,7 @@ DEV bool eye_useful(const SmLane& L, int i1, int depth, int extra) {
 
 DEV void sm_stage(SmQuery& q, int stage, const DevBvh& B, vec3 ro, vec3 rd) {
   q.stage = stage;
-  q.node = 0;
+  q.node = ray_ok(ro, rd) ? 0 : kDone;
   q.sp = 0;
   q.pl = 0;
   q.nodes = B.nodes;
