@@ -1,6 +1,6 @@
 // Device-side building blocks of the residual path estimator for gfx950:
-// counter-based RNG, BSDFs, pinhole camera, light sampling, BVH traversal
-// with a per-lane LDS stack, ghost-crossing records.
+// counter-based RNG, BSDFs, pinhole camera, light sampling (guide-table CDF
+// picks), 4-wide BVH traversal with a per-lane LDS stack, ghost-crossing records.
 #pragma once
 
 #include "rpi_internal.h"

@@ -1,24 +1,38 @@
 // HIP kernels of the residual path estimator (gfx950, wave64).
 //
-// Pipeline per (direction, technique, chunk of samples), all on one stream:
-//   walk_kernel<TECH>  one lane per sample: start sampling (Sec. 4.1/4.2),
-//                      random walks with BVH traversal, next-event and camera
-//                      connections, ghost-crossing records (Sec. 4.3, Sec. 6.1);
-//                      sub-path vertices go to SoA records in HBM and every
-//                      connected path is appended to a queue with one atomic
-//                      per wave (ballot/prefix compaction).
-//   connect_kernel     one lane per connected path: MIS over N_D + N_G + 1
-//                      strategies from forward/backward pdf prefix tables
-//                      (Sec. 4.3), path mapping and rejection (Sec. 5),
-//                      evaluation in both frames (eq. shiftmapped), one signed
-//                      splat record per path.
-//   splat kernels      counting sort of the records by tile (16x16 or 32x32),
-//                      then workgroups take chunks of a tile's records and
-//                      sum them per pixel in LDS in fixed point; the sums go
-//                      to a fixed-point image that is turned into the float
-//                      image at the end of the call (no float atomics: the
-//                      image is the same bit for bit whatever the order).
-// frame_kernel renders a frame by plain path tracing (Sec. 3.1).
+// Pipeline per (technique, round of samples of both directions), all on one
+// stream:
+//   start_order_kernel   the round's samples ordered by where they start (a
+//                        counting sort by grid cell of x_D / x_G, or by pixel
+//                        tile), so that the lanes of a wave start close
+//                        together;
+//   walk_kernel<TECH>    one lane per sample: start sampling (Sec. 4.1/4.2) and
+//                        the start's ray queries (path tracing, 7, also walks
+//                        here); samples whose walks go on are queued as tasks;
+//   walk_task_kernel<TECH>  the queued walks, each lane stepping its own task
+//                        through one traversal loop shared by the wave: random
+//                        walks with BVH traversal, next-event and camera
+//                        connections, ghost-crossing records (Sec. 4.3, 6.1).
+//                        Sub-path vertices go to SoA records in HBM and every
+//                        connected path is appended to a queue with one atomic
+//                        per wave (ballot/prefix compaction);
+//   pair_hist/pair_sort  the path queue sorted by path length;
+//   connect_kernel       one lane per connected path: MIS over N_D + N_G + 1
+//                        strategies from forward/backward pdf prefix tables
+//                        (Sec. 4.3), path mapping and rejection (Sec. 5),
+//                        evaluation in both frames (eq. shiftmapped), one
+//                        signed splat record per path;
+//   splat kernels        counting sort of the records by tile (16x16 or
+//                        32x32), then workgroups take chunks of a tile's
+//                        records and sum them per pixel in LDS in fixed point;
+//                        the sums go to a fixed-point image that is turned into
+//                        the float image at the end of the call (no float
+//                        atomics: the image is the same bit for bit whatever
+//                        the order).
+// Technique 8 adds t8_start_kernel (the learned proposal at x_D and the
+// direction drawn from it) and proposal_pdf_kernel (its density at the queued
+// paths' dynamic vertices, for the MIS sums).  frame_kernel renders a frame by
+// plain path tracing (Sec. 3.1).
 #include "rpi_device.h"
 #include "rpi_mlp.h"
 
@@ -769,9 +783,6 @@ __global__ __launch_bounds__(kOrderThreads) void start_order_kernel(WalkArgs A) 
   }
 }
 
-// Persistent walk kernel: each wave pulls 64-sample work items (job,
-// direction, sample range) from a round counter until the round is drained,
-// which balances jobs of uneven image size and uneven per-sample cost.
 // Occupancy targets of the trace-heavy kernels (waves per SIMD; 0 leaves the
 // register allocation to the compiler).  The 10 KB LDS stack per wave lets a
 // compute unit hold 16 waves, four per SIMD.  The start kernels fit four
@@ -821,12 +832,13 @@ DEV WalkStart load_walk(const Workspace& W, int f0, uint32_t t) {
                    End{xyz(d), xyz(e), (int)__float_as_uint(d.w)}, (int)__float_as_uint(b.w)};
 }
 
-// Start phase: persistent waves pull 64-sample work items (job, direction,
+// Start phase: persistent waves pull 64-slot work items (job, direction,
 // sample range) from a round counter until the round is drained, which
 // balances jobs of uneven image size and uneven per-sample cost.  Each lane
-// draws its technique's start; samples whose walks remain are compacted into
-// the task queue (one atomic per wave), so the walk phase runs full waves
-// instead of the few lanes whose starts succeeded.
+// takes the sample its slot holds (slot_sample: in the order the ordering
+// pass chose) and draws its technique's start; samples whose walks remain
+// are compacted into the task queue (one atomic per wave), so the walk phase
+// runs full waves instead of the few lanes whose starts succeeded.
 template <int TECH, bool CW>
 __global__ __launch_bounds__(kTraceBlock) RPI_START_OCCUPANCY void walk_kernel(WalkArgs A) {
   __shared__ __attribute__((aligned(16))) int stk[kStackDepth * kTraceBlock];
