@@ -1501,10 +1501,11 @@ static rpi_status enqueue(const Plan& pl, const Ws& w, const rpi_render_params* 
         if (r) return r;
       }
       // the path queue sorted by path length, so that a wave's paths loop over
-      // the same number of vertices
+      // the same number of vertices, then within windows by pixel tile (back
+      // into W.pairs), so that a wave's mapping rays start close together
       launch_sort_pairs(A, st);
       WalkArgs As = A;
-      As.W.pairs = w.W.pairs2;
+      As.W.pairs = w.W.pairs;  // the queue ordered by path length, then by pixel tile within windows
       if (t8) {
         r = timed(kKidProposalPdf, [&] { launch_proposal_pdf(As, cblocks, st); });
         if (r) return r;

@@ -153,7 +153,7 @@ struct Workspace {
   uint32_t* ntasks;    // [1] task queue length
   uint32_t* fetch;     // [2] work counters of the walk phase (tasks) and the connect kernel (paths)
   uint32_t* kbins;     // [32] paths per length k, then the sort's cursors per k
-  uint32_t* pairs2;    // [pair_cap] the path queue sorted by path length
+  uint32_t* pairs2;    // [pair_cap] the path queue sorted by path length (then ordered back into pairs)
   uint32_t* order;     // [Q] or null: slot s of the round holds the sample of item-order slot order[s]
   uint16_t* okey;      // [Q] the ordering pass's keys
   float4* t8q;         // technique (8) on: per queued path (2 float4), the proposal's

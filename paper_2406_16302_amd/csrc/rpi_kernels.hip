@@ -16,7 +16,8 @@
 //                        Sub-path vertices go to SoA records in HBM and every
 //                        connected path is appended to a queue with one atomic
 //                        per wave (ballot/prefix compaction);
-//   pair_hist/pair_sort  the path queue sorted by path length;
+//   pair_hist/pair_sort/pair_order  the path queue sorted by path length,
+//                        then within windows by the pixel tile of x_1;
 //   connect_kernel       one lane per connected path: MIS over N_D + N_G + 1
 //                        strategies from forward/backward pdf prefix tables
 //                        (Sec. 4.3), path mapping and rejection (Sec. 5),
@@ -2590,9 +2591,71 @@ void launch_start_order(const WalkArgs& A, hipStream_t st) {
     default: hipLaunchKernelGGL(start_order_kernel<8>, grid, dim3(kOrderThreads), 0, st, A); break;
   }
 }
+// Path order: within windows of kOrderWindow entries of the length-sorted
+// queue (pairs2), the paths are counting-sorted by (length, the tile of
+// their pixel in a 16 x 16 grid over the image) into pairs, so that the
+// connect kernel's camera re-traces and the mapped edges' visibility rays of
+// a wave start from nearby points.
+constexpr int kOrderWindow = 65536;
+__global__ __launch_bounds__(kOrderThreads) void pair_order_kernel(WalkArgs A) {
+  __shared__ uint32_t cnt[kOrderBins], part[kOrderThreads];
+  constexpr int kPerThread = kOrderBins / kOrderThreads;
+  const int n = (int)min((uint32_t)A.W.pair_cap, *A.W.npairs);
+  // the keys: the splat records' space (pair_cap float4), free until connect writes them
+  uint32_t* key = reinterpret_cast<uint32_t*>(A.W.records);
+  for (int w = blockIdx.x; w * kOrderWindow < n; w += gridDim.x) {
+    const int p0 = w * kOrderWindow, p1 = min(p0 + kOrderWindow, n);
+    for (int b = threadIdx.x; b < kOrderBins; b += kOrderThreads) cnt[b] = 0u;
+    __syncthreads();
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += kOrderThreads) {
+      const uint32_t code = A.W.pairs2[p];
+      const int s = code_slot(code), i = code_i(code), j = code_j(code);
+      const bool mid = has_mid(A.tech);
+      const int nsc = (i + 1) + (mid ? 1 : 0) + (j + 1);
+      uint32_t tile = 0u;
+      if (nsc > 0) {
+        const int jd = find_jd(A.item_prefix, 2 * A.njobs, A.item0 + s / kItem);
+        const DevCamera& C = A.jobs[jd >> 1].S.cam;
+        const int px = raster(C, path_vertex(A.W, s, i, mid, 1).p);
+        if (px >= 0) tile = (uint32_t)(((px / C.W) * 16 / C.H) * 16 + (px % C.W) * 16 / C.W);
+      }
+      const uint32_t kk = ((uint32_t)min(nsc + 2, 15) << 8) | tile;
+      atomicAdd(&cnt[kk], 1u);
+      key[p] = kk;
+    }
+    __syncthreads();
+    {  // exclusive prefix sums: each key's first place in the window
+      const int t = threadIdx.x;
+      uint32_t sum = 0u;
+      for (int q = 0; q < kPerThread; ++q) sum += cnt[kPerThread * t + q];
+      part[t] = sum;
+      __syncthreads();
+      for (int off = 1; off < kOrderThreads; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+      }
+      uint32_t run = part[t] - sum;
+      for (int q = 0; q < kPerThread; ++q) {
+        const uint32_t c = cnt[kPerThread * t + q];
+        cnt[kPerThread * t + q] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += kOrderThreads)
+      A.W.pairs[p0 + atomicAdd(&cnt[key[p]], 1u)] = A.W.pairs2[p];
+    __syncthreads();
+  }
+}
+
 void launch_sort_pairs(const WalkArgs& A, hipStream_t st) {
   hipLaunchKernelGGL(pair_hist_kernel, dim3(1024), dim3(256), 0, st, A);
   hipLaunchKernelGGL(pair_sort_kernel, dim3(1024), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(pair_order_kernel,
+                     dim3((unsigned)std::min<int64_t>((A.W.pair_cap + kOrderWindow - 1) / kOrderWindow, 2048)),
+                     dim3(kOrderThreads), 0, st, A);
 }
 
 void launch_connect(const WalkArgs& A, int blocks, hipStream_t st) {
