@@ -1,8 +1,10 @@
 // Learned proposal on the matrix cores: a 6-64-64-64-40 ReLU MLP evaluated
 // by one wavefront for 64 rows at a time with BF16 operands and FP32
-// accumulation (v_mfma_f32_16x16x16bf16_1k), and the 8-lobe von Mises-Fisher
-// mixture it parameterises (addition beyond the paper, which leaves better
-// importance sampling of the residual integrand to future work, Sec. 7).
+// accumulation (v_mfma_f32_16x16x32_bf16 for the 64-wide layers,
+// v_mfma_f32_16x16x16bf16_1k for the zero-padded 16-wide input), and the
+// 8-lobe von Mises-Fisher mixture it parameterises (addition beyond the
+// paper, which leaves better importance sampling of the residual integrand
+// to future work, Sec. 7).
 #pragma once
 
 #include "rpi_device.h"
@@ -10,6 +12,8 @@
 namespace rpi {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMlpIn = 6, kMlpH = 64, kMlpOut = 40, kLobes = 8;
@@ -40,6 +44,15 @@ DEV float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 //   B (K16 x 16):  lane holds B[4g .. 4g+3][r]
 //   D (16 x 16):   lane holds D[4g .. 4g+3][r]
 DEV f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+// MFMA 16x16x32 (gfx950), twice the depth per instruction:
+//   A (16 x K32):  lane holds A[r][8g .. 8g+7]
+//   B (K32 x 16):  lane holds B[8g .. 8g+7][r]
+//   D (16 x 16):   as above
+// (the product needs only that both operands use the same order of k)
+DEV f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a), __builtin_bit_cast(bf16v8, b), c, 0,
+                                                  0, 0);
+}
 
 // One dense layer over the 64 rows in LDS: in [64][IS] bf16 (K columns)
 // times W (transposed in wt [NT*16][K]) + bias; ReLU and bf16 into out
@@ -58,12 +71,22 @@ DEV void mlp_layer(const uint16_t* in, uint16_t* out, const uint16_t* __restrict
     f32x4 acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (K % 32 == 0) {
 #pragma unroll
-    for (int kt = 0; kt < K / 16; ++kt) {
-      const bf16x4 aa = *reinterpret_cast<const bf16x4*>(in + (mt * 16 + r) * IS + kt * 16 + 4 * g);
+      for (int kt = 0; kt < K / 32; ++kt) {
+        const bf16x8 aa = *reinterpret_cast<const bf16x8*>(in + (mt * 16 + r) * IS + kt * 32 + 8 * g);
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-        acc[nt] = mfma(aa, *reinterpret_cast<const bf16x4*>(wt + (nt * 16 + r) * K + kt * 16 + 4 * g), acc[nt]);
+        for (int nt = 0; nt < NT; ++nt)
+          acc[nt] = mfma32(aa, *reinterpret_cast<const bf16x8*>(wt + (nt * 16 + r) * K + kt * 32 + 8 * g), acc[nt]);
+      }
+    } else {
+#pragma unroll
+      for (int kt = 0; kt < K / 16; ++kt) {
+        const bf16x4 aa = *reinterpret_cast<const bf16x4*>(in + (mt * 16 + r) * IS + kt * 16 + 4 * g);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[nt] = mfma(aa, *reinterpret_cast<const bf16x4*>(wt + (nt * 16 + r) * K + kt * 16 + 4 * g), acc[nt]);
+      }
     }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {

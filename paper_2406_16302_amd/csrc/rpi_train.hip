@@ -141,16 +141,16 @@ DEV void grad_w(const uint16_t* X, int xs, const void* G, int gs, float* dst, in
     for (int nt = 0; nt < NT; ++nt) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kt = 0; kt < 4; ++kt) {
-        bf16x4 a, b;
+      for (int kt = 0; kt < 2; ++kt) {
+        bf16x8 a, b;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int row = kt * 16 + 4 * g + e;
+        for (int e = 0; e < 8; ++e) {
+          const int row = kt * 32 + 8 * g + e;
           a[e] = (short)X[row * xs + mt * 16 + r];
           if (GF32) b[e] = (short)f2bf(reinterpret_cast<const float*>(G)[row * gs + nt * 16 + r]);
           else b[e] = (short)reinterpret_cast<const uint16_t*>(G)[row * gs + nt * 16 + r];
         }
-        acc = mfma(a, b, acc);
+        acc = mfma32(a, b, acc);
       }
       const int j = nt * 16 + r;
 #pragma unroll
@@ -178,17 +178,28 @@ DEV void back_signal(const void* Gout, int gs, const uint16_t* __restrict__ w, i
 #pragma unroll 1
     for (int mt = 0; mt < 4; ++mt) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int row = mt * 16 + r;
 #pragma unroll
-      for (int kt = 0; kt < KT; ++kt) {
-        bf16x4 a;
-        const int row = mt * 16 + r;
+      for (int kt = 0; kt < KT / 2; ++kt) {  // 32 outputs at a time
+        bf16x8 a;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int o = kt * 16 + 4 * g + e;
+        for (int e = 0; e < 8; ++e) {
+          const int o = kt * 32 + 8 * g + e;
           if (GF32) a[e] = (short)f2bf(reinterpret_cast<const float*>(Gout)[row * gs + o]);
           else a[e] = (short)reinterpret_cast<const uint16_t*>(Gout)[row * gs + o];
         }
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(w + (nt * 16 + r) * ldw + kt * 16 + 4 * g);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(w + (nt * 16 + r) * ldw + kt * 32 + 8 * g);
+        acc = mfma32(a, b, acc);
+      }
+      if constexpr (KT % 2 == 1) {  // the last 16 outputs
+        bf16x4 a;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int o = (KT - 1) * 16 + 4 * g + e;
+          if (GF32) a[e] = (short)f2bf(reinterpret_cast<const float*>(Gout)[row * gs + o]);
+          else a[e] = (short)reinterpret_cast<const uint16_t*>(Gout)[row * gs + o];
+        }
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(w + (nt * 16 + r) * ldw + (KT - 1) * 16 + 4 * g);
         acc = mfma(a, b, acc);
       }
 #pragma unroll
@@ -307,34 +318,69 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(MlpDev M, const float* __r
   }
 }
 
-DEV float reduce_partial(const float* partial, int blocks, int p) {
+// Sums over the blocks' partials.  A workgroup of kRedWaves waves owns the 64
+// entries p0 .. p0 + 63 (lane l: entry p0 + l); wave w adds the blocks
+// b = w, w + kRedWaves, ... in increasing order, then the wave sums are added
+// in wave order.  The weight sum W (entry kMlpNParam + 1), which every entry
+// divides by, is formed in every workgroup in the same fixed order (thread t
+// adds the blocks t, t + 512, ...; a butterfly over each wave, whose lanes all
+// end with the same value; the wave sums in wave order).  The result does not
+// depend on scheduling.  Returns the entry's sum to the lanes of wave 0.
+constexpr int kRedWaves = 8;
+constexpr int kRedThreads = 64 * kRedWaves;
+constexpr int kRedEntries = kMlpPartial;  // parameters, loss, weight sum
+
+DEV float sum_blocks(const float* __restrict__ partial, int blocks, int p, float* lds, float& W) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   float s = 0.0f;
-  for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * kMlpPartial + p];
-  return s;
+  if (p < kRedEntries) {
+#pragma unroll 8
+    for (int b = w; b < blocks; b += kRedWaves) s += partial[(size_t)b * kMlpPartial + p];
+  }
+  float ws = 0.0f;
+  for (int b = threadIdx.x; b < blocks; b += kRedThreads) ws += partial[(size_t)b * kMlpPartial + kMlpNParam + 1];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) ws += __shfl_xor(ws, off, 64);
+  lds[w * 64 + l] = s;
+  if (l == 0) lds[kRedThreads + w] = ws;
+  __syncthreads();
+  W = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kRedWaves; ++k) W += lds[kRedThreads + k];
+  float t = 0.0f;
+  if (w == 0)
+#pragma unroll
+    for (int k = 0; k < kRedWaves; ++k) t += lds[k * 64 + l];
+  return t;
 }
 
-__global__ void mlp_reduce_kernel(const float* __restrict__ partial, int blocks, float* __restrict__ grad,
-                                  float* __restrict__ loss) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p > kMlpNParam) return;
-  const float W = reduce_partial(partial, blocks, kMlpNParam + 1);
+__global__ __launch_bounds__(kRedThreads) void mlp_reduce_kernel(const float* __restrict__ partial, int blocks,
+                                                                 float* __restrict__ grad, float* __restrict__ loss) {
+  __shared__ float lds[kRedThreads + kRedWaves];
+  const int p = blockIdx.x * 64 + (threadIdx.x & 63);
+  float W;
+  const float s = sum_blocks(partial, blocks, p, lds, W);
+  if (threadIdx.x >= 64) return;
   const float inv = W > 0.0f ? 1.0f / W : 0.0f;
-  if (p < kMlpNParam) grad[p] = reduce_partial(partial, blocks, p) * inv;
-  else if (loss) *loss = reduce_partial(partial, blocks, kMlpNParam) * inv;
+  if (p < kMlpNParam) grad[p] = s * inv;
+  else if (p == kMlpNParam && loss) *loss = s * inv;
 }
 
 // Adam (Kingma and Ba 2015) on the FP32 masters, then the kernels' copies.
-__global__ void mlp_adam_kernel(const float* __restrict__ partial, int blocks, MlpBufs B, float lr, float beta1,
-                                float beta2, float eps, int t, float* __restrict__ loss_out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p > kMlpNParam) return;
-  const float W = reduce_partial(partial, blocks, kMlpNParam + 1);
-  if (!(W > 0.0f)) return;
+__global__ __launch_bounds__(kRedThreads) void mlp_adam_kernel(const float* __restrict__ partial, int blocks, MlpBufs B,
+                                                               float lr, float beta1, float beta2, float eps, int t,
+                                                               float* __restrict__ loss_out) {
+  __shared__ float lds[kRedThreads + kRedWaves];
+  const int p = blockIdx.x * 64 + (threadIdx.x & 63);
+  float W;
+  const float s = sum_blocks(partial, blocks, p, lds, W);
+  if (threadIdx.x >= 64 || !(W > 0.0f)) return;
   if (p == kMlpNParam) {
-    if (loss_out) *loss_out = reduce_partial(partial, blocks, kMlpNParam) / W;
+    if (loss_out) *loss_out = s / W;
     return;
   }
-  const float g = reduce_partial(partial, blocks, p) / W;
+  if (p > kMlpNParam) return;
+  const float g = s / W;
   const float m = beta1 * B.adam_m[p] + (1.0f - beta1) * g;
   const float v = beta2 * B.adam_v[p] + (1.0f - beta2) * g * g;
   B.adam_m[p] = m;
@@ -360,12 +406,13 @@ void launch_mlp_grad(const MlpDev& M, const float* rec, int64_t nrec, int64_t ro
                      partial);
 }
 void launch_mlp_reduce(const float* partial, int blocks, float* grad, float* loss, hipStream_t st) {
-  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kMlpNParam + 256) / 256), dim3(256), 0, st, partial, blocks, grad, loss);
+  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kRedEntries + 63) / 64), dim3(kRedThreads), 0, st, partial, blocks, grad,
+                     loss);
 }
 void launch_mlp_adam(const float* partial, int blocks, const MlpBufs& B, float lr, float beta1, float beta2, float eps,
                      int t, float* loss_out, hipStream_t st) {
-  hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpNParam + 256) / 256), dim3(256), 0, st, partial, blocks, B, lr, beta1,
-                     beta2, eps, t, loss_out);
+  hipLaunchKernelGGL(mlp_adam_kernel, dim3((kRedEntries + 63) / 64), dim3(kRedThreads), 0, st, partial, blocks, B, lr,
+                     beta1, beta2, eps, t, loss_out);
 }
 
 }  // namespace rpi
