@@ -54,10 +54,50 @@ DEV f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
                                                   0, 0);
 }
 
+// Rows mt*16 .. mt*16 + 15 of a dense layer (16 accumulators per lane; the
+// layer is described below).
+template <int K, int NT, bool LAST, int IS = kActStride>
+DEV void mlp_tile(const uint16_t* in, uint16_t* out, const uint16_t* __restrict__ wt, const float* __restrict__ bias,
+                  float* outf, int mt) {
+  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (K % 32 == 0) {
+#pragma unroll
+    for (int kt = 0; kt < K / 32; ++kt) {
+      const bf16x8 aa = *reinterpret_cast<const bf16x8*>(in + (mt * 16 + r) * IS + kt * 32 + 8 * g);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[nt] = mfma32(aa, *reinterpret_cast<const bf16x8*>(wt + (nt * 16 + r) * K + kt * 32 + 8 * g), acc[nt]);
+    }
+  } else {
+#pragma unroll
+    for (int kt = 0; kt < K / 16; ++kt) {
+      const bf16x4 aa = *reinterpret_cast<const bf16x4*>(in + (mt * 16 + r) * IS + kt * 16 + 4 * g);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[nt] = mfma(aa, *reinterpret_cast<const bf16x4*>(wt + (nt * 16 + r) * K + kt * 16 + 4 * g), acc[nt]);
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int col = nt * 16 + r;
+    const float bv = bias[col];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = mt * 16 + 4 * g + e;
+      const float v = acc[nt][e] + bv;
+      if (LAST) outf[row * kOutStride + col] = v;
+      else out[row * kActStride + col] = f2bf(fmaxf(v, 0.0f));
+    }
+  }
+}
+
 // One dense layer over the 64 rows in LDS: in [64][IS] bf16 (K columns)
 // times W (transposed in wt [NT*16][K]) + bias; ReLU and bf16 into out
 // [64][kActStride], or fp32 into outf [64][kOutStride] for the last layer.
-// One 16-row tile at a time (16 accumulators per lane), last tile first.
+// One 16-row tile at a time, last tile first.
 // out / outf may alias in (one wave owns the rows): a tile's input rows are
 // read only by that tile's products, which its writes depend on, and the
 // fp32 output rows of tile mt (bytes [3072 mt, 3072 mt + 3072)) overlap only
@@ -65,42 +105,8 @@ DEV f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
 template <int K, int NT, bool LAST, int IS = kActStride>
 DEV void mlp_layer(const uint16_t* in, uint16_t* out, const uint16_t* __restrict__ wt, const float* __restrict__ bias,
                    float* outf) {
-  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
 #pragma unroll 1
-  for (int mt = 3; mt >= 0; --mt) {
-    f32x4 acc[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if constexpr (K % 32 == 0) {
-#pragma unroll
-      for (int kt = 0; kt < K / 32; ++kt) {
-        const bf16x8 aa = *reinterpret_cast<const bf16x8*>(in + (mt * 16 + r) * IS + kt * 32 + 8 * g);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[nt] = mfma32(aa, *reinterpret_cast<const bf16x8*>(wt + (nt * 16 + r) * K + kt * 32 + 8 * g), acc[nt]);
-      }
-    } else {
-#pragma unroll
-      for (int kt = 0; kt < K / 16; ++kt) {
-        const bf16x4 aa = *reinterpret_cast<const bf16x4*>(in + (mt * 16 + r) * IS + kt * 16 + 4 * g);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[nt] = mfma(aa, *reinterpret_cast<const bf16x4*>(wt + (nt * 16 + r) * K + kt * 16 + 4 * g), acc[nt]);
-      }
-    }
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int col = nt * 16 + r;
-      const float bv = bias[col];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = mt * 16 + 4 * g + e;
-        const float v = acc[nt][e] + bv;
-        if (LAST) outf[row * kOutStride + col] = v;
-        else out[row * kActStride + col] = f2bf(fmaxf(v, 0.0f));
-      }
-    }
-  }
+  for (int mt = 3; mt >= 0; --mt) mlp_tile<K, NT, LAST, IS>(in, out, wt, bias, outf, mt);
   __syncthreads();
 }
 

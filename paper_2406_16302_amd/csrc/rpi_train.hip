@@ -3,8 +3,8 @@
 // batched MLP inference, the gradient of the weighted negative log-likelihood
 // of the vMF mixture (the Monte Carlo KL objective of neural importance
 // sampling, Mueller et al. 2019) by back-propagation on the matrix cores, and
-// Adam.  BF16 operands, FP32 accumulation, one wavefront per workgroup and
-// 64 rows per pass.
+// Adam.  BF16 operands, FP32 accumulation, 64 rows per pass (inference: one
+// wavefront per workgroup; the gradient: four).
 #include "rpi_mlp.h"
 
 namespace rpi {
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(64) void mlp_forward_kernel(MlpDev M, const float* 
 
 // ------------------------------------------------------------------ training
 constexpr int kA0Stride = 24;  // bf16 per row of the (16-wide, zero-padded) input block
+constexpr int kGradWaves = 4;  // waves per 64-row tile of the gradient kernel
 
 // Gradient of -log q(w) with respect to the 40 raw outputs (one row).
 // Mixture terms in log space: log f_l = log kappa - log(2 pi (1 - e^{-2 kappa}))
@@ -129,100 +130,101 @@ DEV float nll_grad(const float* raw, vec3 w, float g[kMlpOut]) {
   return -lq;
 }
 
-// Weight gradient dst[i][j] (+)= sum over the 64 rows of X[row][i] G[row][j]
-// (the matrix cores reduce over rows: A = X^T, B = G).  X: bf16 rows of
-// stride xs; G: bf16 rows of stride gs, or fp32 rows when GF32.
-template <int MT, int NT, bool GF32>
-DEV void grad_w(const uint16_t* X, int xs, const void* G, int gs, float* dst, int ldd, int ni, int nj, bool first) {
+// Tile (mt, nt) of a weight gradient: dst[i][j] (+)= sum over the 64 rows of
+// X[row][i] G[row][j] for i in mt*16 .. +15, j in nt*16 .. +15 (the matrix
+// cores reduce over rows: A = X^T, B = G).  X: bf16 rows of stride xs; G:
+// bf16 rows of stride gs, or fp32 rows when GF32.
+template <bool GF32>
+DEV void grad_tile(const uint16_t* X, int xs, const void* G, int gs, float* dst, int ldd, int ni, int nj, bool first,
+                   int mt, int nt) {
   const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
-#pragma unroll 1
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll 1
-    for (int nt = 0; nt < NT; ++nt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kt = 0; kt < 2; ++kt) {
-        bf16x8 a, b;
+  for (int kt = 0; kt < 2; ++kt) {
+    bf16x8 a, b;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int row = kt * 32 + 8 * g + e;
-          a[e] = (short)X[row * xs + mt * 16 + r];
-          if (GF32) b[e] = (short)f2bf(reinterpret_cast<const float*>(G)[row * gs + nt * 16 + r]);
-          else b[e] = (short)reinterpret_cast<const uint16_t*>(G)[row * gs + nt * 16 + r];
-        }
-        acc = mfma32(a, b, acc);
-      }
-      const int j = nt * 16 + r;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int i = mt * 16 + 4 * g + e;
-        if (i < ni && j < nj) {
-          float* d = dst + i * ldd + j;
-          *d = first ? acc[e] : *d + acc[e];
-        }
-      }
+    for (int e = 0; e < 8; ++e) {
+      const int row = kt * 32 + 8 * g + e;
+      a[e] = (short)X[row * xs + mt * 16 + r];
+      if (GF32) b[e] = (short)f2bf(reinterpret_cast<const float*>(G)[row * gs + nt * 16 + r]);
+      else b[e] = (short)reinterpret_cast<const uint16_t*>(G)[row * gs + nt * 16 + r];
     }
+    acc = mfma32(a, b, acc);
+  }
+  const int j = nt * 16 + r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = mt * 16 + 4 * g + e;
+    if (i < ni && j < nj) {
+      float* d = dst + i * ldd + j;
+      *d = first ? acc[e] : *d + acc[e];
+    }
+  }
 }
 
-// Back-propagated signal into a 64-wide layer: Gin[row][i] = [A[row][i] > 0]
-// sum_o Gout[row][o] W[i][o] (W in [in][out] layout, ldw per row, KT*16
-// outputs), stored bf16; returns through db the column sums (the layer's
-// bias gradient), valid in lanes 0..15 for columns nt*16 + lane.
+// Back-propagated signal into features nt*16 .. nt*16 + 15 of a 64-wide
+// layer: Gin[row][i] = [A[row][i] > 0] sum_o Gout[row][o] W[i][o] (W in
+// [in][out] layout, ldw per row, KT*16 outputs), stored bf16; returns the
+// column sums (the layer's bias gradient), valid in lanes 0..15 for columns
+// nt*16 + lane.
 template <int KT, bool GF32>
-DEV void back_signal(const void* Gout, int gs, const uint16_t* __restrict__ w, int ldw, const uint16_t* A,
-                     uint16_t* Gin, float db[4]) {
+DEV float back_tile(const void* Gout, int gs, const uint16_t* __restrict__ w, int ldw, const uint16_t* A,
+                    uint16_t* Gin, int nt) {
   const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+  float cs = 0.0f;
 #pragma unroll 1
-  for (int nt = 0; nt < 4; ++nt) {
-    float cs = 0.0f;
-#pragma unroll 1
-    for (int mt = 0; mt < 4; ++mt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      const int row = mt * 16 + r;
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int row = mt * 16 + r;
 #pragma unroll
-      for (int kt = 0; kt < KT / 2; ++kt) {  // 32 outputs at a time
-        bf16x8 a;
+    for (int kt = 0; kt < KT / 2; ++kt) {  // 32 outputs at a time
+      bf16x8 a;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int o = kt * 32 + 8 * g + e;
-          if (GF32) a[e] = (short)f2bf(reinterpret_cast<const float*>(Gout)[row * gs + o]);
-          else a[e] = (short)reinterpret_cast<const uint16_t*>(Gout)[row * gs + o];
-        }
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(w + (nt * 16 + r) * ldw + kt * 32 + 8 * g);
-        acc = mfma32(a, b, acc);
+      for (int e = 0; e < 8; ++e) {
+        const int o = kt * 32 + 8 * g + e;
+        if (GF32) a[e] = (short)f2bf(reinterpret_cast<const float*>(Gout)[row * gs + o]);
+        else a[e] = (short)reinterpret_cast<const uint16_t*>(Gout)[row * gs + o];
       }
-      if constexpr (KT % 2 == 1) {  // the last 16 outputs
-        bf16x4 a;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int o = (KT - 1) * 16 + 4 * g + e;
-          if (GF32) a[e] = (short)f2bf(reinterpret_cast<const float*>(Gout)[row * gs + o]);
-          else a[e] = (short)reinterpret_cast<const uint16_t*>(Gout)[row * gs + o];
-        }
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(w + (nt * 16 + r) * ldw + (KT - 1) * 16 + 4 * g);
-        acc = mfma(a, b, acc);
-      }
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(w + (nt * 16 + r) * ldw + kt * 32 + 8 * g);
+      acc = mfma32(a, b, acc);
+    }
+    if constexpr (KT % 2 == 1) {  // the last 16 outputs
+      bf16x4 a;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = mt * 16 + 4 * g + e, col = nt * 16 + r;
-        const float v = A[row * kActStride + col] != 0 && !(A[row * kActStride + col] & 0x8000u) ? acc[e] : 0.0f;
-        Gin[row * kActStride + col] = f2bf(v);
-        cs += v;
+        const int o = (KT - 1) * 16 + 4 * g + e;
+        if (GF32) a[e] = (short)f2bf(reinterpret_cast<const float*>(Gout)[row * gs + o]);
+        else a[e] = (short)reinterpret_cast<const uint16_t*>(Gout)[row * gs + o];
       }
+      const bf16x4 b = *reinterpret_cast<const bf16x4*>(w + (nt * 16 + r) * ldw + (KT - 1) * 16 + 4 * g);
+      acc = mfma(a, b, acc);
     }
-    cs += __shfl_xor(cs, 16, 64);
-    cs += __shfl_xor(cs, 32, 64);
-    db[nt] = cs;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = mt * 16 + 4 * g + e, col = nt * 16 + r;
+      const float v = A[row * kActStride + col] != 0 && !(A[row * kActStride + col] & 0x8000u) ? acc[e] : 0.0f;
+      Gin[row * kActStride + col] = f2bf(v);
+      cs += v;
+    }
   }
+  cs += __shfl_xor(cs, 16, 64);
+  cs += __shfl_xor(cs, 32, 64);
+  return cs;
 }
 
 // Gradient partials of the weighted NLL: block b accumulates the tiles
 // b, b + grid, ... of 64 rows into partial[b][kMlpPartial] (the first tile
 // overwrites); the last two words are the weighted loss and the weight sum.
-// Records: {x[6], w_obj[3], weight} (10 floats).
-__global__ __launch_bounds__(64) void mlp_grad_kernel(MlpDev M, const float* __restrict__ rec, int64_t nrec,
-                                                      int64_t rows, int sampled, uint32_t k0, uint32_t k1,
-                                                      uint32_t step, float* __restrict__ partial) {
+// Records: {x[6], w_obj[3], weight} (10 floats).  Four waves share a tile:
+// wave w runs the forward products of rows 16w .. 16w + 15, and in the
+// backward pass the weight-gradient tiles of input features 16w .. 16w + 15
+// and the signal into features 16w .. 16w + 15 (the first layer's output
+// tile w); wave 0 alone does the per-row loss.  Every word of the partial
+// has one writer, and the sums are those of one wave doing all the tiles.
+__global__ __launch_bounds__(64 * kGradWaves) void mlp_grad_kernel(MlpDev M, const float* __restrict__ rec,
+                                                                   int64_t nrec, int64_t rows, int sampled,
+                                                                   uint32_t k0, uint32_t k1, uint32_t step,
+                                                                   float* __restrict__ partial) {
   __shared__ __attribute__((aligned(16))) uint16_t A0[64 * kA0Stride];
   __shared__ __attribute__((aligned(16))) uint16_t A1[64 * kActStride];
   __shared__ __attribute__((aligned(16))) uint16_t A2[64 * kActStride];
@@ -230,7 +232,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(MlpDev M, const float* __r
   __shared__ __attribute__((aligned(16))) uint16_t GA[64 * kActStride];
   __shared__ __attribute__((aligned(16))) uint16_t GB[64 * kActStride];
   __shared__ __attribute__((aligned(16))) float OUT[64 * kOutStride];
-  const int l = threadIdx.x & 63;
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float* P = partial + (size_t)blockIdx.x * kMlpPartial;
   const int64_t ntiles = (rows + 63) / 64;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -238,82 +240,81 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(MlpDev M, const float* __r
     const int64_t row = tile * 64 + l;
     float wt = 0.0f;
     vec3 om = v3(0.f, 0.f, 1.f);
-    float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (row < rows) {
-      int64_t ri = row;
-      if (sampled) ri = (int64_t)(((uint64_t)philox((uint32_t)row, step, 0x5eedu, 0u, k0, k1).x * (uint64_t)nrec) >> 32);
-      const float* R = rec + ri * 10;
+    if (wv == 0) {
+      float x[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (row < rows) {
+        int64_t ri = row;
+        if (sampled)
+          ri = (int64_t)(((uint64_t)philox((uint32_t)row, step, 0x5eedu, 0u, k0, k1).x * (uint64_t)nrec) >> 32);
+        const float* R = rec + ri * 10;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) x[c] = R[c];
-      om = v3(R[6], R[7], R[8]);
-      wt = R[9];
+        for (int c = 0; c < 6; ++c) x[c] = R[c];
+        om = v3(R[6], R[7], R[8]);
+        wt = R[9];
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) A0[l * kA0Stride + c] = c < 6 ? f2bf(x[c]) : (uint16_t)0;
     }
-#pragma unroll
-    for (int c = 0; c < 16; ++c) A0[l * kA0Stride + c] = c < 6 ? f2bf(x[c]) : (uint16_t)0;
     __syncthreads();
-    mlp_layer<16, 4, false, kA0Stride>(A0, A1, M.wt1, M.b1, nullptr);
-    mlp_layer<64, 4, false>(A1, A2, M.wt2, M.b2, nullptr);
-    mlp_layer<64, 4, false>(A2, A3, M.wt3, M.b3, nullptr);
-    mlp_layer<64, 3, true>(A3, nullptr, M.wt4, M.b4, OUT);
-    // output signal, weighted (normalised by the total weight at the reduction)
-    float gr[kMlpOut];
-    float loss = 0.0f;
-    if (wt != 0.0f) loss = wt * nll_grad(OUT + l * kOutStride, om, gr);
-    else
+    mlp_tile<16, 4, false, kA0Stride>(A0, A1, M.wt1, M.b1, nullptr, wv);
+    __syncthreads();
+    mlp_tile<64, 4, false>(A1, A2, M.wt2, M.b2, nullptr, wv);
+    __syncthreads();
+    mlp_tile<64, 4, false>(A2, A3, M.wt3, M.b3, nullptr, wv);
+    __syncthreads();
+    mlp_tile<64, 3, true>(A3, nullptr, M.wt4, M.b4, OUT, wv);
+    __syncthreads();
+    if (wv == 0) {
+      // output signal, weighted (normalised by the total weight at the reduction)
+      float gr[kMlpOut];
+      float loss = 0.0f;
+      if (wt != 0.0f) loss = wt * nll_grad(OUT + l * kOutStride, om, gr);
+      else
 #pragma unroll
-      for (int c = 0; c < kMlpOut; ++c) gr[c] = 0.0f;
+        for (int c = 0; c < kMlpOut; ++c) gr[c] = 0.0f;
 #pragma unroll
-    for (int c = 0; c < kOutStride; ++c) OUT[l * kOutStride + c] = c < kMlpOut ? wt * gr[c] : 0.0f;
-    // loss and weight sums
-    float ls = loss, ws = wt;
+      for (int c = 0; c < kOutStride; ++c) OUT[l * kOutStride + c] = c < kMlpOut ? wt * gr[c] : 0.0f;
+      // loss and weight sums
+      float ls = loss, ws = wt;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      ls += __shfl_xor(ls, off, 64);
-      ws += __shfl_xor(ws, off, 64);
-    }
-    if (l == 0) {
-      P[kMlpNParam] = first ? ls : P[kMlpNParam] + ls;
-      P[kMlpNParam + 1] = first ? ws : P[kMlpNParam + 1] + ws;
+      for (int off = 32; off > 0; off >>= 1) {
+        ls += __shfl_xor(ls, off, 64);
+        ws += __shfl_xor(ws, off, 64);
+      }
+      if (l == 0) {
+        P[kMlpNParam] = first ? ls : P[kMlpNParam] + ls;
+        P[kMlpNParam + 1] = first ? ws : P[kMlpNParam + 1] + ws;
+      }
     }
     __syncthreads();
     // layer 4: db4 = column sums of the output signal, dW4 = A3^T G4
-    if (l < kMlpOut) {
+    if (wv == 0 && l < kMlpOut) {
       float cs = 0.0f;
       for (int q = 0; q < 64; ++q) cs += OUT[q * kOutStride + l];
       P[OFF_B4 + l] = first ? cs : P[OFF_B4 + l] + cs;
     }
-    grad_w<4, 3, true>(A3, kActStride, OUT, kOutStride, P + OFF_W4, kMlpOut, 64, kMlpOut, first);
-    float db[4];
-    back_signal<3, true>(OUT, kOutStride, M.w4, 48, A3, GA, db);
-    if (l < 16)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        float* d = P + OFF_B3 + nt * 16 + l;
-        *d = first ? db[nt] : *d + db[nt];
-      }
+#pragma unroll 1
+    for (int nt = 0; nt < 3; ++nt)
+      grad_tile<true>(A3, kActStride, OUT, kOutStride, P + OFF_W4, kMlpOut, 64, kMlpOut, first, wv, nt);
+    float db = back_tile<3, true>(OUT, kOutStride, M.w4, 48, A3, GA, wv);
+    if (l < 16) P[OFF_B3 + wv * 16 + l] = first ? db : P[OFF_B3 + wv * 16 + l] + db;
     __syncthreads();
     // layer 3
-    grad_w<4, 4, false>(A2, kActStride, GA, kActStride, P + OFF_W3, 64, 64, 64, first);
-    back_signal<4, false>(GA, kActStride, M.w3, 64, A2, GB, db);
-    if (l < 16)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        float* d = P + OFF_B2 + nt * 16 + l;
-        *d = first ? db[nt] : *d + db[nt];
-      }
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt)
+      grad_tile<false>(A2, kActStride, GA, kActStride, P + OFF_W3, 64, 64, 64, first, wv, nt);
+    db = back_tile<4, false>(GA, kActStride, M.w3, 64, A2, GB, wv);
+    if (l < 16) P[OFF_B2 + wv * 16 + l] = first ? db : P[OFF_B2 + wv * 16 + l] + db;
     __syncthreads();
     // layer 2
-    grad_w<4, 4, false>(A1, kActStride, GB, kActStride, P + OFF_W2, 64, 64, 64, first);
-    back_signal<4, false>(GB, kActStride, M.w2, 64, A1, GA, db);
-    if (l < 16)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        float* d = P + OFF_B1 + nt * 16 + l;
-        *d = first ? db[nt] : *d + db[nt];
-      }
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt)
+      grad_tile<false>(A1, kActStride, GB, kActStride, P + OFF_W2, 64, 64, 64, first, wv, nt);
+    db = back_tile<4, false>(GB, kActStride, M.w2, 64, A1, GA, wv);
+    if (l < 16) P[OFF_B1 + wv * 16 + l] = first ? db : P[OFF_B1 + wv * 16 + l] + db;
     __syncthreads();
-    // layer 1 (inputs 0..5 of the padded 16)
-    grad_w<1, 4, false>(A0, kA0Stride, GA, kActStride, P + OFF_W1, 64, kMlpIn, 64, first);
+    // layer 1 (inputs 0..5 of the padded 16): output tile wv
+    grad_tile<false>(A0, kA0Stride, GA, kActStride, P + OFF_W1, 64, kMlpIn, 64, first, 0, wv);
     __syncthreads();
   }
 }
@@ -402,8 +403,8 @@ void launch_mlp_forward(const MlpDev& M, const float* x, int64_t n, float* out, 
 }
 void launch_mlp_grad(const MlpDev& M, const float* rec, int64_t nrec, int64_t rows, int sampled, uint32_t k0,
                      uint32_t k1, uint32_t step, float* partial, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(64), 0, st, M, rec, nrec, rows, sampled, k0, k1, step,
-                     partial);
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3(blocks), dim3(64 * kGradWaves), 0, st, M, rec, nrec, rows, sampled, k0, k1,
+                     step, partial);
 }
 void launch_mlp_reduce(const float* partial, int blocks, float* grad, float* loss, hipStream_t st) {
   hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kRedEntries + 63) / 64), dim3(kRedThreads), 0, st, partial, blocks, grad,
