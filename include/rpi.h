@@ -183,7 +183,8 @@ typedef struct {
   double milliseconds;    /* device time of the call (when stats are requested) */
   /* Per kernel: index t = 1..8 start phase of technique t, 16 + t its walk
    * phase, 9 connect, 10 splat (all splat kernels of a chunk), 11 frame,
-   * 12 proposal densities for the MIS sums, 13 technique-8 starts (MLP).
+   * 12 proposal densities for the MIS sums, 13 technique-8 starts (MLP),
+   * 14 the coherent sample-order pass before each start phase.
    * ms/launches with RPI_FLAG_TIME_KERNELS; node/triangle fetches and bytes
    * written with RPI_FLAG_COUNT_WORK. */
   double kernel_ms[32];
