@@ -98,7 +98,8 @@ typedef struct {
   const int32_t* indices;      /* [3 * num_triangles], counter-clockwise around the normal */
   int32_t num_triangles;
   const int32_t* tri_material; /* [num_triangles], < num_materials */
-  const int32_t* tri_object;   /* [num_triangles], 0 static, 1 dynamic/edited object */
+  const int32_t* tri_object;   /* [num_triangles], 0 static, 1 dynamic/edited object (one object:
+                                  values above 1 are UNSUPPORTED, negative ones INVALID_ARG) */
   const float* materials;      /* [8 * num_materials] */
   int32_t num_materials;
   const float* env;            /* [3] constant environment radiance (0 = none) */
@@ -205,8 +206,9 @@ typedef struct {
  * hipMallocAsync, else every device allocation of the scene and of the
  * calls made on it goes through it (learned proposals keep their own).
  * Errors: INVALID_ARG (NaN/inf vertex, index out of range, bad material id
- * or type, zero-area object or emitter, bad camera), UNSUPPORTED (emissive
- * object, object with several materials, no dynamic triangles, no emitter),
+ * or type, negative tri_object, zero-area object or emitter, bad camera),
+ * UNSUPPORTED (emissive object, object with several materials, several
+ * objects (tri_object > 1), no dynamic triangles, no emitter),
  * OUT_OF_MEMORY, DEVICE.  Validation happens before any device work. */
 rpi_status rpi_build_scene(const rpi_scene_desc* desc, const rpi_allocator* allocator, rpi_scene** out);
 rpi_status rpi_destroy_scene(rpi_scene* scene);

@@ -728,6 +728,9 @@ extern "C" rpi_status rpi_build_scene(const rpi_scene_desc* d, const rpi_allocat
     std::memcpy(t.v1, d->positions + 3 * ix[1], 12);
     std::memcpy(t.v2, d->positions + 3 * ix[2], 12);
     t.id = f;
+    if (d->tri_object[f] < 0) return fail(RPI_ERR_INVALID_ARG, "negative tri_object in triangle " + std::to_string(f));
+    if (d->tri_object[f] > 1)  // every dynamic triangle moves with the one pose pair of an edit
+      return fail(RPI_ERR_UNSUPPORTED, "several independently moving objects (tri_object > 1)");
     t.mat = d->tri_material[f];
     if (t.mat < 0 || t.mat >= d->num_materials) return fail(RPI_ERR_INVALID_ARG, "material id out of range");
     const int type = (int)d->materials[8 * t.mat];

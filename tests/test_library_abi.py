@@ -129,6 +129,14 @@ def _mutated(name):
         return _copy(sc, indices=i), INVALID, "zero-area emitter"
     if name == "no_object":
         return _copy(sc, tri_object=np.zeros_like(sc.tri_object)), UNSUPPORTED, "no dynamic triangles"
+    if name == "second_object":
+        o = sc.tri_object.copy()
+        o[obj[:2]] = 2
+        return _copy(sc, tri_object=o), UNSUPPORTED, "several independently moving objects"
+    if name == "negative_object":
+        o = sc.tri_object.copy()
+        o[0] = -1
+        return _copy(sc, tri_object=o), INVALID, "negative tri_object"
     if name == "two_object_materials":
         tm = sc.tri_material.copy()
         tm[obj[0]] = 0 if tm[obj[1]] != 0 else 1
@@ -139,7 +147,7 @@ def _mutated(name):
 @pytest.mark.parametrize("name", ["nan_vertex", "inf_vertex", "index_out_of_range", "negative_index",
                                   "material_id_out_of_range", "bad_material_type", "ggx_zero_roughness", "bad_fov",
                                   "fractional_width", "emissive_object", "zero_area_object", "zero_area_emitter",
-                                  "no_object", "two_object_materials"])
+                                  "no_object", "second_object", "negative_object", "two_object_materials"])
 def test_build_scene_rejects_malformed_scenes(name):
     sc, code, msg = _mutated(name)
     rc, err = _build(sc)
