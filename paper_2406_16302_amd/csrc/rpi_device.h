@@ -303,11 +303,13 @@ DEV bool ray_ok(vec3 o, vec3 d) {
 // One visit of a 4-wide node: test(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, tnear)
 // says whether the ray meets a child's box.  ORDER: the nearest child met is
 // returned and the others go on the lane's stack, the farthest first
-// (deepest), so the next nearest is popped first (closest-hit and any-hit
-// queries find their hit sooner); without ORDER (all-hit queries, which
-// visit every box met anyway) the children are taken in slot order.  With
-// no child met the next entry is popped (kDone once the stack is empty).
-// At most (children - 1) entries are pushed.
+// (deepest), so the next nearest is popped first (closest-hit queries find
+// their hit sooner and cull more); without ORDER the children are taken in
+// slot order: all-hit queries visit every box met anyway, and so does an
+// any-hit query whose segment is clear (any_in; for the blocked ones the
+// sort costs more than it saves).  With no child met the next entry is
+// popped (kDone once the stack is empty).  At most (children - 1) entries
+// are pushed.
 constexpr int kDone = 0x7fffffff;  // no node left (inner node indices stay below it)
 template <bool ORDER = true, class Test>
 DEV int visit4(const float4* __restrict__ N, int node, int* __restrict__ stk, int& sp, Test&& test) {
@@ -365,7 +367,7 @@ DEV int visit4(const float4* __restrict__ N, int node, int* __restrict__ stk, in
 // lanes that found a leaf early do useful node work meanwhile.  A
 // closest-hit query may visit a few nodes that the postponed leaf's hit
 // would have culled; the hit found is the same.  ORDER: nearest child first
-// (false for all-hit queries).
+// (false for any-hit and all-hit queries).
 template <bool CW, bool ORDER = true, class Leaf>
 DEV void bvh_walk(const float4* __restrict__ N, vec3 o, vec3 d, const float& tlim, int* __restrict__ stk,
                      WorkCount& wc, Leaf&& leaf) {
@@ -594,7 +596,7 @@ DEV void closest_line(const DevScene& S, const DevFrame& F, vec3 o, vec3 d, Hit&
 template <bool CW>
 DEV bool any_in(const DevBvh& B, vec3 o, vec3 d, float tmax, int* stk, WorkCount& wc) {
   bool hit = false;
-  bvh_walk<CW>(B.nodes, o, d, tmax, stk, wc, [&](int code) {
+  bvh_walk<CW, false>(B.nodes, o, d, tmax, stk, wc, [&](int code) {
     const int f = leaf_first(code), n = leaf_count(code);
     for (int i = f; i < f + n; ++i) {
       vec3 v0, e1, e2;
