@@ -105,6 +105,49 @@ def test_gradient_matches_oracle(small_scene, n):
         assert rb < 5e-2, (lo, hi, rb)
 
 
+def test_adam_steps_follow_their_definition(small_scene):
+    """Two training steps against Adam (Kingma and Ba 2015) written out in
+    float32 on the host, from the library's own gradient of the same rows:
+    step t draws row r of its batch as record floor(philox(r, t, 0x5eed,
+    0; seed).x * n / 2^32), and the gradient of those rows in that order
+    comes from the same tiles and the same reduction as the training step's."""
+    from paper_2406_16302_amd import native
+    rng = np.random.default_rng(77)
+    n, batch, seed = 5000, 1088, (7 << 32) | 11
+    lr, b1, b2, eps = np.float32(2e-3), np.float32(0.9), np.float32(0.999), np.float32(1e-8)
+    rec = _records(rng, n)
+    d_rec = torch.from_numpy(rec).cuda()
+    x = oracle.mlp_init(12).astype(np.float32)
+    pr = native.Proposal(small_scene, x)
+    m = np.zeros_like(x)
+    v = np.zeros_like(x)
+    grad = torch.zeros(native.PROPOSAL_NPARAM, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    losses = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for t in (1, 2):
+        rows = np.array([(int(oracle.philox([r, t, 0x5EED, 0], [seed & 0xFFFFFFFF, seed >> 32])[0]) * n) >> 32
+                         for r in range(batch)])
+        pr.loss_grad(torch.from_numpy(np.ascontiguousarray(rec[rows])).cuda(), grad, loss)
+        torch.cuda.synchronize()
+        g = grad.cpu().numpy()
+        pr.train(d_rec, n, 1, batch=batch, lr=float(lr), beta1=float(b1), beta2=float(b2), eps=float(eps), seed=seed,
+                 losses=losses)
+        torch.cuda.synchronize()
+        m = b1 * m + (np.float32(1) - b1) * g
+        v = b2 * v + (np.float32(1) - b2) * g * g
+        mh = m / (np.float32(1) - b1 ** t)
+        vh = v / (np.float32(1) - b2 ** t)
+        x = x - lr * mh / (np.sqrt(vh) + eps)
+        w = pr.get_weights()
+        err = np.abs(w - x)
+        print("step %d: loss %.6g vs %.6g, max |dx| %.3g" % (t, float(losses.item()), float(loss.item()), err.max()))
+        assert abs(float(losses.item()) - float(loss.item())) <= 1e-5 * abs(float(loss.item()))
+        # one rounding of g (s / W against s * (1 / W)) and of the update's
+        # arithmetic: a few float32 ulps of the weights
+        assert np.all(err <= 1e-6 * np.abs(x) + 1e-3 * float(lr)), err.max()
+        x = w.copy()
+
+
 def _t8_parity(ws, mask, seed_mlp):
     from gpu_parity import compare_records, gpu_residual, oracle_residual, rel_l2
     P = oracle.mlp_init(seed_mlp)
