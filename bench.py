@@ -357,6 +357,16 @@ def bench_single(name, args):
             native.render_residual(sc, ed, params(0, None, ref_mask), out)
             methods["plain_estimator"] = (mse(out, ref), t_plain)
             spp_used["plain_estimator"] = ws.spp
+            # technique 8 added to techniques 1-3 as one more strategy, the
+            # counts of all four allocated from a pilot
+            madd = ws.mask | 0x80
+            cadd = native.allocate_samples(sc, ed, params(0, None, madd), pilot_spp=max(2, ws.spp // 8))
+            padd = native.Params.make(ws.spp, ws.depth, ws.seed, mask=madd, flags=base, proposal=prop,
+                                      technique_spp=cadd)
+            t_add = device_ms(lambda: native.render_residual(sc, ed, padd, out), reps=3)
+            native.render_residual(sc, ed, padd, out)
+            methods["added_to_1_3_allocated"] = (mse(out, ref), t_add)
+            spp_used["added_to_1_3_allocated"] = cadd
         if not material:
             pnm = native.Params.make(ws.spp, ws.depth, ws.seed, mask=mask, flags=base | native.FLAG_NO_MAPPING)
             t_nm = device_ms(lambda: native.render_residual(sc, ed, pnm, out), reps=2)
